@@ -1,0 +1,164 @@
+/* qtn.h -- C ABI of the MI355X (gfx950) QAOA-MaxCut light-cone tensor-network
+ * library.
+ *
+ * What it computes (Lykov & Alexeev, "Importance of Diagonal Gates in Tensor
+ * Network Simulations"):
+ *   * the MaxCut cost C = 1/2 sum_{(j,k) in E} (1 - Z_j Z_k) and the QAOA state
+ *     |gamma beta> = prod_l U_B(beta_l) U_C(gamma_l) |+>^N with
+ *     U_C(gamma) = exp(-i gamma C), U_B(beta) = exp(-i beta sum_q X_q)
+ *     (Section II, eq. qaoa1; layer 1 first, cost before mixer);
+ *   * E = <gamma beta| C |gamma beta> = sum over edges of (1 - <Z_j Z_k>)/2, each
+ *     edge term from its own light-cone tensor network (Section II);
+ *   * each network is built with the ZZ phase gates as rank-2 diagonal tensors
+ *     that add no index (Section IV.B, eq. example) and contracted by bucket
+ *     elimination (Section III.B, eq. tn);
+ *   * dE/dgamma_l and dE/dbeta_l by a reverse sweep over the same buckets.
+ *
+ * Conventions: all entry points return a qtn_status; on anything but QTN_OK
+ * qtn_last_error() returns a message (thread-local, valid until the next call
+ * on the same thread).  No C++ exception crosses this interface.  Host
+ * pointers are only read during the call (inputs are copied).  Device
+ * pointers (workspace, zz_out) are owned by the caller and must stay valid
+ * until the work queued on `stream` has finished.  `stream` is a hipStream_t
+ * (NULL = the legacy default stream).  Every call is asynchronous on `stream`
+ * except when it writes host outputs, in which case it synchronises `stream`
+ * before returning.  A qtn_net must not be used by two threads at once.
+ */
+#ifndef QTN_H
+#define QTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtn_ctx qtn_ctx;
+typedef struct qtn_net qtn_net;
+
+typedef enum {
+  QTN_OK = 0,
+  QTN_EINVAL = 1,       /* bad argument: graph, depth, angle, pointer, mode */
+  QTN_ENOMEM = 2,       /* workspace smaller than qtn_workspace_size(), or host/device allocation failed */
+  QTN_EDEVICE = 3,      /* a HIP call failed, or a kernel reported an error */
+  QTN_EUNSUPPORTED = 4, /* plan exceeds a kernel limit (width > 30, > 8 inputs per bucket) */
+  QTN_ESTATE = 5        /* call out of order (e.g. contract before qtn_order / qtn_set_params) */
+} qtn_status;
+
+typedef enum { QTN_C64 = 0, QTN_C128 = 1 } qtn_dtype;          /* complex64 (FP32 accumulate) or complex128 */
+typedef enum { QTN_ORDER_MIN_DEGREE = 0, QTN_ORDER_MIN_FILL = 1 } qtn_order_kind;
+typedef enum { QTN_PLAIN = 0, QTN_BATCHED = 1 } qtn_mode;
+/* QTN_PLAIN: host loop over edges, one kernel launch per bucket step.
+ * QTN_BATCHED: every light cone in one persistent launch fed by a device work
+ * queue, captured once as a hipGraph and replayed. */
+
+/* Kernel tile parameters (see qtn_set_tuning / qtn_autotune). */
+typedef struct {
+  int32_t threads;      /* workgroup size: 64, 128, 256 or 512 */
+  int32_t lane_cap;     /* max union bits mapped to the lanes of one sub-block (1..10) */
+  int32_t seq_max_bits; /* buckets with more union bits than this are split across workgroups */
+  int32_t tile_blocks;  /* blocks of a split bucket handled by one queue item */
+  int32_t loop_cap;     /* summed bits looped inside a thread before partial sums go to atomics */
+  int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
+} qtn_tuning;
+
+typedef struct {
+  int32_t n_cones;          /* = number of edges */
+  int32_t p;
+  int32_t max_width;        /* largest bucket output rank over all cones */
+  int32_t dtype;            /* qtn_dtype */
+  int64_t n_buckets;        /* total buckets over all cones */
+  int64_t n_ops_fwd;        /* device ops of the forward program */
+  int64_t n_ops_grad;       /* device ops of the forward + adjoint program */
+  int64_t n_items_fwd, n_items_grad;  /* persistent-queue items */
+  double fwd_bytes;         /* algorithmic bytes of one forward sweep (each input read once, output written once) */
+  double bwd_bytes;         /* algorithmic bytes of the adjoint sweep */
+  double fwd_flops;         /* complex multiply = 6, add = 2 */
+  size_t ws_fwd, ws_grad;   /* workspace bytes: forward only / forward + gradient */
+} qtn_info;
+
+/* Context bound to HIP device `device` (hipSetDevice is called on it).  Owns a
+ * private stream used only for graph capture.  device = QTN_HOST_ONLY gives a
+ * planning-only context: build, order, sizes, statistics and plan validation
+ * work without a GPU; contractions return QTN_ESTATE. */
+#define QTN_HOST_ONLY (-1)
+qtn_status qtn_create(int device, qtn_ctx** out);
+void qtn_destroy(qtn_ctx* ctx);
+const char* qtn_last_error(void);
+
+/* Network for MaxCut on the graph with vertices 0..n_vertices-1 and edge list
+ * edges[2*e], edges[2*e+1] (int32, host).  QAOA depth p >= 1.  One light cone
+ * per edge (Section II).  Rejects ids out of range, self-loops, duplicate edges
+ * (QTN_EINVAL).  No device memory is allocated. */
+qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                     qtn_dtype dtype, qtn_net** out);
+
+/* Greedy elimination order of every light cone (Section III.B: the order fixes
+ * the largest intermediate).  Host work, independent of gamma and beta.
+ * Builds the bucket plan and uploads it (the only device allocation of the
+ * library).  *max_width_out (nullable) receives the contraction width. */
+qtn_status qtn_order(qtn_net* net, qtn_order_kind kind, int32_t* max_width_out);
+
+/* Bytes of device workspace that qtn_contract (with_grad = 0) or
+ * qtn_energy_grad (with_grad = 1) need. */
+qtn_status qtn_workspace_size(const qtn_net* net, int32_t with_grad, size_t* bytes_out);
+
+/* gamma[p], beta[p] (host, float64, finite).  Leaf tensor values are computed
+ * on the host in float64 and cast to the network dtype. */
+qtn_status qtn_set_params(qtn_net* net, const double* gamma, const double* beta);
+
+/* Contract every light cone.  workspace: device, >= qtn_workspace_size(.,0)
+ * bytes, 256-byte aligned.  zz_out (device, nullable): n_edges complex values
+ * <Z_j Z_k> in the network dtype (interleaved re, im).  energy_out (host,
+ * nullable): E in float64; when given the call synchronises `stream`. */
+qtn_status qtn_contract(qtn_net* net, qtn_mode mode, void* workspace, size_t ws_bytes, void* stream, void* zz_out,
+                        double* energy_out);
+
+/* Forward sweep plus the adjoint sweep.  energy_out, dgamma_out[p], dbeta_out[p]
+ * are host float64 (dgamma_out/dbeta_out may be NULL only together); the call
+ * synchronises `stream`.  zz_out as in qtn_contract. */
+qtn_status qtn_energy_grad(qtn_net* net, qtn_mode mode, void* workspace, size_t ws_bytes, void* stream,
+                           void* zz_out, double* energy_out, double* dgamma_out, double* dbeta_out);
+
+/* Per-edge results of the last sweep, host float64: zz[2*e] = Re <Z_j Z_k>,
+ * zz[2*e+1] = Im; dzz (nullable) [n_edges][2p][2]: d<Z_j Z_k>/d(gamma_1..p,
+ * beta_1..p), complex.  Reads the workspace of that sweep; synchronises `stream`. */
+qtn_status qtn_edge_results(qtn_net* net, const void* workspace, void* stream, double* zz, double* dzz);
+
+qtn_status qtn_get_info(const qtn_net* net, qtn_info* out);
+/* Per-cone statistics (host arrays of n_edges, each nullable): contraction
+ * width, qubits in the light cone, tensor indices, leaf tensors, buckets,
+ * algorithmic forward / adjoint bytes. */
+qtn_status qtn_cone_stats(const qtn_net* net, int32_t* width, int32_t* n_qubits, int32_t* n_indices,
+                          int32_t* n_tensors, int32_t* n_buckets, double* fwd_bytes, double* bwd_bytes);
+
+/* Checks the plan's invariants (each index eliminated once, each bucket output
+ * consumed exactly once by a later bucket that holds all its indices, masks
+ * consistent with the union sets, widths, arena ranges disjoint and in bounds).
+ * QTN_OK or QTN_EINVAL with the first violation in qtn_last_error(). */
+qtn_status qtn_validate_plan(const qtn_net* net);
+
+/* Tile parameters; changing them rebuilds and re-uploads the device program. */
+qtn_status qtn_get_tuning(const qtn_net* net, qtn_tuning* out);
+qtn_status qtn_set_tuning(qtn_net* net, const qtn_tuning* t);
+
+/* Project-written autotuner: times the batched sweep (with_grad as given) for
+ * each candidate tile shape on `stream`, keeps the fastest and returns it in
+ * *best (nullable).  Needs qtn_set_params first and a workspace as for the sweep. */
+qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
+                        int32_t reps, qtn_tuning* best);
+
+/* Device time of the batched sweep's graph replay (leaf upload, queue reset,
+ * persistent kernel, final reduction), summed over batched sweeps that wrote
+ * host outputs since the last reset, from HIP events recorded on the launch
+ * stream around the replay; and the number of such sweeps. */
+qtn_status qtn_kernel_time(qtn_net* net, double* ms_sum, int64_t* count, int32_t reset);
+
+void qtn_net_free(qtn_net* net);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTN_H */

@@ -1,0 +1,676 @@
+// C ABI of the library (declared in include/qtn.h).  Host orchestration:
+// plan upload, leaf values, plain per-op launches, the persistent sweep and
+// its hipGraph, result read-back, autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/qtn.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace qtn;
+
+namespace {
+thread_local std::string g_err;
+
+qtn_status fail(qtn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+#define HIPCHECK(call)                                                                              \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return fail(QTN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+// Upper bound on the polls of one dependency wait in the persistent kernel
+// (~1 us each): a plan bug makes the sweep report an error instead of hanging.
+constexpr long long kSpinLimit = 20000000LL;
+}  // namespace
+
+struct qtn_ctx {
+  int device = 0;
+  int n_cu = 256;
+  hipStream_t cap_stream = nullptr;
+};
+
+struct DevProg {
+  QItem* items = nullptr;
+  int32_t* succ = nullptr;
+  int32_t* init = nullptr;
+  int32_t n_items = 0, n_nodes = 0;
+};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  void* zz = nullptr;
+  bool valid = false;
+};
+
+struct qtn_net {
+  qtn_ctx* ctx = nullptr;
+  Plan P;
+  bool c128 = false;
+  int elem = 8;
+  // device plan
+  OpDesc* d_ops = nullptr;
+  LeafRef* d_leafrefs = nullptr;
+  DevProg prog[2];
+  void* d_leafvals = nullptr;  // vals then dvals, element type
+  // host staging (pinned)
+  void* h_leafvals = nullptr;
+  double* h_fin = nullptr;
+  size_t leaf_bytes = 0;
+  bool params_set = false;
+  int grid = 0;
+  GraphCache graph[2];
+  hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
+  bool ev_pending = false;
+  double kernel_ms_sum = 0;
+  int64_t kernel_count = 0;
+  std::vector<double> gamma, beta;
+};
+
+namespace {
+
+// Workspace layout: [res: n_cones*(2+4p) doubles][fin: 1+2p doubles][ctl: 2+n_nodes int32][arena]
+struct WsLayout {
+  size_t res_off, fin_off, ctl_off, arena_off, total;
+};
+
+WsLayout ws_layout(const qtn_net* n, bool grad) {
+  WsLayout L;
+  const size_t nc = n->P.cones.size();
+  const int rs = 2 + 4 * n->P.p;
+  L.res_off = 0;
+  L.fin_off = align256(nc * rs * sizeof(double));
+  L.ctl_off = L.fin_off + align256((1 + 2 * n->P.p) * sizeof(double));
+  const int nn = std::max(n->prog[0].n_nodes, n->prog[1].n_nodes);
+  L.arena_off = L.ctl_off + align256((2 + nn) * sizeof(int32_t));
+  L.total = L.arena_off + align256((size_t)(grad ? n->P.arena_grad : n->P.arena_fwd) * n->elem);
+  return L;
+}
+
+void free_device_plan(qtn_net* n) {
+  (void)hipFree(n->d_ops);
+  (void)hipFree(n->d_leafrefs);
+  for (auto& pg : n->prog) {
+    (void)hipFree(pg.items);
+    (void)hipFree(pg.succ);
+    (void)hipFree(pg.init);
+    pg = DevProg();
+  }
+  n->d_ops = nullptr;
+  n->d_leafrefs = nullptr;
+  for (auto& g : n->graph) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = GraphCache();
+  }
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  size_t bytes = std::max<size_t>(sizeof(T), src.size() * sizeof(T));
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+qtn_status rebuild_programs(qtn_net* n) {
+  std::string err = build_programs(n->P, n->elem);
+  if (!err.empty()) return fail(QTN_EUNSUPPORTED, err);
+  build_items(n->P, false);
+  build_items(n->P, true);
+  if (n->ctx->device < 0) {  // host-only context: plan without upload
+    for (int g = 0; g < 2; ++g)
+      n->prog[g].n_nodes = (int32_t)(g ? n->P.node_init_grad.size() : n->P.node_init_fwd.size());
+    return QTN_OK;
+  }
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  free_device_plan(n);
+  HIPCHECK(upload(&n->d_ops, n->P.ops));
+  HIPCHECK(upload(&n->d_leafrefs, n->P.leafrefs));
+  for (int g = 0; g < 2; ++g) {
+    DevProg& pg = n->prog[g];
+    const auto& items = g ? n->P.items_grad : n->P.items_fwd;
+    const auto& succ = g ? n->P.succ_grad : n->P.succ_fwd;
+    const auto& init = g ? n->P.node_init_grad : n->P.node_init_fwd;
+    HIPCHECK(upload(&pg.items, items));
+    HIPCHECK(upload(&pg.succ, succ));
+    HIPCHECK(upload(&pg.init, init));
+    pg.n_items = (int32_t)items.size();
+    pg.n_nodes = (int32_t)init.size();
+  }
+  return QTN_OK;
+}
+
+Env make_env(qtn_net* n, char* ws, const WsLayout& L) {
+  Env e;
+  e.arena = ws + L.arena_off;
+  e.res = reinterpret_cast<double*>(ws + L.res_off);
+  e.leafvals = n->d_leafvals;
+  e.dleafvals = (char*)n->d_leafvals + n->leaf_bytes / 2;
+  e.leafrefs = n->d_leafrefs;
+  e.p = n->P.p;
+  e.res_stride = 2 + 4 * n->P.p;
+  return e;
+}
+
+// Enqueue one complete sweep on stream st (no host synchronisation).
+qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t st, void* zz_out) {
+  const WsLayout L = ws_layout(n, grad);
+  char* w = static_cast<char*>(ws);
+  Env env = make_env(n, w, L);
+  // kernel launches report through hipGetLastError: drop any error left
+  // behind by unrelated earlier calls on this thread
+  (void)hipGetLastError();
+  HIPCHECK(hipMemcpyAsync(n->d_leafvals, n->h_leafvals, n->leaf_bytes, hipMemcpyHostToDevice, st));
+  const TuneParams& T = n->P.tune;
+  if (mode == QTN_PLAIN) {
+    for (size_t c = 0; c < n->P.cones.size(); ++c) {
+      auto run = [&](int32_t lo, int32_t hi) -> qtn_status {
+        for (int32_t o = lo; o < hi; ++o) {
+          hipError_t e = launch_op(n->c128, n->d_ops, n->P.ops[o], o, env, T.threads, 4096, st);
+          if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("op launch: ") + hipGetErrorString(e));
+        }
+        return QTN_OK;
+      };
+      qtn_status s;
+      if (grad) {
+        if ((s = run(n->P.cone_fwd_lo[c], n->P.cone_fwd_hi[c])) != QTN_OK) return s;
+        if ((s = run(n->P.cone_adj_lo[c], n->P.cone_adj_hi[c])) != QTN_OK) return s;
+      } else {
+        if ((s = run(n->P.cone_fwd_lo[c], n->P.cone_fwd_hi[c] + 1)) != QTN_OK) return s;
+      }
+    }
+  } else {
+    DevProg& pg = n->prog[grad ? 1 : 0];
+    int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
+    HIPCHECK(launch_reset(ctl, pg.init, pg.n_nodes, st));
+    const int grid = std::max(1, std::min<int>(n->grid, std::max(1, pg.n_items)));
+    HIPCHECK(launch_persistent(n->c128, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env, T.threads, grid,
+                               kSpinLimit, st));
+  }
+  HIPCHECK(launch_final(n->c128, env.res, env.res_stride, (int)n->P.cones.size(), n->P.p, grad ? 1 : 0, zz_out,
+                        reinterpret_cast<double*>(w + L.fin_off), st));
+  HIPCHECK(hipMemcpyAsync(n->h_fin, w + L.fin_off, (1 + 2 * n->P.p) * sizeof(double), hipMemcpyDeviceToHost, st));
+  return QTN_OK;
+}
+
+qtn_status check_ready(qtn_net* n, void* ws, size_t ws_bytes, bool grad) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (n->ctx->device < 0) return fail(QTN_ESTATE, "host-only context cannot run contractions");
+  if (!n->P.ordered || !n->d_ops) return fail(QTN_ESTATE, "qtn_order has not been called");
+  if (!n->params_set) return fail(QTN_ESTATE, "qtn_set_params has not been called");
+  const WsLayout L = ws_layout(n, grad);
+  if (!ws && L.total) return fail(QTN_EINVAL, "workspace is NULL");
+  if ((uintptr_t)ws % 256) return fail(QTN_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(QTN_ENOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(L.total));
+  return QTN_OK;
+}
+
+qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes, hipStream_t st, void* zz_out,
+                     bool want_host) {
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  if (mode == QTN_BATCHED) {
+    GraphCache& g = n->graph[grad ? 1 : 0];
+    // the workspace and zz_out pointers are baked into the graph: re-capture
+    // when either changes
+    const bool reuse = g.valid && g.ws == ws && g.zz == zz_out;
+    if (!reuse) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g = GraphCache();
+      hipStream_t cs = n->ctx->cap_stream;
+      HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      qtn_status s = enqueue_sweep(n, mode, grad, ws, cs, zz_out);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(cs, &graph);
+      if (s != QTN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      g.ws = ws;
+      g.zz = zz_out;
+      g.valid = true;
+    }
+    // events on the caller's stream around the replay time the device work
+    // of the whole sweep (events recorded inside a captured graph carry no
+    // timestamps)
+    HIPCHECK(hipEventRecord(n->ev_k0, st));
+    HIPCHECK(hipGraphLaunch(g.exec, st));
+    HIPCHECK(hipEventRecord(n->ev_k1, st));
+    n->ev_pending = true;
+  } else {
+    qtn_status s = enqueue_sweep(n, mode, grad, ws, st, zz_out);
+    if (s != QTN_OK) return s;
+  }
+  HIPCHECK(hipEventRecord(n->ev_done, st));
+  if (want_host) {
+    HIPCHECK(hipEventSynchronize(n->ev_done));
+    if (mode == QTN_BATCHED && n->ev_pending) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, n->ev_k0, n->ev_k1) == hipSuccess) {
+        n->kernel_ms_sum += ms;
+        n->kernel_count += 1;
+      } else {
+        (void)hipGetLastError();
+      }
+      n->ev_pending = false;
+    }
+    // the persistent kernel's error flag
+    if (mode == QTN_BATCHED) {
+      const WsLayout L = ws_layout(n, grad);
+      int32_t flag = 0;
+      HIPCHECK(hipMemcpy(&flag, (char*)ws + L.ctl_off + sizeof(int32_t), sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (flag) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
+    }
+  }
+  return QTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qtn_last_error(void) { return g_err.c_str(); }
+
+qtn_status qtn_create(int device, qtn_ctx** out) {
+  if (!out) return fail(QTN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (device == QTN_HOST_ONLY) {
+    qtn_ctx* c = new (std::nothrow) qtn_ctx();
+    if (!c) return fail(QTN_ENOMEM, "host allocation failed");
+    c->device = QTN_HOST_ONLY;
+    *out = c;
+    return QTN_OK;
+  }
+  int ndev = 0;
+  HIPCHECK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(QTN_EINVAL, "device id out of range");
+  HIPCHECK(hipSetDevice(device));
+  qtn_ctx* c = new (std::nothrow) qtn_ctx();
+  if (!c) return fail(QTN_ENOMEM, "host allocation failed");
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(QTN_EDEVICE, "stream creation failed");
+  }
+  *out = c;
+  return QTN_OK;
+}
+
+void qtn_destroy(qtn_ctx* c) {
+  if (!c) return;
+  if (c->device < 0) {
+    delete c;
+    return;
+  }
+  (void)hipSetDevice(c->device);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                     qtn_dtype dtype, qtn_net** out) {
+  if (!ctx || !out) return fail(QTN_EINVAL, "ctx or out is NULL");
+  *out = nullptr;
+  if (dtype != QTN_C64 && dtype != QTN_C128) return fail(QTN_EINVAL, "unknown dtype");
+  std::string err = validate_graph(n_vertices, n_edges, edges, p);
+  if (!err.empty()) return fail(QTN_EINVAL, err);
+  try {
+    qtn_net* n = new qtn_net();
+    n->ctx = ctx;
+    n->c128 = dtype == QTN_C128;
+    n->elem = n->c128 ? 16 : 8;
+    n->P.n = n_vertices;
+    n->P.p = p;
+    for (int e = 0; e < n_edges; ++e) n->P.edges.push_back({edges[2 * e], edges[2 * e + 1]});
+    build_cones(n->P);
+    n->grid = 8 * ctx->n_cu;
+    *out = n;
+    return QTN_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(QTN_ENOMEM, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(QTN_EINVAL, ex.what());
+  }
+}
+
+qtn_status qtn_order(qtn_net* n, qtn_order_kind kind, int32_t* max_width_out) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (kind != QTN_ORDER_MIN_DEGREE && kind != QTN_ORDER_MIN_FILL) return fail(QTN_EINVAL, "unknown order kind");
+  try {
+    unsigned hw = std::thread::hardware_concurrency();
+    order_cones(n->P, (int)kind, (int)std::max(1u, std::min(hw, 16u)));
+    layout_cones(n->P);
+    if (n->P.max_width > MAXBITS - 1)
+      return fail(QTN_EUNSUPPORTED, "contraction width " + std::to_string(n->P.max_width) + " exceeds 30");
+    qtn_status s = rebuild_programs(n);
+    if (s != QTN_OK) return s;
+    n->leaf_bytes = 2 * (size_t)n_leaf_kinds(n->P.p) * 4 * n->elem;
+    if (n->ctx->device < 0) {
+      if (!n->h_leafvals) n->h_leafvals = std::calloc(1, n->leaf_bytes);
+      if (!n->h_leafvals) return fail(QTN_ENOMEM, "host allocation failed");
+      if (max_width_out) *max_width_out = n->P.max_width;
+      return QTN_OK;
+    }
+    HIPCHECK(hipSetDevice(n->ctx->device));
+    if (!n->d_leafvals) {
+      n->leaf_bytes = 2 * (size_t)n_leaf_kinds(n->P.p) * 4 * n->elem;
+      HIPCHECK(hipMalloc(&n->d_leafvals, n->leaf_bytes));
+      HIPCHECK(hipHostMalloc(&n->h_leafvals, n->leaf_bytes, hipHostMallocDefault));
+      HIPCHECK(hipHostMalloc((void**)&n->h_fin, (1 + 2 * n->P.p) * sizeof(double), hipHostMallocDefault));
+      HIPCHECK(hipEventCreate(&n->ev_k0));
+      HIPCHECK(hipEventCreate(&n->ev_k1));
+      HIPCHECK(hipEventCreateWithFlags(&n->ev_done, hipEventDisableTiming));
+      std::memset(n->h_leafvals, 0, n->leaf_bytes);
+    }
+    if (max_width_out) *max_width_out = n->P.max_width;
+    return QTN_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+qtn_status qtn_workspace_size(const qtn_net* n, int32_t with_grad, size_t* bytes_out) {
+  if (!n || !bytes_out) return fail(QTN_EINVAL, "net or bytes_out is NULL");
+  if (!n->P.ordered) return fail(QTN_ESTATE, "qtn_order has not been called");
+  *bytes_out = ws_layout(n, with_grad != 0).total;
+  return QTN_OK;
+}
+
+qtn_status qtn_set_params(qtn_net* n, const double* gamma, const double* beta) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (!n->h_leafvals) return fail(QTN_ESTATE, "qtn_order has not been called");
+  const int p = n->P.p;
+  if (p > 0 && (!gamma || !beta)) return fail(QTN_EINVAL, "gamma or beta is NULL");
+  for (int l = 0; l < p; ++l)
+    if (!std::isfinite(gamma[l]) || !std::isfinite(beta[l])) return fail(QTN_EINVAL, "non-finite angle");
+  // the previous sweep may still read the staging buffer
+  if (n->ev_done) HIPCHECK(hipEventSynchronize(n->ev_done));
+  if (!n->h_leafvals) return fail(QTN_ESTATE, "qtn_order has not been called");
+  const int nk = n_leaf_kinds(p);
+  std::vector<double> v((size_t)nk * 8, 0.0), dv((size_t)nk * 8, 0.0);  // [kind][entry][re,im]
+  auto put = [&](std::vector<double>& a, int kind, int e, double re, double im) {
+    a[((size_t)kind * 4 + e) * 2] = re;
+    a[((size_t)kind * 4 + e) * 2 + 1] = im;
+  };
+  const double h = std::sqrt(0.5);
+  put(v, LK_PLUS, 0, h, 0);
+  put(v, LK_PLUS, 1, h, 0);
+  put(v, LK_ZOBS, 0, 1, 0);
+  put(v, LK_ZOBS, 1, -1, 0);
+  for (int l = 0; l < p; ++l) {
+    // ZZ phase of exp(-i gamma C) on one edge: 1 if the bits agree, exp(-i gamma) if not
+    const double cg = std::cos(gamma[l]), sg = std::sin(gamma[l]);
+    const double cb = std::cos(beta[l]), sb = std::sin(beta[l]);
+    for (int conj = 0; conj < 2; ++conj) {
+      const double sgn = conj ? -1.0 : 1.0;
+      const int kz = conj ? lk_zzb(l) : lk_zz(l);
+      put(v, kz, 0, 1, 0);
+      put(v, kz, 3, 1, 0);
+      put(v, kz, 1, cg, -sgn * sg);
+      put(v, kz, 2, cg, -sgn * sg);
+      // d/dgamma exp(-i s gamma) = -i s exp(-i s gamma)
+      put(dv, kz, 1, -sg, -sgn * cg);
+      put(dv, kz, 2, -sg, -sgn * cg);
+      // mixer exp(-i beta X) = [[cos, -i sin], [-i sin, cos]] (conjugated on the bra)
+      const int km = conj ? lk_mxb(l) : lk_mx(l);
+      put(v, km, 0, cb, 0);
+      put(v, km, 3, cb, 0);
+      put(v, km, 1, 0, -sgn * sb);
+      put(v, km, 2, 0, -sgn * sb);
+      put(dv, km, 0, -sb, 0);
+      put(dv, km, 3, -sb, 0);
+      put(dv, km, 1, 0, -sgn * cb);
+      put(dv, km, 2, 0, -sgn * cb);
+    }
+  }
+  const size_t half = n->leaf_bytes / 2;
+  if (n->c128) {
+    std::memcpy(n->h_leafvals, v.data(), half);
+    std::memcpy((char*)n->h_leafvals + half, dv.data(), half);
+  } else {
+    float* f = static_cast<float*>(n->h_leafvals);
+    for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+    for (size_t i = 0; i < dv.size(); ++i) f[v.size() + i] = (float)dv[i];
+  }
+  n->gamma.assign(gamma, gamma + p);
+  n->beta.assign(beta, beta + p);
+  n->params_set = true;
+  return QTN_OK;
+}
+
+qtn_status qtn_contract(qtn_net* n, qtn_mode mode, void* ws, size_t ws_bytes, void* stream, void* zz_out,
+                        double* energy_out) {
+  if (mode != QTN_PLAIN && mode != QTN_BATCHED) return fail(QTN_EINVAL, "unknown mode");
+  qtn_status s = check_ready(n, ws, ws_bytes, false);
+  if (s != QTN_OK) return s;
+  s = run_sweep(n, mode, false, ws, ws_bytes, (hipStream_t)stream, zz_out, energy_out != nullptr);
+  if (s != QTN_OK) return s;
+  if (energy_out) *energy_out = n->h_fin[0];
+  return QTN_OK;
+}
+
+qtn_status qtn_energy_grad(qtn_net* n, qtn_mode mode, void* ws, size_t ws_bytes, void* stream, void* zz_out,
+                           double* energy_out, double* dgamma_out, double* dbeta_out) {
+  if (mode != QTN_PLAIN && mode != QTN_BATCHED) return fail(QTN_EINVAL, "unknown mode");
+  if (!energy_out) return fail(QTN_EINVAL, "energy_out is NULL");
+  if ((dgamma_out == nullptr) != (dbeta_out == nullptr)) return fail(QTN_EINVAL, "dgamma_out/dbeta_out mismatch");
+  qtn_status s = check_ready(n, ws, ws_bytes, true);
+  if (s != QTN_OK) return s;
+  s = run_sweep(n, mode, true, ws, ws_bytes, (hipStream_t)stream, zz_out, true);
+  if (s != QTN_OK) return s;
+  const int p = n->P.p;
+  *energy_out = n->h_fin[0];
+  if (dgamma_out)
+    for (int l = 0; l < p; ++l) {
+      dgamma_out[l] = n->h_fin[1 + l];
+      dbeta_out[l] = n->h_fin[1 + p + l];
+    }
+  return QTN_OK;
+}
+
+qtn_status qtn_edge_results(qtn_net* n, const void* ws, void* stream, double* zz, double* dzz) {
+  if (!n || !ws) return fail(QTN_EINVAL, "net or workspace is NULL");
+  if (n->ctx->device < 0) return fail(QTN_ESTATE, "host-only context has no device results");
+  if (!n->P.ordered) return fail(QTN_ESTATE, "qtn_order has not been called");
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  const size_t nc = n->P.cones.size();
+  const int rs = 2 + 4 * n->P.p;
+  std::vector<double> res(nc * rs);
+  if (nc) HIPCHECK(hipMemcpy(res.data(), ws, res.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (size_t c = 0; c < nc; ++c) {
+    if (zz) {
+      zz[2 * c] = res[c * rs];
+      zz[2 * c + 1] = res[c * rs + 1];
+    }
+    if (dzz)
+      for (int t = 0; t < 4 * n->P.p; ++t) dzz[c * 4 * n->P.p + t] = res[c * rs + 2 + t];
+  }
+  return QTN_OK;
+}
+
+qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
+  if (!n || !out) return fail(QTN_EINVAL, "net or out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->n_cones = (int32_t)n->P.cones.size();
+  out->p = n->P.p;
+  out->dtype = n->c128 ? QTN_C128 : QTN_C64;
+  if (!n->P.ordered) return QTN_OK;
+  out->max_width = n->P.max_width;
+  for (size_t c = 0; c < n->P.cones.size(); ++c) {
+    const Cone& C = n->P.cones[c];
+    out->n_buckets += (int64_t)C.buckets.size();
+    out->fwd_bytes += C.fwd_bytes_alg;
+    out->bwd_bytes += C.bwd_bytes_alg;
+    out->fwd_flops += C.fwd_flops;
+    out->n_ops_fwd += n->P.cone_fwd_hi[c] + 1 - n->P.cone_fwd_lo[c];
+    out->n_ops_grad += (n->P.cone_fwd_hi[c] - n->P.cone_fwd_lo[c]) + (n->P.cone_adj_hi[c] - n->P.cone_adj_lo[c]);
+  }
+  out->n_items_fwd = (int64_t)n->P.items_fwd.size();
+  out->n_items_grad = (int64_t)n->P.items_grad.size();
+  out->ws_fwd = ws_layout(n, false).total;
+  out->ws_grad = ws_layout(n, true).total;
+  return QTN_OK;
+}
+
+qtn_status qtn_cone_stats(const qtn_net* n, int32_t* width, int32_t* n_qubits, int32_t* n_indices, int32_t* n_tensors,
+                          int32_t* n_buckets, double* fwd_bytes, double* bwd_bytes) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  for (size_t c = 0; c < n->P.cones.size(); ++c) {
+    const Cone& C = n->P.cones[c];
+    if (width) width[c] = C.width;
+    if (n_qubits) n_qubits[c] = C.n_qubits;
+    if (n_indices) n_indices[c] = C.n_idx;
+    if (n_tensors) n_tensors[c] = (int32_t)C.leaves.size();
+    if (n_buckets) n_buckets[c] = (int32_t)C.buckets.size();
+    if (fwd_bytes) fwd_bytes[c] = C.fwd_bytes_alg;
+    if (bwd_bytes) bwd_bytes[c] = C.bwd_bytes_alg;
+  }
+  return QTN_OK;
+}
+
+qtn_status qtn_get_tuning(const qtn_net* n, qtn_tuning* out) {
+  if (!n || !out) return fail(QTN_EINVAL, "net or out is NULL");
+  out->threads = n->P.tune.threads;
+  out->lane_cap = n->P.tune.lane_cap;
+  out->seq_max_bits = n->P.tune.seq_max_bits;
+  out->tile_blocks = n->P.tune.tile_blocks;
+  out->loop_cap = n->P.tune.loop_cap;
+  out->grid = n->grid;
+  return QTN_OK;
+}
+
+qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
+  if (!n || !t) return fail(QTN_EINVAL, "net or tuning is NULL");
+  const int th = t->threads;
+  if (th != 64 && th != 128 && th != 256 && th != 512) return fail(QTN_EINVAL, "threads must be 64, 128, 256 or 512");
+  if (t->lane_cap < 1 || t->lane_cap > 10) return fail(QTN_EINVAL, "lane_cap must be in 1..10");
+  if (t->seq_max_bits < 1 || t->seq_max_bits > 31) return fail(QTN_EINVAL, "seq_max_bits must be in 1..31");
+  if (t->tile_blocks < 1) return fail(QTN_EINVAL, "tile_blocks must be >= 1");
+  if (t->loop_cap < 0 || t->loop_cap > 31) return fail(QTN_EINVAL, "loop_cap must be in 0..31");
+  if (t->grid < 0) return fail(QTN_EINVAL, "grid must be >= 0");
+  n->P.tune.threads = th;
+  n->P.tune.lane_cap = t->lane_cap;
+  n->P.tune.seq_max_bits = t->seq_max_bits;
+  n->P.tune.tile_blocks = t->tile_blocks;
+  n->P.tune.loop_cap = t->loop_cap;
+  n->grid = t->grid ? t->grid : 8 * n->ctx->n_cu;
+  if (!n->P.ordered) return QTN_OK;
+  return rebuild_programs(n);
+}
+
+qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes, void* stream, int32_t reps,
+                        qtn_tuning* best_out) {
+  qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
+  if (s != QTN_OK) return s;
+  if (reps < 1) reps = 3;
+  hipStream_t st = (hipStream_t)stream;
+  qtn_tuning base;
+  qtn_get_tuning(n, &base);
+  std::vector<qtn_tuning> cand;
+  for (int th : {128, 256, 512})
+    for (int lc : {6, 7, 8})
+      for (int sq : {14, 16, 18})
+        for (int tb : {4, 16}) {
+          if ((1 << lc) > th) continue;
+          qtn_tuning t = base;
+          t.threads = th;
+          t.lane_cap = lc;
+          t.seq_max_bits = sq;
+          t.tile_blocks = tb;
+          t.grid = 0;
+          cand.push_back(t);
+        }
+  double best_ms = 1e300;
+  qtn_tuning best = base;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  for (const qtn_tuning& t : cand) {
+    if ((s = qtn_set_tuning(n, &t)) != QTN_OK) break;
+    if ((s = check_ready(n, ws, ws_bytes, with_grad != 0)) != QTN_OK) break;
+    if ((s = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, true)) != QTN_OK) break;
+    HIPCHECK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r)
+      if ((s = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, false)) != QTN_OK) break;
+    if (s != QTN_OK) break;
+    HIPCHECK(hipEventRecord(e1, st));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != QTN_OK) return s;
+  s = qtn_set_tuning(n, &best);
+  n->kernel_ms_sum = 0;
+  n->kernel_count = 0;
+  if (best_out) *best_out = best;
+  return s;
+}
+
+qtn_status qtn_kernel_time(qtn_net* n, double* ms_sum, int64_t* count, int32_t reset) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (ms_sum) *ms_sum = n->kernel_ms_sum;
+  if (count) *count = n->kernel_count;
+  if (reset) {
+    n->kernel_ms_sum = 0;
+    n->kernel_count = 0;
+  }
+  return QTN_OK;
+}
+
+qtn_status qtn_validate_plan(const qtn_net* n) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (!n->P.ordered) return fail(QTN_ESTATE, "qtn_order has not been called");
+  std::string err = validate_plan(n->P);
+  return err.empty() ? QTN_OK : fail(QTN_EINVAL, err);
+}
+
+void qtn_net_free(qtn_net* n) {
+  if (!n) return;
+  if (n->ctx->device < 0) {
+    std::free(n->h_leafvals);
+    delete n;
+    return;
+  }
+  (void)hipSetDevice(n->ctx->device);
+  if (n->ev_done) (void)hipEventSynchronize(n->ev_done);
+  free_device_plan(n);
+  (void)hipFree(n->d_leafvals);
+  if (n->h_leafvals) (void)hipHostFree(n->h_leafvals);
+  if (n->h_fin) (void)hipHostFree(n->h_fin);
+  if (n->ev_k0) (void)hipEventDestroy(n->ev_k0);
+  if (n->ev_k1) (void)hipEventDestroy(n->ev_k1);
+  if (n->ev_done) (void)hipEventDestroy(n->ev_done);
+  delete n;
+}
+
+}  // extern "C"

@@ -1,0 +1,515 @@
+// HIP kernels for gfx950: bucket-elimination contraction of light-cone
+// tensor networks (Section III.B of the paper: multiply every tensor holding
+// the eliminated index over the union of their indices, then sum that index),
+// its adjoint, the leaf-product tables of the diagonal-gate network
+// (Section IV.B) and the final energy / gradient reductions.
+//
+// Every tensor stores its indices in elimination order, earliest index in the
+// lowest bit, so the eliminated index of a bucket is bit 0 of every input that
+// holds it: each thread loads the (x_v = 0, 1) pair of such an input with one
+// 16-byte load and sums the pair in registers.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace qtn {
+
+// ------------------------------------------------------------------ complex helpers
+template <typename R>
+struct CT;
+template <>
+struct CT<float> {
+  using E = float2;
+};
+template <>
+struct CT<double> {
+  using E = double2;
+};
+
+template <typename E>
+__device__ __forceinline__ E cmul(E a, E b) {
+  E r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename E>
+__device__ __forceinline__ E cadd(E a, E b) {
+  E r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+
+__device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
+  float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void load_pair(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
+}
+__device__ __forceinline__ void store_pair(float2* p, float2 a, float2 b) {
+  *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void store_pair(double2* p, double2 a, double2 b) {
+  p[0] = a;
+  p[1] = b;
+}
+__device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ float2 shfl_xor_c(float2 v, int m) {
+  return make_float2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+__device__ __forceinline__ double2 shfl_xor_c(double2 v, int m) {
+  return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+
+// Element stride of union bit u inside a tensor whose union-bit mask is m.
+__device__ __forceinline__ uint32_t bit_stride(uint32_t m, uint32_t u) {
+  return ((m >> u) & 1u) ? (1u << __popc(m & ((1u << u) - 1u))) : 0u;
+}
+
+// ------------------------------------------------------------------ contraction op
+// Runs the blocks of one OP_CONTRACT assigned to this workgroup: block index
+// blk = blk_begin + (wg_rank + k*wg_count)*nsub + sub for k = 0, 1, ...
+template <typename R, int NIN>
+__device__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                              int64_t blk_end, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk;
+  const int lanes = 1 << nl;
+  const int nsub = blockDim.x >> nl;
+  const int sub = tid >> nl;
+  const int lane = tid & (lanes - 1);
+  if (sub >= nsub) return;  // never: blockDim is a multiple of 2^nl
+  const uint32_t out_mask = d.out_mask;
+  const bool out_pair = out_mask & 1u;
+  const bool atomic = d.flags & F_ATOMIC;
+
+  uint32_t mask[NIN];
+  uint32_t loff[NIN];
+  const E* inp[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    inp[i] = arena + d.in_off[i];
+    uint32_t o = 0;
+    for (int j = 0; j < nl; ++j)
+      if ((lane >> j) & 1) o += bit_stride(mask[i], d.zbit[j]);
+    loff[i] = o;
+  }
+  uint32_t lout = 0;
+  for (int j = 0; j < nl; ++j)
+    if ((lane >> j) & 1) lout += bit_stride(out_mask, d.zbit[j]);
+  E* outp = arena + d.out_off;
+  const uint32_t lane_sum = d.lane_sum;
+  const int zb0 = nl + nk;
+  const int nb = d.nb;
+  const int64_t nloop = int64_t(1) << nk;
+
+  const int64_t step = wg_count * nsub;
+  for (int64_t base = blk_begin + wg_rank * nsub; base < blk_end; base += step) {
+    int64_t blk = base + sub;
+    const bool valid = blk < blk_end;
+    if (!valid) blk = blk_begin;
+    uint32_t boff[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    uint32_t bout = lout;
+    for (int j = 0; j < nb; ++j)
+      if ((blk >> j) & 1) {
+        const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+        bout += bit_stride(out_mask, u);
+      }
+    E acc0 = {0, 0}, acc1 = {0, 0};
+    uint32_t koff[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) koff[i] = 0;
+    uint32_t gray = 0;
+    for (int64_t it = 0; it < nloop; ++it) {
+      if (it) {
+        const int fb = __ffsll((unsigned long long)it) - 1;  // Gray code: one loop bit flips
+        const uint32_t u = d.zbit[nl + fb];
+        gray ^= 1u << fb;
+        const bool up = (gray >> fb) & 1u;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t s = bit_stride(mask[i], u);
+          koff[i] = up ? koff[i] + s : koff[i] - s;
+        }
+      }
+      E p0, p1;
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) {
+        const uint32_t o = boff[i] + koff[i];
+        E a0, a1;
+        if (mask[i] & 1u) {
+          load_pair(inp[i] + o, a0, a1);
+        } else {
+          a0 = inp[i][o];
+          a1 = a0;
+        }
+        if (i == 0) {
+          p0 = a0;
+          p1 = a1;
+        } else {
+          p0 = cmul(p0, a0);
+          p1 = cmul(p1, a1);
+        }
+      }
+      acc0 = cadd(acc0, p0);
+      acc1 = cadd(acc1, p1);
+    }
+    if (lane_sum) {
+      for (int j = 0; j < 6; ++j)
+        if ((lane_sum >> j) & 1) {
+          acc0 = cadd(acc0, shfl_xor_c(acc0, 1 << j));
+          acc1 = cadd(acc1, shfl_xor_c(acc1, 1 << j));
+        }
+    }
+    if (valid && (lane & lane_sum) == 0) {
+      if (out_pair) {
+        if (atomic) {
+          atomic_add_c(outp + bout, acc0);
+          atomic_add_c(outp + bout + 1, acc1);
+        } else {
+          store_pair(outp + bout, acc0, acc1);
+        }
+      } else {
+        const E s = cadd(acc0, acc1);
+        if (atomic)
+          atomic_add_c(outp + bout, s);
+        else
+          outp[bout] = s;
+      }
+    }
+  }
+}
+
+template <typename R>
+__device__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1, int64_t r,
+                                  int64_t c) {
+  switch (d.n_in) {
+    case 1: exec_contract<R, 1>(d, arena, b0, b1, r, c); break;
+    case 2: exec_contract<R, 2>(d, arena, b0, b1, r, c); break;
+    case 3: exec_contract<R, 3>(d, arena, b0, b1, r, c); break;
+    case 4: exec_contract<R, 4>(d, arena, b0, b1, r, c); break;
+    case 5: exec_contract<R, 5>(d, arena, b0, b1, r, c); break;
+    case 6: exec_contract<R, 6>(d, arena, b0, b1, r, c); break;
+    case 7: exec_contract<R, 7>(d, arena, b0, b1, r, c); break;
+    default: exec_contract<R, 8>(d, arena, b0, b1, r, c); break;
+  }
+}
+
+// ------------------------------------------------------------------ leaf tables
+// Leaf-product table of one bucket: entry e = prod over the bucket's leaves of
+// leaf[e restricted to the leaf's indices].
+template <typename R>
+__device__ void exec_leaf(const OpDesc& d, typename CT<R>::E* arena, const Env& env, int64_t wg_rank,
+                          int64_t wg_count) {
+  using E = typename CT<R>::E;
+  const E* vals = reinterpret_cast<const E*>(env.leafvals);
+  const int64_t n = int64_t(1) << d.nbits;
+  E* out = arena + d.out_off;
+  for (int64_t e = wg_rank * blockDim.x + threadIdx.x; e < n; e += wg_count * blockDim.x) {
+    E p = {1, 0};
+    for (int r = 0; r < d.aux1; ++r) {
+      const LeafRef L = env.leafrefs[d.aux0 + r];
+      int idx = (e >> L.pa) & 1;
+      if (L.pb >= 0) idx |= ((e >> L.pb) & 1) << 1;
+      p = cmul(p, vals[L.kind * 4 + idx]);
+    }
+    out[e] = p;
+  }
+}
+
+// Parameter slot of a leaf kind inside a cone's result record: gamma_l at
+// 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+> and Z.
+__device__ __forceinline__ int theta_slot(int kind, int p) {
+  if (kind < 2) return -1;
+  const int l = (kind - 2) >> 2, t = (kind - 2) & 3;
+  return t < 2 ? 2 + 2 * l : 2 + 2 * p + 2 * l;
+}
+
+template <typename R>
+__device__ double2 block_sum(double2 v) {
+  __shared__ double2 red[32];
+  for (int m = 32; m >= 1; m >>= 1) {
+    v.x += __shfl_xor(v.x, m);
+    v.y += __shfl_xor(v.y, m);
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double2 s = make_double2(0, 0);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) {
+      s.x += red[i].x;
+      s.y += red[i].y;
+    }
+  return s;  // valid in thread 0
+}
+
+// dR/dtheta += sum_e Lbar[e] * d(leaf product)/dtheta [e], split per leaf:
+// the derivative of one leaf times the product of the others.
+template <typename R>
+__device__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
+  using E = typename CT<R>::E;
+  const E* vals = reinterpret_cast<const E*>(env.leafvals);
+  const E* dvals = reinterpret_cast<const E*>(env.dleafvals);
+  const int64_t n = int64_t(1) << d.nbits;
+  const E* lbar = arena + d.in_off[0];
+  double* res = env.res + (int64_t)d.cone * env.res_stride;
+  for (int r = 0; r < d.aux1; ++r) {
+    const LeafRef L = env.leafrefs[d.aux0 + r];
+    const int slot = theta_slot(L.kind, env.p);
+    if (slot < 0) continue;  // uniform across the workgroup
+    double2 acc = make_double2(0, 0);
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+      E t = lbar[e];
+      for (int s = 0; s < d.aux1; ++s) {
+        const LeafRef Ls = env.leafrefs[d.aux0 + s];
+        int idx = (e >> Ls.pa) & 1;
+        if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
+        t = cmul(t, s == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
+      }
+      acc.x += (double)t.x;
+      acc.y += (double)t.y;
+    }
+    const double2 s = block_sum<R>(acc);
+    if (threadIdx.x == 0) {
+      atomicAdd(res + slot, s.x);
+      atomicAdd(res + slot + 1, s.y);
+    }
+  }
+}
+
+// Cone value R = product of the scalar outputs; with F_GRAD also the seed
+// dR/dO_s = product of the other scalars, and zeroed gradient accumulators.
+template <typename R>
+__device__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
+  using E = typename CT<R>::E;
+  double* res = env.res + (int64_t)d.cone * env.res_stride;
+  const int ns = d.n_in;
+  if (threadIdx.x == 0) {
+    double2 prod = make_double2(1, 0);
+    for (int s = 0; s < ns; ++s) {
+      const E x = arena[d.in_off[s]];
+      prod = cmul(prod, make_double2(x.x, x.y));
+    }
+    res[0] = prod.x;
+    res[1] = prod.y;
+  }
+  if (d.flags & F_GRAD) {
+    // seed of scalar s: product of the other scalars (thread s; no private arrays)
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      double2 seed = make_double2(1, 0);
+      for (int t = 0; t < ns; ++t)
+        if (t != s) {
+          const E x = arena[d.in_off[t]];
+          seed = cmul(seed, make_double2(x.x, x.y));
+        }
+      E o;
+      o.x = (R)seed.x;
+      o.y = (R)seed.y;
+      arena[d.in_off[ns + s]] = o;
+    }
+    for (int i = threadIdx.x; i < 4 * env.p; i += blockDim.x) res[2 + i] = 0.0;
+  }
+}
+
+template <typename R>
+__device__ void exec_zero(const OpDesc& d, typename CT<R>::E* arena, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  E* out = arena + d.out_off;
+  const int64_t n = d.in_off[0];
+  for (int64_t e = wg_rank * blockDim.x + threadIdx.x; e < n; e += wg_count * blockDim.x) out[e] = E{0, 0};
+}
+
+template <typename R>
+__device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  E* arena = reinterpret_cast<E*>(env.arena);
+  switch (d.kind) {
+    case OP_CONTRACT: exec_contract_any<R>(d, arena, b0, b1, wg_rank, wg_count); break;
+    case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
+    case OP_RESULT:
+      if (wg_rank == 0) exec_result<R>(d, arena, env);
+      break;
+    case OP_ZERO: exec_zero<R>(d, arena, wg_rank, wg_count); break;
+    case OP_LEAFGRAD:
+      if (wg_rank == 0) exec_leafgrad<R>(d, arena, env);
+      break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+// One op per launch (the plain per-edge loop).
+template <typename R>
+__global__ void __launch_bounds__(512) op_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  const OpDesc& d = ops[op];
+  const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
+  exec_op<R>(d, env, 0, nblocks, blockIdx.x, gridDim.x);
+}
+
+// Persistent sweep: workgroups pop items from a device queue in topological
+// order; an item waits until its node counter is zero, runs, then releases
+// its successor nodes.  Every item waits only on items earlier in the queue,
+// which were already taken by running workgroups, so the sweep always drains.
+template <typename R>
+__global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items,
+                                                          int n_items, const int32_t* __restrict__ succ, int32_t* ctl,
+                                                          Env env, long long spin_limit) {
+  __shared__ int s_item;
+  __shared__ int s_abort;
+  int32_t* head = ctl;
+  int32_t* err = ctl + 1;
+  int32_t* node_cnt = ctl + 2;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_item = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_abort = 0;
+    }
+    __syncthreads();
+    const int it = s_item;
+    if (it >= n_items) break;
+    const QItem I = items[it];
+    if (threadIdx.x == 0 && I.node >= 0) {
+      long long spins = 0;
+      while (__hip_atomic_load(node_cnt + I.node, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > spin_limit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_abort = 1;
+          break;
+        }
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          s_abort = 1;
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!s_abort) {
+      for (int op = I.op_lo; op < I.op_hi; ++op) {
+        const OpDesc& d = ops[op];
+        const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
+        const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
+        const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
+        exec_op<R>(d, env, b0, b1, 0, 1);
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0 && I.succ_hi > I.succ_lo) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int s = I.succ_lo; s < I.succ_hi; ++s)
+        __hip_atomic_fetch_add(node_cnt + succ[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+// Resets the queue head, the error flag and the node counters (a kernel, not
+// a memset, so the sweep can be captured in a graph).
+__global__ void reset_ctl_kernel(int32_t* ctl, const int32_t* __restrict__ init, int n_nodes) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes + 2; i += gridDim.x * blockDim.x)
+    ctl[i] = i < 2 ? 0 : init[i - 2];
+}
+
+// E = sum_c (1 - Re R_c)/2, dE/dtheta = -1/2 sum_c Re dR_c/dtheta, and the
+// per-edge <Z_j Z_k> = R_c in the caller's dtype.
+template <typename R>
+__global__ void final_kernel(const double* __restrict__ res, int res_stride, int n_cones, int p, int with_grad,
+                             typename CT<R>::E* zz_out, double* fin) {
+  using E = typename CT<R>::E;
+  const int nv = 1 + (with_grad ? 2 * p : 0);
+  for (int c = threadIdx.x; c < n_cones; c += blockDim.x)
+    if (zz_out) {
+      E z;
+      z.x = (R)res[(int64_t)c * res_stride];
+      z.y = (R)res[(int64_t)c * res_stride + 1];
+      zz_out[c] = z;
+    }
+  for (int v = 0; v < nv; ++v) {
+    double acc = 0;
+    for (int c = threadIdx.x; c < n_cones; c += blockDim.x) {
+      const double* r = res + (int64_t)c * res_stride;
+      acc += v == 0 ? 0.5 * (1.0 - r[0]) : -0.5 * r[2 + 2 * (v - 1)];
+    }
+    const double2 s = block_sum<R>(make_double2(acc, 0));
+    if (threadIdx.x == 0) fin[v] = s.x;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ host launchers
+template <typename R>
+static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads, int max_grid,
+                              hipStream_t st) {
+  int64_t grid = 1;
+  if (h.kind == OP_CONTRACT) {
+    const int64_t nsub = threads >> h.nl;
+    const int64_t nblocks = int64_t(1) << h.nb;
+    grid = (nblocks + nsub - 1) / nsub;
+  } else if (h.kind == OP_LEAF) {
+    grid = ((int64_t(1) << h.nbits) + threads - 1) / threads;
+  } else if (h.kind == OP_ZERO) {
+    grid = (h.in_off[0] + threads - 1) / threads;
+  }
+  if (grid > max_grid) grid = max_grid;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(op_kernel<R>, dim3((unsigned)grid), dim3(threads), 0, st, d_ops, op, env);
+  return hipGetLastError();
+}
+
+hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads,
+                     int max_grid, hipStream_t st) {
+  return c128 ? launch_op_t<double>(d_ops, h, op, env, threads, max_grid, st)
+              : launch_op_t<float>(d_ops, h, op, env, threads, max_grid, st);
+}
+
+hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st) {
+  int grid = (n_nodes + 2 + 255) / 256;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(reset_ctl_kernel, dim3(grid), dim3(256), 0, st, ctl, init, n_nodes);
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent(bool c128, const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
+                             int32_t* ctl, const Env& env, int threads, int grid, long long spin_limit,
+                             hipStream_t st) {
+  if (c128)
+    hipLaunchKernelGGL(persistent_kernel<double>, dim3(grid), dim3(threads), 0, st, ops, items, n_items, succ, ctl,
+                       env, spin_limit);
+  else
+    hipLaunchKernelGGL(persistent_kernel<float>, dim3(grid), dim3(threads), 0, st, ops, items, n_items, succ, ctl,
+                       env, spin_limit);
+  return hipGetLastError();
+}
+
+hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
+                        double* fin, hipStream_t st) {
+  if (c128)
+    hipLaunchKernelGGL(final_kernel<double>, dim3(1), dim3(256), 0, st, res, res_stride, n_cones, p, with_grad,
+                       reinterpret_cast<double2*>(zz_out), fin);
+  else
+    hipLaunchKernelGGL(final_kernel<float>, dim3(1), dim3(256), 0, st, res, res_stride, n_cones, p, with_grad,
+                       reinterpret_cast<float2*>(zz_out), fin);
+  return hipGetLastError();
+}
+
+}  // namespace qtn

@@ -1,0 +1,30 @@
+// Launch interface of the HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "opdesc.hpp"
+
+namespace qtn {
+
+// Pointers every kernel needs.  All device pointers.
+struct Env {
+  void* arena;              // tensor elements (complex64 or complex128)
+  double* res;              // per cone: R (re, im), dR/dgamma_l, dR/dbeta_l (re, im)
+  const void* leafvals;     // [4p+2][4] leaf entries, element type
+  const void* dleafvals;    // [4p+2][4] their derivatives in the leaf's angle
+  const LeafRef* leafrefs;
+  int p;
+  int res_stride;           // 2 + 4p doubles
+};
+
+hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads,
+                     int max_grid, hipStream_t st);
+hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st);
+hipError_t launch_persistent(bool c128, const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
+                             int32_t* ctl, const Env& env, int threads, int grid, long long spin_limit,
+                             hipStream_t st);
+hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
+                        double* fin, hipStream_t st);
+
+}  // namespace qtn

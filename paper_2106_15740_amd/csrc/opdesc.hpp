@@ -1,0 +1,64 @@
+// Plain-old-data records shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace qtn {
+
+constexpr int MAXIN = 8;     // tensor inputs of one contraction op
+constexpr int MAXBITS = 31;  // union bits of one bucket (output rank <= 30)
+
+enum OpKind : int32_t {
+  OP_CONTRACT = 0,  // out[pext(u,out)] (+)= sum over unmasked bits of prod_i in_i[pext(u,mask_i)]
+  OP_LEAF = 1,      // leaf-product table of one bucket
+  OP_RESULT = 2,    // cone value R = prod of scalar outputs; optional adjoint seeds
+  OP_ZERO = 3,      // zero a range of the arena
+  OP_LEAFGRAD = 4,  // dR/dtheta from the adjoint of one leaf-product table
+};
+
+enum OpFlags : int32_t {
+  F_ATOMIC = 1,  // output receives partial sums from several blocks / waves
+  F_GRAD = 2,    // OP_RESULT also writes adjoint seeds
+};
+
+// A contraction op iterates the union index u of a bucket.  Bit 0 of u is the
+// eliminated index and is handled inside each thread as a pair (x_v = 0, 1).
+// The other union bits are listed in zbit[] in iteration order: the first nl
+// are lanes of a sub-block of 2^nl threads, the next nk are a per-thread loop,
+// the last nb enumerate blocks.  Input i reads element pext(u, in_mask[i]) at
+// in_off[i]; the output is written at pext(u, out_mask).
+struct alignas(16) OpDesc {
+  int32_t kind;
+  int32_t n_in;
+  int32_t nbits;      // union bits (contract) / table rank (leaf, leafgrad)
+  int32_t nl, nk, nb;
+  int32_t flags;
+  uint32_t out_mask;
+  uint32_t lane_sum;  // lane z-bits (< 6) that are summed by wavefront shuffles
+  int32_t cone;
+  int32_t aux0, aux1;  // leaf ref range for OP_LEAF / OP_LEAFGRAD
+  int64_t out_off;
+  int64_t in_off[MAXIN];
+  uint32_t in_mask[MAXIN];
+  uint8_t zbit[32];
+};
+
+struct LeafRef {
+  int16_t kind;
+  int8_t pa, pb;  // bit positions inside the leaf-product table (pb < 0: rank 1)
+};
+
+// Persistent-queue work item: ops [op_lo, op_hi) run in sequence by one
+// workgroup over all their blocks (blk_hi < 0), or blocks [blk_lo, blk_hi) of
+// the single op op_lo.  The item may start once node_cnt[node] reaches zero
+// (node < 0: no dependency) and on completion decrements node_cnt[s] for every
+// s in succ[succ_lo, succ_hi).
+struct QItem {
+  int32_t op_lo, op_hi;
+  int32_t blk_lo, blk_hi;
+  int32_t node;
+  int32_t succ_lo, succ_hi;
+  int32_t pad;
+};
+
+}  // namespace qtn

@@ -1,0 +1,791 @@
+// Host planner.  Paper passages followed:
+//   * MaxCut cost and QAOA ansatz: Section II (eq. qaoa1), U_C = exp(-i gamma C).
+//   * light cone of an edge term: Section II (local terms; gates outside the
+//     backward light cone cancel).
+//   * tensors of states and gates, diagonal gates without new indices:
+//     Sections III.A and IV.B (eq. example, the rank-2 ZZ tensor).
+//   * bucket elimination and the role of the order: Section III.B (eq. tn).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <cmath>
+#include <numeric>
+#include <thread>
+#include <set>
+
+namespace qtn {
+
+std::string validate_graph(int32_t n, int32_t m, const int32_t* edges, int32_t p) {
+  if (n < 1) return "n_vertices must be >= 1";
+  if (m < 0) return "n_edges must be >= 0";
+  if (p < 1) return "p must be >= 1";
+  if (p > 16) return "p must be <= 16";
+  if (m > 0 && !edges) return "edges is NULL";
+  std::set<std::pair<int, int>> seen;
+  for (int e = 0; e < m; ++e) {
+    int u = edges[2 * e], v = edges[2 * e + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n) return "edge " + std::to_string(e) + " has a vertex id out of range";
+    if (u == v) return "edge " + std::to_string(e) + " is a self-loop";
+    if (!seen.insert({std::min(u, v), std::max(u, v)}).second)
+      return "edge " + std::to_string(e) + " is a duplicate";
+  }
+  return "";
+}
+
+// ---------------------------------------------------------------- light cones
+// Qubit q at graph distance d(q) <= p from {j,k} keeps its mixers of layers
+// 1..m_q with m_q = p - d(q); the ZZ gate of layer l on (u,w) survives iff
+// min(d_u, d_w) <= p - l.  Each qubit carries ket indices a_{q,0..m_q-1}, bra
+// indices b_{q,0..m_q-1} and one index t_q shared by ket and bra (the identity
+// and the observable between them are diagonal).
+void build_cones(Plan& P) {
+  const int n = P.n, p = P.p;
+  std::vector<std::vector<int>> adj(n);
+  for (auto& e : P.edges) {
+    adj[e.first].push_back(e.second);
+    adj[e.second].push_back(e.first);
+  }
+  for (auto& a : adj) std::sort(a.begin(), a.end());
+  P.cones.assign(P.edges.size(), Cone());
+  std::vector<int> dist(n, -1), local(n, -1);
+  for (size_t ei = 0; ei < P.edges.size(); ++ei) {
+    Cone& C = P.cones[ei];
+    const int j = P.edges[ei].first, k = P.edges[ei].second;
+    C.j = j;
+    C.k = k;
+    std::vector<int> qs = {j, k};
+    dist[j] = dist[k] = 0;
+    for (size_t h = 0; h < qs.size(); ++h) {
+      int u = qs[h];
+      if (dist[u] == p) continue;
+      for (int w : adj[u])
+        if (dist[w] < 0) {
+          dist[w] = dist[u] + 1;
+          qs.push_back(w);
+        }
+    }
+    const int nq = (int)qs.size();
+    C.n_qubits = nq;
+    for (int i = 0; i < nq; ++i) local[qs[i]] = i;
+    // index ids
+    std::vector<int> top(nq), m(nq), a0(nq), b0(nq);
+    int nid = 0;
+    for (int i = 0; i < nq; ++i) {
+      m[i] = p - dist[qs[i]];
+      top[i] = nid++;
+      a0[i] = nid;
+      nid += m[i];
+      b0[i] = nid;
+      nid += m[i];
+    }
+    C.n_idx = nid;
+    auto K = [&](int i, int s) { return s < m[i] ? a0[i] + s : top[i]; };
+    auto B = [&](int i, int s) { return s < m[i] ? b0[i] + s : top[i]; };
+    auto& L = C.leaves;
+    for (int i = 0; i < nq; ++i) {
+      L.push_back({LK_PLUS, K(i, 0), -1});
+      L.push_back({LK_PLUS, B(i, 0), -1});
+      for (int l = 1; l <= m[i]; ++l) {
+        L.push_back({lk_mx(l - 1), K(i, l - 1), K(i, l)});
+        L.push_back({lk_mxb(l - 1), B(i, l - 1), B(i, l)});
+      }
+    }
+    for (int i = 0; i < nq; ++i) {
+      int u = qs[i];
+      for (int w : adj[u]) {
+        if (local[w] < 0 || w <= u) continue;
+        int iw = local[w];
+        int dmin = std::min(dist[u], dist[w]);
+        for (int l = 1; l <= p; ++l) {
+          if (dmin > p - l) continue;
+          L.push_back({lk_zz(l - 1), K(i, l - 1), K(iw, l - 1)});
+          L.push_back({lk_zzb(l - 1), B(i, l - 1), B(iw, l - 1)});
+        }
+      }
+    }
+    L.push_back({LK_ZOBS, top[0], -1});
+    L.push_back({LK_ZOBS, top[1], -1});
+    for (int u : qs) {
+      dist[u] = -1;
+      local[u] = -1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- ordering
+// Greedy elimination on the interaction graph (indices adjacent iff they share
+// a leaf).  min-degree: fewest neighbours; min-fill: fewest new edges among
+// the neighbours.  Ties go to the lowest index id.
+static void order_one(Cone& C, int kind) {
+  const int n = C.n_idx;
+  const int nw = (n + 63) / 64;
+  std::vector<uint64_t> adj((size_t)n * nw, 0);
+  auto row = [&](int v) { return adj.data() + (size_t)v * nw; };
+  auto setb = [&](uint64_t* r, int b) { r[b >> 6] |= 1ull << (b & 63); };
+  for (auto& l : C.leaves)
+    if (l.b >= 0) {
+      setb(row(l.a), l.b);
+      setb(row(l.b), l.a);
+    }
+  std::vector<char> alive(n, 1);
+  std::vector<int64_t> score(n, 0);
+  auto deg = [&](int v) {
+    int d = 0;
+    const uint64_t* r = row(v);
+    for (int w = 0; w < nw; ++w) d += __builtin_popcountll(r[w]);
+    return d;
+  };
+  auto fill = [&](int v) {
+    const uint64_t* r = row(v);
+    int64_t f = 0;
+    for (int w = 0; w < nw; ++w) {
+      uint64_t bits = r[w];
+      while (bits) {
+        int a = (w << 6) + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const uint64_t* ra = row(a);
+        for (int x = 0; x < nw; ++x) {
+          uint64_t miss = r[x] & ~ra[x];
+          if (x == (a >> 6)) miss &= ~(1ull << (a & 63));
+          f += __builtin_popcountll(miss);
+        }
+      }
+    }
+    return f / 2;
+  };
+  for (int v = 0; v < n; ++v) score[v] = kind == 1 ? fill(v) * 1024 + deg(v) : deg(v);
+  C.order.clear();
+  C.order.reserve(n);
+  int width = 0;
+  std::vector<int> nb, touched;
+  std::vector<char> mark(n, 0);
+  for (int step = 0; step < n; ++step) {
+    int best = -1;
+    for (int v = 0; v < n; ++v)
+      if (alive[v] && (best < 0 || score[v] < score[best])) best = v;
+    const int v = best;
+    nb.clear();
+    uint64_t* rv = row(v);
+    for (int w = 0; w < nw; ++w) {
+      uint64_t bits = rv[w];
+      while (bits) {
+        nb.push_back((w << 6) + __builtin_ctzll(bits));
+        bits &= bits - 1;
+      }
+    }
+    width = std::max(width, (int)nb.size());
+    for (int a : nb) {
+      uint64_t* ra = row(a);
+      for (int w = 0; w < nw; ++w) ra[w] |= rv[w];
+      ra[a >> 6] &= ~(1ull << (a & 63));
+      ra[v >> 6] &= ~(1ull << (v & 63));
+    }
+    std::fill(rv, rv + nw, 0);
+    alive[v] = 0;
+    C.order.push_back(v);
+    touched.clear();
+    for (int a : nb)
+      if (!mark[a]) {
+        mark[a] = 1;
+        touched.push_back(a);
+      }
+    if (kind == 1) {
+      const size_t n1 = touched.size();
+      for (size_t t = 0; t < n1; ++t) {
+        const uint64_t* ra = row(touched[t]);
+        for (int w = 0; w < nw; ++w) {
+          uint64_t bits = ra[w];
+          while (bits) {
+            int b = (w << 6) + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            if (!mark[b]) {
+              mark[b] = 1;
+              touched.push_back(b);
+            }
+          }
+        }
+      }
+    }
+    for (int a : touched) {
+      mark[a] = 0;
+      score[a] = kind == 1 ? fill(a) * 1024 + deg(a) : deg(a);
+    }
+  }
+  C.width = width;
+}
+
+// Symbolic bucket elimination (Section III.B): the bucket of v holds every
+// tensor whose earliest-eliminated index is v; its output carries the union of
+// their indices without v and goes to the bucket of its earliest index.
+static void buckets_one(Cone& C) {
+  const int n = C.n_idx;
+  std::vector<int> pos(n);
+  for (int s = 0; s < n; ++s) pos[C.order[s]] = s;
+  C.buckets.assign(n, Bucket());
+  std::vector<std::vector<int>> out_idx(n);
+  for (size_t li = 0; li < C.leaves.size(); ++li) {
+    const Leaf& l = C.leaves[li];
+    int first = l.b < 0 ? l.a : (pos[l.a] < pos[l.b] ? l.a : l.b);
+    C.buckets[pos[first]].leaves.push_back((int)li);
+  }
+  C.scalars.clear();
+  std::vector<std::vector<int>> pending(n);  // producer buckets waiting at each bucket
+  int width = 0;
+  for (int s = 0; s < n; ++s) {
+    Bucket& Bk = C.buckets[s];
+    Bk.v = C.order[s];
+    Bk.in_bkt = pending[s];
+    std::vector<int> uni = {Bk.v};
+    for (int li : Bk.leaves) {
+      uni.push_back(C.leaves[li].a);
+      if (C.leaves[li].b >= 0) uni.push_back(C.leaves[li].b);
+    }
+    for (int pb : Bk.in_bkt)
+      for (int x : out_idx[pb]) uni.push_back(x);
+    std::sort(uni.begin(), uni.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+    uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+    Bk.uni = uni;
+    auto bit_of = [&](int idx) {
+      for (size_t t = 0; t < uni.size(); ++t)
+        if (uni[t] == idx) return (int)t;
+      return -1;
+    };
+    Bk.lam_mask = 0;
+    for (int li : Bk.leaves) {
+      Bk.lam_mask |= 1u << bit_of(C.leaves[li].a);
+      if (C.leaves[li].b >= 0) Bk.lam_mask |= 1u << bit_of(C.leaves[li].b);
+    }
+    Bk.in_mask.clear();
+    for (int pb : Bk.in_bkt) {
+      uint32_t mk = 0;
+      for (int x : out_idx[pb]) mk |= 1u << bit_of(x);
+      Bk.in_mask.push_back(mk);
+    }
+    out_idx[s].assign(uni.begin() + 1, uni.end());
+    width = std::max(width, (int)uni.size() - 1);
+    if (uni.size() == 1) {
+      C.scalars.push_back(s);
+      Bk.consumer = -1;
+    } else {
+      Bk.consumer = pos[uni[1]];
+      pending[Bk.consumer].push_back(s);
+    }
+  }
+  C.width = width;
+}
+
+void order_cones(Plan& P, int order_kind, int n_threads) {
+  const size_t nc = P.cones.size();
+  n_threads = std::max(1, std::min<int>(n_threads, (int)nc));
+  std::vector<std::thread> th;
+  for (int t = 0; t < n_threads; ++t)
+    th.emplace_back([&, t]() {
+      for (size_t c = t; c < nc; c += n_threads) {
+        order_one(P.cones[c], order_kind);
+        buckets_one(P.cones[c]);
+      }
+    });
+  for (auto& x : th) x.join();
+  P.max_width = 0;
+  for (auto& C : P.cones) P.max_width = std::max(P.max_width, C.width);
+  P.order_kind = order_kind;
+  P.ordered = true;
+}
+
+// ---------------------------------------------------------------- arena layout
+static int64_t align_elems(int64_t off, int64_t size) {
+  int64_t a = size >= 64 ? 64 : 2;
+  return (off + a - 1) / a * a;
+}
+
+void layout_cones(Plan& P) {
+  // forward region of every cone first, then every cone's adjoint region, so a
+  // forward-only sweep needs only the first part of the arena.
+  int64_t off = 0;
+  P.cone_base.assign(P.cones.size(), 0);
+  for (size_t c = 0; c < P.cones.size(); ++c) {
+    Cone& C = P.cones[c];
+    const size_t nb = C.buckets.size();
+    C.out_off.assign(nb, -1);
+    C.lam_off.assign(nb, -1);
+    C.adj_off.assign(nb, -1);
+    C.lamadj_off.assign(nb, -1);
+    for (size_t b = 0; b < nb; ++b) {
+      int64_t sz = int64_t(1) << C.buckets[b].out_rank();
+      off = align_elems(off, sz);
+      C.out_off[b] = off;
+      off += std::max<int64_t>(sz, 2);
+      if (C.buckets[b].lam_mask) {
+        int64_t sl = int64_t(1) << C.buckets[b].lam_rank();
+        off = align_elems(off, sl);
+        C.lam_off[b] = off;
+        off += sl;
+      }
+    }
+  }
+  P.arena_fwd = align_elems(off, 64);
+  off = P.arena_fwd;
+  for (size_t c = 0; c < P.cones.size(); ++c) {
+    Cone& C = P.cones[c];
+    for (size_t b = 0; b < C.buckets.size(); ++b) {
+      int64_t sz = int64_t(1) << C.buckets[b].out_rank();
+      off = align_elems(off, sz);
+      C.adj_off[b] = off;
+      off += std::max<int64_t>(sz, 2);
+      if (C.buckets[b].lam_mask) {
+        int64_t sl = int64_t(1) << C.buckets[b].lam_rank();
+        off = align_elems(off, sl);
+        C.lamadj_off[b] = off;
+        off += sl;
+      }
+    }
+  }
+  P.arena_grad = align_elems(off, 64);
+}
+
+// ---------------------------------------------------------------- op programs
+namespace {
+
+struct Ctx {
+  Plan& P;
+  int elem_bytes;
+};
+
+// Split the non-pair union bits of a contraction op into lanes, loop and
+// blocks (see OpDesc).  seq: the op runs inside one workgroup, so no summed
+// bit may become a block bit (no atomics).
+void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T) {
+  std::vector<int> freeb, sumb;
+  for (int u = 1; u < nbits; ++u) ((out_mask >> u) & 1 ? freeb : sumb).push_back(u);
+  int max_lanes = std::min(T.lane_cap, 31 - __builtin_clz((unsigned)std::max(T.threads, 1)));
+  std::vector<int> lanes, loop, blocks;
+  size_t fi = 0, si = 0;
+  while (fi < freeb.size() && (int)lanes.size() < max_lanes) lanes.push_back(freeb[fi++]);
+  d.lane_sum = 0;
+  while (si < sumb.size() && (int)lanes.size() < std::min(6, max_lanes)) {
+    d.lane_sum |= 1u << lanes.size();
+    lanes.push_back(sumb[si++]);
+  }
+  const int loop_cap = seq ? 31 : T.loop_cap;
+  while (si < sumb.size() && (int)loop.size() < loop_cap) loop.push_back(sumb[si++]);
+  while (fi < freeb.size()) blocks.push_back(freeb[fi++]);
+  bool atomic = false;
+  while (si < sumb.size()) {
+    blocks.push_back(sumb[si++]);
+    atomic = true;
+  }
+  d.nl = (int)lanes.size();
+  d.nk = (int)loop.size();
+  d.nb = (int)blocks.size();
+  int z = 0;
+  for (int u : lanes) d.zbit[z++] = (uint8_t)u;
+  for (int u : loop) d.zbit[z++] = (uint8_t)u;
+  for (int u : blocks) d.zbit[z++] = (uint8_t)u;
+  for (; z < 32; ++z) d.zbit[z] = 0;
+  d.flags = atomic ? F_ATOMIC : 0;
+}
+
+OpDesc blank(int kind, int cone) {
+  OpDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.kind = kind;
+  d.cone = cone;
+  return d;
+}
+
+}  // namespace
+
+std::string build_programs(Plan& P, int elem_bytes) {
+  (void)elem_bytes;
+  const TuneParams& T = P.tune;
+  P.ops.clear();
+  P.leafrefs.clear();
+  const size_t nc = P.cones.size();
+  P.cone_fwd_lo.assign(nc, 0);
+  P.cone_fwd_hi.assign(nc, 0);
+  P.cone_adj_lo.assign(nc, 0);
+  P.cone_adj_hi.assign(nc, 0);
+  std::vector<std::vector<int32_t>> zero_ops(nc);
+  for (size_t c = 0; c < nc; ++c) {
+    Cone& C = P.cones[c];
+    const int64_t base = 0;  // offsets are absolute arena offsets
+    (void)base;
+    if (C.width > MAXBITS - 1) return "contraction width " + std::to_string(C.width) + " exceeds 30";
+    if (C.scalars.size() > MAXIN / 2) return "more than 4 disconnected components in one light cone";
+    C.fwd_bytes_alg = C.bwd_bytes_alg = C.fwd_flops = 0;
+    P.cone_fwd_lo[c] = (int32_t)P.ops.size();
+    // leaf-product tables
+    for (size_t b = 0; b < C.buckets.size(); ++b) {
+      const Bucket& Bk = C.buckets[b];
+      if (!Bk.lam_mask) continue;
+      OpDesc d = blank(OP_LEAF, (int)c);
+      d.nbits = Bk.lam_rank();
+      d.out_off = C.lam_off[b];
+      d.aux0 = (int32_t)P.leafrefs.size();
+      for (int li : Bk.leaves) {
+        const Leaf& l = C.leaves[li];
+        auto lbit = [&](int idx) {
+          int u = 0;
+          while (Bk.uni[u] != idx) ++u;
+          return __builtin_popcount(Bk.lam_mask & ((1u << u) - 1));
+        };
+        LeafRef r;
+        r.kind = (int16_t)l.kind;
+        r.pa = (int8_t)lbit(l.a);
+        r.pb = (int8_t)(l.b >= 0 ? lbit(l.b) : -1);
+        P.leafrefs.push_back(r);
+      }
+      d.aux1 = (int32_t)P.leafrefs.size() - d.aux0;
+      P.ops.push_back(d);
+    }
+    // forward buckets
+    for (size_t b = 0; b < C.buckets.size(); ++b) {
+      const Bucket& Bk = C.buckets[b];
+      const int nbits = Bk.nbits();
+      const bool seq = nbits <= T.seq_max_bits;
+      OpDesc d = blank(OP_CONTRACT, (int)c);
+      d.nbits = nbits;
+      int ni = 0;
+      double in_elems = 0;
+      for (size_t t = 0; t < Bk.in_bkt.size(); ++t) {
+        if (ni >= MAXIN) return "bucket with more than 8 inputs";
+        d.in_off[ni] = C.out_off[Bk.in_bkt[t]];
+        d.in_mask[ni] = Bk.in_mask[t];
+        in_elems += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
+        ++ni;
+      }
+      if (Bk.lam_mask) {
+        if (ni >= MAXIN) return "bucket with more than 8 inputs";
+        d.in_off[ni] = C.lam_off[b];
+        d.in_mask[ni] = Bk.lam_mask;
+        ++ni;
+      }
+      d.n_in = ni;
+      d.out_mask = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u) & ~1u;
+      d.out_off = C.out_off[b];
+      partition_bits(d, nbits, d.out_mask, seq, T);
+      P.ops.push_back(d);
+      const double outn = std::ldexp(1.0, nbits - 1);
+      C.fwd_bytes_alg += (in_elems + outn) * elem_bytes;
+      C.fwd_flops += 6.0 * std::max(0, ni - 1) * std::ldexp(1.0, nbits) + 2.0 * outn;
+    }
+    P.cone_fwd_hi[c] = (int32_t)P.ops.size();
+    // result (+ seeds when a gradient is requested; the same op record serves
+    // both programs, F_GRAD is set on the gradient copy)
+    {
+      OpDesc d = blank(OP_RESULT, (int)c);
+      d.n_in = (int)C.scalars.size();
+      for (size_t s = 0; s < C.scalars.size(); ++s) {
+        d.in_off[s] = C.out_off[C.scalars[s]];
+        d.in_off[C.scalars.size() + s] = C.adj_off[C.scalars[s]];
+      }
+      P.ops.push_back(d);
+    }
+    P.cone_adj_lo[c] = (int32_t)P.ops.size();
+    {
+      OpDesc d = P.ops.back();
+      d.flags = F_GRAD;
+      P.ops.push_back(d);
+    }
+    // adjoint sweep, buckets in reverse elimination order
+    const size_t zero_slot = P.ops.size();
+    (void)zero_slot;
+    for (size_t bb = C.buckets.size(); bb-- > 0;) {
+      const Bucket& Bk = C.buckets[bb];
+      const int nbits = Bk.nbits();
+      const bool seq = nbits <= T.seq_max_bits;
+      const uint32_t all = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u);
+      const int nin = (int)Bk.in_bkt.size();
+      const double ob = std::ldexp(1.0, nbits - 1);
+      double stored = 0;
+      for (int t = 0; t < nin; ++t) stored += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
+      C.bwd_bytes_alg += (ob + stored) * elem_bytes;
+      auto add_common = [&](OpDesc& d, int skip_t, bool with_lam) {
+        int ni = 0;
+        d.in_off[ni] = C.adj_off[bb];
+        d.in_mask[ni] = all & ~1u;
+        ++ni;
+        if (with_lam && Bk.lam_mask) {
+          d.in_off[ni] = C.lam_off[bb];
+          d.in_mask[ni] = Bk.lam_mask;
+          ++ni;
+        }
+        for (int t = 0; t < nin; ++t) {
+          if (t == skip_t) continue;
+          d.in_off[ni] = C.out_off[Bk.in_bkt[t]];
+          d.in_mask[ni] = Bk.in_mask[t];
+          ++ni;
+        }
+        d.n_in = ni;
+      };
+      for (int t = 0; t < nin; ++t) {
+        OpDesc d = blank(OP_CONTRACT, (int)c);
+        d.nbits = nbits;
+        add_common(d, t, true);
+        if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
+        d.out_mask = Bk.in_mask[t];
+        d.out_off = C.adj_off[Bk.in_bkt[t]];
+        partition_bits(d, nbits, d.out_mask, seq, T);
+        if (d.flags & F_ATOMIC) zero_ops[c].push_back((int32_t)P.ops.size());
+        P.ops.push_back(d);
+        C.bwd_bytes_alg += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t])) * elem_bytes;
+      }
+      if (Bk.lam_mask) {
+        OpDesc d = blank(OP_CONTRACT, (int)c);
+        d.nbits = nbits;
+        add_common(d, -1, false);
+        if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
+        d.out_mask = Bk.lam_mask;
+        d.out_off = C.lamadj_off[bb];
+        partition_bits(d, nbits, d.out_mask, seq, T);
+        if (d.flags & F_ATOMIC) zero_ops[c].push_back((int32_t)P.ops.size());
+        P.ops.push_back(d);
+        OpDesc g = blank(OP_LEAFGRAD, (int)c);
+        g.nbits = Bk.lam_rank();
+        g.in_off[0] = C.lamadj_off[bb];
+        // the OP_LEAF record of this bucket holds the leaf refs
+        g.aux0 = -1;
+        for (int32_t o = P.cone_fwd_lo[c]; o < P.cone_fwd_hi[c]; ++o)
+          if (P.ops[o].kind == OP_LEAF && P.ops[o].out_off == C.lam_off[bb]) {
+            g.aux0 = P.ops[o].aux0;
+            g.aux1 = P.ops[o].aux1;
+            break;
+          }
+        P.ops.push_back(g);
+      }
+    }
+    P.cone_adj_hi[c] = (int32_t)P.ops.size();
+  }
+  // Zeroing of atomic adjoint outputs: insert right after each cone's result
+  // op.  Rebuild the op list with the zero ops spliced in.
+  bool any_zero = false;
+  for (auto& z : zero_ops) any_zero |= !z.empty();
+  if (any_zero) {
+    std::vector<OpDesc> ops;
+    ops.reserve(P.ops.size() + 64);
+    for (size_t c = 0; c < nc; ++c) {
+      int32_t flo = (int32_t)ops.size();
+      for (int32_t o = P.cone_fwd_lo[c]; o < P.cone_fwd_hi[c]; ++o) ops.push_back(P.ops[o]);
+      int32_t fhi = (int32_t)ops.size();
+      ops.push_back(P.ops[P.cone_fwd_hi[c]]);  // forward result op
+      int32_t alo = (int32_t)ops.size();
+      ops.push_back(P.ops[P.cone_adj_lo[c]]);  // gradient result op
+      for (int32_t zo : zero_ops[c]) {
+        const OpDesc& src = P.ops[zo];
+        OpDesc z = blank(OP_ZERO, (int)c);
+        z.out_off = src.out_off;
+        z.in_off[0] = int64_t(1) << __builtin_popcount(src.out_mask);
+        ops.push_back(z);
+      }
+      for (int32_t o = P.cone_adj_lo[c] + 1; o < P.cone_adj_hi[c]; ++o) ops.push_back(P.ops[o]);
+      int32_t ahi = (int32_t)ops.size();
+      P.cone_fwd_lo[c] = flo;
+      P.cone_fwd_hi[c] = fhi;
+      P.cone_adj_lo[c] = alo;
+      P.cone_adj_hi[c] = ahi;
+    }
+    P.ops.swap(ops);
+  }
+  return "";
+}
+
+std::string validate_plan(const Plan& P) {
+  auto S = [](auto... a) {
+    std::string r;
+    ((r += std::to_string(a), r += ' '), ...);
+    return r;
+  };
+  struct Iv {
+    int64_t lo, hi;
+  };
+  std::vector<Iv> iv;
+  for (size_t c = 0; c < P.cones.size(); ++c) {
+    const Cone& C = P.cones[c];
+    const int n = C.n_idx;
+    if ((int)C.order.size() != n) return "cone " + S(c) + "order length != index count";
+    std::vector<int> pos(n, -1);
+    for (int s = 0; s < n; ++s) {
+      int v = C.order[s];
+      if (v < 0 || v >= n || pos[v] >= 0) return "cone " + S(c) + "order is not a permutation";
+      pos[v] = s;
+    }
+    std::vector<int> leaf_seen(C.leaves.size(), 0), consumed(n, 0);
+    int width = 0;
+    for (int b = 0; b < n; ++b) {
+      const Bucket& B = C.buckets[b];
+      if (B.v != C.order[b] || B.uni.empty() || B.uni[0] != B.v) return "cone " + S(c, b) + "bucket index mismatch";
+      for (size_t t = 1; t < B.uni.size(); ++t)
+        if (pos[B.uni[t]] <= pos[B.uni[t - 1]]) return "cone " + S(c, b) + "union not in elimination order";
+      const uint32_t all = (uint32_t)((uint64_t(1) << B.uni.size()) - 1);
+      uint32_t cover = 1;
+      for (int li : B.leaves) {
+        leaf_seen[li]++;
+        const Leaf& L = C.leaves[li];
+        for (int idx : {L.a, L.b}) {
+          if (idx < 0) continue;
+          auto it = std::find(B.uni.begin(), B.uni.end(), idx);
+          if (it == B.uni.end()) return "cone " + S(c, b) + "leaf index outside the union";
+          if (pos[idx] < b) return "cone " + S(c, b) + "leaf holds an index eliminated earlier";
+          const uint32_t bit = 1u << (it - B.uni.begin());
+          if (!(B.lam_mask & bit)) return "cone " + S(c, b) + "leaf bit missing from the leaf-product mask";
+          cover |= bit;
+        }
+      }
+      for (size_t t = 0; t < B.in_bkt.size(); ++t) {
+        const int pb = B.in_bkt[t];
+        if (pb < 0 || pb >= b) return "cone " + S(c, b) + "producer is not earlier";
+        const Bucket& Pb = C.buckets[pb];
+        if (Pb.consumer != b) return "cone " + S(c, b) + "producer's consumer mismatch";
+        consumed[pb]++;
+        uint32_t mk = 0;
+        for (size_t q = 1; q < Pb.uni.size(); ++q) {
+          auto it = std::find(B.uni.begin(), B.uni.end(), Pb.uni[q]);
+          if (it == B.uni.end()) return "cone " + S(c, b) + "input index outside the union";
+          mk |= 1u << (it - B.uni.begin());
+        }
+        if (mk != B.in_mask[t] || !(mk & 1u)) return "cone " + S(c, b) + "input mask mismatch";
+        cover |= mk;
+      }
+      if (cover != all) return "cone " + S(c, b) + "union larger than its inputs";
+      width = std::max(width, (int)B.uni.size() - 1);
+      if (B.uni.size() == 1 && B.consumer != -1) return "cone " + S(c, b) + "scalar with a consumer";
+    }
+    for (size_t li = 0; li < C.leaves.size(); ++li)
+      if (leaf_seen[li] != 1) return "cone " + S(c, li) + "leaf not absorbed exactly once";
+    for (int b = 0; b < n; ++b)
+      if ((C.buckets[b].consumer >= 0) != (consumed[b] == 1)) return "cone " + S(c, b) + "output not consumed once";
+    if (width != C.width) return "cone " + S(c) + "width mismatch";
+    for (int b = 0; b < n; ++b) {
+      const Bucket& B = C.buckets[b];
+      const int64_t sz = std::max<int64_t>(int64_t(1) << B.out_rank(), 2);
+      iv.push_back({C.out_off[b], C.out_off[b] + sz});
+      iv.push_back({C.adj_off[b], C.adj_off[b] + sz});
+      if (B.lam_mask) {
+        iv.push_back({C.lam_off[b], C.lam_off[b] + (int64_t(1) << B.lam_rank())});
+        iv.push_back({C.lamadj_off[b], C.lamadj_off[b] + (int64_t(1) << B.lam_rank())});
+      }
+    }
+  }
+  std::sort(iv.begin(), iv.end(), [](const Iv& a, const Iv& b) { return a.lo < b.lo; });
+  for (size_t i = 0; i < iv.size(); ++i) {
+    if (iv[i].lo < 0 || iv[i].hi > P.arena_grad) return "arena range out of bounds";
+    if (i && iv[i].lo < iv[i - 1].hi) return "arena ranges overlap";
+  }
+  for (size_t o = 0; o < P.ops.size(); ++o) {
+    const OpDesc& d = P.ops[o];
+    if (d.kind != OP_CONTRACT) continue;
+    if (d.nl + d.nk + d.nb != d.nbits - 1) return "op " + S(o) + "bit partition does not cover the union";
+    uint32_t seen = 0;
+    bool summed_block = false;
+    for (int z = 0; z < d.nbits - 1; ++z) {
+      const uint32_t u = d.zbit[z];
+      if (u < 1 || (int)u >= d.nbits || (seen >> u) & 1) return "op " + S(o) + "bad zbit";
+      seen |= 1u << u;
+      if (z >= d.nl + d.nk && !((d.out_mask >> u) & 1)) summed_block = true;
+    }
+    for (int z = 0; z < 6; ++z)
+      if ((d.lane_sum >> z) & 1)
+        if (z >= d.nl || (d.out_mask >> d.zbit[z]) & 1) return "op " + S(o) + "bad lane reduction bit";
+    if (summed_block != bool(d.flags & F_ATOMIC)) return "op " + S(o) + "atomic flag mismatch";
+    for (int i = 0; i < d.n_in; ++i)
+      if (d.in_off[i] < 0 || d.in_off[i] + (int64_t(1) << __builtin_popcount(d.in_mask[i])) > P.arena_grad)
+        return "op " + S(o) + "input range out of bounds";
+    if (d.out_off < 0 || d.out_off + (int64_t(1) << __builtin_popcount(d.out_mask)) > P.arena_grad)
+      return "op " + S(o) + "output range out of bounds";
+  }
+  return "";
+}
+
+void build_items(Plan& P, bool grad) {
+  const TuneParams& T = P.tune;
+  auto& items = grad ? P.items_grad : P.items_fwd;
+  auto& init = grad ? P.node_init_grad : P.node_init_fwd;
+  auto& succ = grad ? P.succ_grad : P.succ_fwd;
+  items.clear();
+  init.clear();
+  succ.clear();
+  struct Seg {
+    int32_t op_lo, op_hi;
+    bool wide;
+    int64_t nblocks;
+  };
+  struct Key {
+    int level;
+    double cost;
+    int32_t cone, seg;
+  };
+  const size_t nc = P.cones.size();
+  std::vector<std::vector<Seg>> segs(nc);
+  std::vector<double> cost(nc, 0.0);
+  std::vector<Key> keys;
+  for (size_t c = 0; c < nc; ++c) {
+    std::vector<std::pair<int32_t, int32_t>> ranges;
+    if (grad) {
+      ranges.push_back({P.cone_fwd_lo[c], P.cone_fwd_hi[c]});
+      ranges.push_back({P.cone_adj_lo[c], P.cone_adj_hi[c]});
+    } else {
+      ranges.push_back({P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1});
+    }
+    for (auto& r : ranges) {
+      int32_t open = -1;
+      for (int32_t o = r.first; o < r.second; ++o) {
+        const OpDesc& d = P.ops[o];
+        const bool wide = d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits;
+        if (d.kind == OP_CONTRACT) cost[c] += std::ldexp(1.0, d.nbits) * (d.n_in + 1);
+        if (wide) {
+          if (open >= 0) segs[c].push_back({open, o, false, 1});
+          open = -1;
+          segs[c].push_back({o, o + 1, true, int64_t(1) << d.nb});
+        } else if (open < 0) {
+          open = o;
+        }
+      }
+      if (open >= 0) segs[c].push_back({open, r.second, false, 1});
+    }
+  }
+  // node ids: one per segment
+  std::vector<std::vector<int32_t>> node_of(nc);
+  int32_t nn = 0;
+  for (size_t c = 0; c < nc; ++c) {
+    for (size_t s = 0; s < segs[c].size(); ++s) {
+      node_of[c].push_back(nn++);
+      keys.push_back({(int)s, cost[c], (int32_t)c, (int32_t)s});
+    }
+  }
+  init.assign(nn, 0);
+  std::vector<int32_t> nitems_of(nn, 0);
+  auto n_items = [&](const Seg& g) -> int32_t {
+    if (!g.wide) return 1;
+    const int64_t tb = std::max(1, T.tile_blocks);
+    return (int32_t)((g.nblocks + tb - 1) / tb);
+  };
+  for (size_t c = 0; c < nc; ++c)
+    for (size_t s = 1; s < segs[c].size(); ++s) init[node_of[c][s]] = n_items(segs[c][s - 1]);
+  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+    if (a.level != b.level) return a.level < b.level;
+    if (a.cost != b.cost) return a.cost > b.cost;
+    return a.cone < b.cone;
+  });
+  for (const Key& k : keys) {
+    const Seg& g = segs[k.cone][k.seg];
+    const int32_t node = node_of[k.cone][k.seg];
+    const bool has_next = (size_t)k.seg + 1 < segs[k.cone].size();
+    int32_t slo = (int32_t)succ.size(), shi = slo;
+    if (has_next) {
+      succ.push_back(node_of[k.cone][k.seg + 1]);
+      shi = slo + 1;
+    }
+    const int32_t wait_node = k.seg > 0 ? node : -1;
+    if (!g.wide) {
+      items.push_back({g.op_lo, g.op_hi, 0, -1, wait_node, slo, shi, 0});
+    } else {
+      const int64_t tb = std::max(1, T.tile_blocks);
+      for (int64_t b = 0; b < g.nblocks; b += tb)
+        items.push_back({g.op_lo, g.op_hi, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node, slo,
+                         shi, 0});
+    }
+  }
+}
+
+}  // namespace qtn

@@ -1,0 +1,101 @@
+// Host-side planner: graph intake, per-edge light cone, diagonal-gate tensor
+// network, greedy elimination order, bucket plan and the per-cone op program
+// that the HIP kernels execute.  Nothing here touches the GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "opdesc.hpp"
+
+namespace qtn {
+
+// Leaf tensor kinds.  Every leaf has rank 1 or 2 and is one of 4p+2 distinct
+// values: |+> (1,1)/sqrt2, the observable Z = (1,-1), and per layer l the ket
+// ZZ phase tensor, its conjugate (bra), the ket mixer exp(-i beta X) and its
+// conjugate.
+enum LeafKind : int32_t { LK_PLUS = 0, LK_ZOBS = 1 };
+inline int32_t lk_zz(int l) { return 2 + 4 * l + 0; }     // l is 0-based layer
+inline int32_t lk_zzb(int l) { return 2 + 4 * l + 1; }
+inline int32_t lk_mx(int l) { return 2 + 4 * l + 2; }
+inline int32_t lk_mxb(int l) { return 2 + 4 * l + 3; }
+inline int32_t n_leaf_kinds(int p) { return 2 + 4 * p; }
+
+struct Leaf {
+  int32_t kind;
+  int32_t a, b;  // index ids; b = -1 for rank-1 leaves
+};
+
+struct Bucket {
+  int32_t v = -1;                 // eliminated index
+  std::vector<int32_t> uni;       // union, sorted by elimination position (uni[0] == v)
+  std::vector<int32_t> in_bkt;    // producer bucket of each intermediate input
+  std::vector<uint32_t> in_mask;  // its mask over union bits (bit 0 always set)
+  std::vector<int32_t> leaves;    // leaf ids absorbed by this bucket
+  uint32_t lam_mask = 0;          // union bits carried by the leaf product (0: no leaves)
+  int32_t consumer = -1;          // bucket that reads this output (-1: scalar result)
+  int nbits() const { return (int)uni.size(); }
+  int out_rank() const { return (int)uni.size() - 1; }
+  int lam_rank() const { return __builtin_popcount(lam_mask); }
+};
+
+// One edge term <Z_j Z_k>: the light-cone network and its contraction plan.
+struct Cone {
+  int32_t j = 0, k = 0;
+  int32_t n_qubits = 0;
+  int32_t n_idx = 0;
+  std::vector<Leaf> leaves;
+  std::vector<int32_t> order;     // elimination order (index ids)
+  int32_t width = 0;              // largest bucket output rank
+  std::vector<Bucket> buckets;    // in elimination order
+  std::vector<int32_t> scalars;   // buckets whose output has rank 0
+  // arena layout (element offsets relative to the cone's base)
+  std::vector<int64_t> out_off, lam_off, adj_off, lamadj_off;
+  int64_t fwd_elems = 0;          // outputs + leaf tables
+  int64_t total_elems = 0;        // + adjoint buffers
+  double fwd_bytes_alg = 0, bwd_bytes_alg = 0, fwd_flops = 0;
+};
+
+struct TuneParams {
+  int threads = 256;        // workgroup size of every kernel
+  int lane_cap = 8;         // at most this many lane bits per op
+  int seq_max_bits = 16;    // ops with more union bits run as multi-workgroup tiles
+  int tile_blocks = 8;      // blocks of a wide op handled by one queue item
+  int loop_cap = 12;        // summed bits kept inside a thread before spilling to atomics
+};
+
+struct Plan {
+  int32_t n = 0, p = 0;
+  std::vector<std::pair<int32_t, int32_t>> edges;
+  std::vector<Cone> cones;
+  int order_kind = 0;
+  bool ordered = false;
+  TuneParams tune;
+  // device programs
+  std::vector<OpDesc> ops;          // all ops of all cones
+  std::vector<int32_t> cone_fwd_lo, cone_fwd_hi, cone_adj_lo, cone_adj_hi;
+  std::vector<LeafRef> leafrefs;
+  std::vector<int64_t> cone_base;   // element offset of each cone in the arena
+  int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
+  // persistent-queue items (forward-only and forward+gradient programs)
+  std::vector<QItem> items_fwd, items_grad;
+  std::vector<int32_t> node_init_fwd, node_init_grad;   // initial dependency counts
+  std::vector<int32_t> succ_fwd, succ_grad;             // successor node lists (CSR payload)
+  int32_t max_width = 0;
+};
+
+// Returns "" on success, else an error message.
+std::string validate_graph(int32_t n, int32_t m, const int32_t* edges, int32_t p);
+void build_cones(Plan& P);
+// order_kind: 0 = min-degree, 1 = min-fill
+void order_cones(Plan& P, int order_kind, int n_threads);
+void layout_cones(Plan& P);
+std::string build_programs(Plan& P, int elem_bytes);
+// Persistent-queue items for the forward (grad = false) or forward + adjoint
+// program; items are in topological order.
+void build_items(Plan& P, bool grad);
+// Plan invariants; "" if all hold, else the first violation.
+std::string validate_plan(const Plan& P);
+
+}  // namespace qtn

@@ -1,0 +1,189 @@
+"""Thin Python wrapper over the C ABI: one QAOA-MaxCut energy network.
+
+PyTorch supplies device memory (the caller-owned workspace) and the stream;
+every contraction step runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib as L
+
+_DTYPES = {"c64": L.QTN_C64, "c128": L.QTN_C128}
+_ORDERS = {"min_degree": L.QTN_ORDER_MIN_DEGREE, "min_fill": L.QTN_ORDER_MIN_FILL}
+_MODES = {"plain": L.QTN_PLAIN, "batched": L.QTN_BATCHED}
+
+
+class Context:
+    """A device (or host-only planning) context."""
+
+    def __init__(self, device: int = 0):
+        self._lib = L.lib()
+        h = C.c_void_p()
+        L.check(self._lib.qtn_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.qtn_destroy(self.handle)
+            self.handle = None
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+class QaoaNet:
+    """Light-cone tensor networks of every edge term of <gamma beta|C|gamma beta>.
+
+    n, edges: the graph (vertices 0..n-1); p: QAOA depth; dtype "c64" or
+    "c128"; order "min_degree" or "min_fill"; device: HIP device id, or
+    None for a host-only planning network (statistics and plan checks only).
+    """
+
+    def __init__(self, n: int, edges: Sequence[Tuple[int, int]], p: int, dtype: str = "c64",
+                 order: str = "min_fill", device: Optional[int] = 0):
+        self._lib = L.lib()
+        self.ctx = Context(L.QTN_HOST_ONLY) if device is None else default_context(device)
+        self.n, self.p, self.dtype, self.order = int(n), int(p), dtype, order
+        self.edges = [(int(u), int(v)) for u, v in edges]
+        self.device = device
+        e = np.ascontiguousarray(np.array(self.edges, dtype=np.int32).reshape(-1, 2))
+        self._edges_buf = e
+        h = C.c_void_p()
+        L.check(self._lib.qtn_build(self.ctx.handle, self.n, len(self.edges), e.ctypes.data_as(C.c_void_p),
+                                    self.p, _DTYPES[dtype], C.byref(h)))
+        self.handle = h
+        w = C.c_int32()
+        L.check(self._lib.qtn_order(self.handle, _ORDERS[order], C.byref(w)))
+        self.max_width = w.value
+        self._ws = {}
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.qtn_net_free(self.handle)
+            self.handle = None
+
+    # ------------------------------------------------------------------ info
+    def info(self) -> dict:
+        i = L.Info()
+        L.check(self._lib.qtn_get_info(self.handle, C.byref(i)))
+        return i.as_dict()
+
+    def cone_stats(self) -> dict:
+        m = len(self.edges)
+        arrs = {k: np.zeros(m, np.int32) for k in ("width", "n_qubits", "n_indices", "n_tensors", "n_buckets")}
+        arrs.update({k: np.zeros(m, np.float64) for k in ("fwd_bytes", "bwd_bytes")})
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+        L.check(self._lib.qtn_cone_stats(self.handle, *(ptr(arrs[k]) for k in (
+            "width", "n_qubits", "n_indices", "n_tensors", "n_buckets", "fwd_bytes", "bwd_bytes"))))
+        return arrs
+
+    def validate(self) -> None:
+        L.check(self._lib.qtn_validate_plan(self.handle))
+
+    def workspace_size(self, with_grad: bool) -> int:
+        s = C.c_size_t()
+        L.check(self._lib.qtn_workspace_size(self.handle, int(bool(with_grad)), C.byref(s)))
+        return s.value
+
+    def tuning(self) -> dict:
+        t = L.Tuning()
+        L.check(self._lib.qtn_get_tuning(self.handle, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw) -> None:
+        t = L.Tuning()
+        L.check(self._lib.qtn_get_tuning(self.handle, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        L.check(self._lib.qtn_set_tuning(self.handle, C.byref(t)))
+
+    # ------------------------------------------------------------------ device work
+    def _workspace(self, with_grad: bool):
+        import torch
+
+        need = self.workspace_size(with_grad)
+        buf = self._ws.get("buf")
+        if buf is None or buf.numel() < need:
+            self._ws.clear()
+            buf = torch.empty(max(need, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws["buf"] = buf
+        return buf
+
+    def _stream(self):
+        import torch
+
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def set_params(self, gamma, beta) -> None:
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(-1))
+        b = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(-1))
+        if g.size != self.p or b.size != self.p:
+            raise ValueError(f"gamma and beta must have length p={self.p}")
+        L.check(self._lib.qtn_set_params(self.handle, g.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p)))
+
+    def zz_buffer(self):
+        import torch
+
+        dt = torch.complex64 if self.dtype == "c64" else torch.complex128
+        return torch.empty(len(self.edges), dtype=dt, device=f"cuda:{self.device}")
+
+    def energy(self, mode: str = "batched", zz_out=None) -> float:
+        ws = self._workspace(False)
+        e = C.c_double()
+        L.check(self._lib.qtn_contract(self.handle, _MODES[mode], C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       self._stream(), C.c_void_p(zz_out.data_ptr() if zz_out is not None else 0),
+                                       C.byref(e)))
+        return e.value
+
+    def energy_grad(self, mode: str = "batched", zz_out=None) -> Tuple[float, np.ndarray, np.ndarray]:
+        ws = self._workspace(True)
+        e = C.c_double()
+        dg = np.zeros(self.p)
+        db = np.zeros(self.p)
+        L.check(self._lib.qtn_energy_grad(self.handle, _MODES[mode], C.c_void_p(ws.data_ptr()), ws.numel(),
+                                          self._stream(),
+                                          C.c_void_p(zz_out.data_ptr() if zz_out is not None else 0), C.byref(e),
+                                          dg.ctypes.data_as(C.c_void_p), db.ctypes.data_as(C.c_void_p)))
+        return e.value, dg, db
+
+    def edge_results(self, with_grad: bool = False):
+        """Per-edge <Z_j Z_k> (complex128) and, with_grad, d<ZZ>/d(gamma, beta)
+        of shape [n_edges, 2p] from the last sweep."""
+        ws = self._ws.get("buf")
+        if ws is None:
+            raise RuntimeError("no sweep has run")
+        m = len(self.edges)
+        zz = np.zeros(2 * m)
+        dzz = np.zeros(m * 4 * self.p) if with_grad else None
+        L.check(self._lib.qtn_edge_results(self.handle, C.c_void_p(ws.data_ptr()), self._stream(),
+                                           zz.ctypes.data_as(C.c_void_p),
+                                           dzz.ctypes.data_as(C.c_void_p) if with_grad else None))
+        z = zz[0::2] + 1j * zz[1::2]
+        if not with_grad:
+            return z
+        d = dzz.reshape(m, 2 * self.p, 2)
+        return z, d[..., 0] + 1j * d[..., 1]
+
+    def autotune(self, with_grad: bool = True, reps: int = 3) -> dict:
+        ws = self._workspace(with_grad)
+        t = L.Tuning()
+        L.check(self._lib.qtn_autotune(self.handle, int(bool(with_grad)), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       self._stream(), int(reps), C.byref(t)))
+        return t.as_dict()
+
+    def kernel_time(self, reset: bool = False) -> Tuple[float, int]:
+        ms = C.c_double()
+        cnt = C.c_int64()
+        L.check(self._lib.qtn_kernel_time(self.handle, C.byref(ms), C.byref(cnt), int(bool(reset))))
+        return ms.value, cnt.value

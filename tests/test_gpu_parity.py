@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: complex128 energies within 1e-10 relative and per-edge <ZZ>
+within 1e-10 absolute (|<ZZ>| <= 1 and may be ~0, so absolute); complex64 (FP32
+accumulate) within 1e-5 relative / absolute.  Gradients: against the oracle's
+exact adjoint-state gradient 1e-9 (c128) / 1e-4 (c64); against central
+differences with h = 1e-4 within 1e-6 (truncation ~h^2 E'''/6).
+"""
+import numpy as np
+import pytest
+
+from oracle import ball, statevector as sv, tn
+from workloads import bfs_subgraph, random_regular_graph, triangle_counts, workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def make(n, edges, p, dtype, order, g, b, **tune):
+    from paper_2106_15740_amd import QaoaNet
+
+    print(f"[case] n={n} m={len(edges)} p={p} {dtype} {order} {tune}", flush=True)
+    net = QaoaNet(n, edges, p, dtype=dtype, order=order, device=0)
+    if tune:
+        net.set_tuning(**tune)
+    net.set_params(g, b)
+    return net
+
+
+MODES = ["plain", "batched"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_c128_vs_statevector(mode):
+    w = workload("p1_n10")
+    net = make(w.n, w.edges, w.p, "c128", "min_degree", w.gamma, w.beta)
+    zz_dev = net.zz_buffer()
+    e = net.energy(mode, zz_out=zz_dev)
+    zz_ref = sv.zz_expectations(w.n, w.edges, w.gamma, w.beta)
+    e_ref = sv.energy(w.n, w.edges, w.gamma, w.beta)
+    assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
+    np.testing.assert_allclose(zz_dev.cpu().numpy(), zz_ref, atol=1e-10)
+    np.testing.assert_allclose(net.edge_results(), zz_ref, atol=1e-10)
+    e2, dg, db = net.energy_grad(mode)
+    _, dg_ref, db_ref = sv.energy_grad_adjoint(w.n, w.edges, w.gamma, w.beta)
+    assert abs(e2 - e_ref) <= 1e-10 * abs(e_ref)
+    np.testing.assert_allclose(dg, dg_ref, atol=1e-9)
+    np.testing.assert_allclose(db, db_ref, atol=1e-9)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config2_c64_vs_ball_statevector(mode):
+    w = workload("p2_n60")
+    net = make(w.n, w.edges, w.p, "c64", "min_fill", w.gamma, w.beta)
+    e = net.energy(mode)
+    zz = net.edge_results()
+    ref = np.array([ball.zz_edge(w.n, w.edges, w.gamma, w.beta, j, k) for j, k in w.edges])
+    np.testing.assert_allclose(zz, ref, atol=1e-5)
+    e_ref = float(np.sum(0.5 * (1 - ref.real)))
+    assert abs(e - e_ref) <= 1e-5 * abs(e_ref)
+    assert np.max(np.abs(zz.imag)) < 1e-5
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_small_graphs_energy_and_gradient(mode, dtype):
+    """Regular, irregular, triangle-rich and tiny graphs, p = 1..3, against the
+    full state vector (N <= 12) and its adjoint-state gradient."""
+    k4 = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    cases = [(4, k4, 2), (2, [(0, 1)], 3), (12, random_regular_graph(12, 3, 3), 3),
+             (9, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (0, 5), (5, 6), (6, 7), (2, 8), (8, 1)], 2),
+             (7, [(0, 1), (2, 3)], 2)]
+    tol_e, tol_g = (1e-10, 1e-9) if dtype == "c128" else (1e-5, 1e-4)
+    for n, edges, p in cases:
+        rng = np.random.default_rng(n * 10 + p)
+        g, b = rng.uniform(0, np.pi, p), rng.uniform(0, np.pi, p)
+        for order in ("min_degree", "min_fill"):
+            net = make(n, edges, p, dtype, order, g, b)
+            e, dg, db = net.energy_grad(mode)
+            e_ref, dg_ref, db_ref = sv.energy_grad_adjoint(n, edges, g, b)
+            assert abs(e - e_ref) <= tol_e * max(1.0, abs(e_ref)), (n, p, order)
+            np.testing.assert_allclose(dg, dg_ref, atol=tol_g * max(1.0, np.abs(dg_ref).max()))
+            np.testing.assert_allclose(db, db_ref, atol=tol_g * max(1.0, np.abs(db_ref).max()))
+            zz = net.edge_results()
+            np.testing.assert_allclose(zz, sv.zz_expectations(n, edges, g, b), atol=tol_e)
+
+
+def test_special_values_and_empty_graph():
+    from paper_2106_15740_amd import QaoaNet
+
+    w = workload("p2_n60")
+    net = make(w.n, w.edges, w.p, "c64", "min_fill", [0.0, 0.0], w.beta)
+    for mode in MODES:
+        assert abs(net.energy(mode) - len(w.edges) / 2) < 1e-5 * len(w.edges)
+    net = QaoaNet(6, [], 2, dtype="c64", device=0)
+    net.set_params([0.3, 0.2], [0.1, 0.4])
+    for mode in MODES:
+        e, dg, db = net.energy_grad(mode)
+        assert e == 0.0 and np.all(dg == 0) and np.all(db == 0)
+
+
+@pytest.mark.parametrize("order", ["min_fill", "min_degree"])
+def test_config3_p3_n244_batched_vs_tn_oracle(order):
+    w = workload("p3_n244")
+    net = make(w.n, w.edges, w.p, "c64", order, w.gamma, w.beta)
+    e_b, dg_b, db_b = net.energy_grad("batched")
+    zz = net.edge_results()
+    ref = np.array([tn.zz_edge(w.n, w.edges, w.gamma, w.beta, j, k) for j, k in w.edges])
+    np.testing.assert_allclose(zz, ref, atol=1e-5)
+    e_ref = float(np.sum(0.5 * (1 - ref.real)))
+    assert abs(e_b - e_ref) <= 1e-5 * e_ref
+    e_p, dg_p, db_p = net.energy_grad("plain")
+    assert abs(e_p - e_b) <= 1e-5 * e_ref
+    np.testing.assert_allclose(dg_p, dg_b, rtol=1e-4, atol=1e-3)
+    np.testing.assert_allclose(db_p, db_b, rtol=1e-4, atol=1e-3)
+
+
+def test_config3_tree_like_edges_share_one_value():
+    w = workload("p3_n244")
+    net = make(w.n, w.edges, w.p, "c128", "min_fill", w.gamma, w.beta)
+    net.energy("batched")
+    zz = net.edge_results()
+    st = net.cone_stats()
+    tree = st["n_qubits"] == 30
+    assert tree.sum() > 10
+    assert np.ptp(zz[tree].real) < 1e-12
+    ref = tn.zz_edge(w.n, w.edges, w.gamma, w.beta, *w.edges[int(np.argmax(tree))])
+    assert abs(zz[tree][0] - ref) < 1e-10
+
+
+def test_config4_gradient_subgraph_statevector():
+    """p = 4 gradient on the N=16 BFS subgraph of the N=100 graph against the
+    state-vector adjoint gradient, c64 and c128."""
+    w = workload("p4_n100")
+    n, edges = bfs_subgraph(w.n, w.edges, 16)
+    e_ref, dg_ref, db_ref = sv.energy_grad_adjoint(n, edges, w.gamma, w.beta)
+    for dtype, tol in (("c128", 1e-9), ("c64", 1e-4)):
+        for mode in MODES:
+            net = make(n, edges, w.p, dtype, "min_fill", w.gamma, w.beta)
+            e, dg, db = net.energy_grad(mode)
+            assert abs(e - e_ref) <= (1e-10 if dtype == "c128" else 1e-5) * abs(e_ref)
+            np.testing.assert_allclose(dg, dg_ref, atol=tol * max(1, np.abs(dg_ref).max()))
+            np.testing.assert_allclose(db, db_ref, atol=tol * max(1, np.abs(db_ref).max()))
+
+
+def test_config4_gradient_vs_finite_differences():
+    """p = 4, N = 100: c64 adjoint gradient against central differences of the
+    c128 energy (h = 1e-4) computed through the library."""
+    w = workload("p4_n100")
+    net64 = make(w.n, w.edges, w.p, "c64", "min_fill", w.gamma, w.beta)
+    e, dg, db = net64.energy_grad("batched")
+    net128 = make(w.n, w.edges, w.p, "c128", "min_fill", w.gamma, w.beta)
+
+    def f(g, b):
+        net128.set_params(g, b)
+        return net128.energy("batched")
+
+    e128 = f(w.gamma, w.beta)
+    assert abs(e - e128) <= 1e-5 * abs(e128)
+    fg, fb = sv.energy_grad_fd(f, w.gamma, w.beta, h=1e-4)
+    net128.set_params(w.gamma, w.beta)
+    _, dg128, db128 = net128.energy_grad("batched")
+    np.testing.assert_allclose(dg128, fg, atol=1e-6 * max(1, np.abs(fg).max()) + 2e-6)
+    np.testing.assert_allclose(db128, fb, atol=1e-6 * max(1, np.abs(fb).max()) + 2e-6)
+    np.testing.assert_allclose(dg, dg128, atol=1e-4 * max(1, np.abs(dg128).max()))
+    np.testing.assert_allclose(db, db128, atol=1e-4 * max(1, np.abs(db128).max()))
+
+
+def test_config4_sampled_edges_vs_tn_oracle():
+    w = workload("p4_n100")
+    net = make(w.n, w.edges, w.p, "c128", "min_fill", w.gamma, w.beta)
+    net.energy("batched")
+    zz = net.edge_results()
+    for e in (0, 77):
+        ref = tn.zz_edge(w.n, w.edges, w.gamma, w.beta, *w.edges[e])
+        assert abs(zz[e] - ref) < 1e-10
+
+
+def test_autograd_function():
+    from paper_2106_15740_amd import qaoa_energy
+
+    w = workload("p1_n10")
+    net = make(w.n, w.edges, 2, "c128", "min_degree", [0.4, 0.2], [0.3, 0.1])
+    g = torch.tensor([0.4, 0.2], dtype=torch.float64, requires_grad=True)
+    b = torch.tensor([0.3, 0.1], dtype=torch.float64, requires_grad=True)
+    e = qaoa_energy(g, b, net)
+    (2.0 * e).backward()
+    e_ref, dg_ref, db_ref = sv.energy_grad_adjoint(w.n, w.edges, [0.4, 0.2], [0.3, 0.1])
+    assert abs(e.item() - e_ref) < 1e-10 * e_ref
+    np.testing.assert_allclose(g.grad.numpy(), 2 * dg_ref, atol=1e-9)
+    np.testing.assert_allclose(b.grad.numpy(), 2 * db_ref, atol=1e-9)
+
+
+def test_graph_replay_and_param_refresh():
+    """The batched sweep is a captured hipGraph: replays with new angles and
+    with the program's own work in between must all match the oracle."""
+    w = workload("p2_n60")
+    net = make(w.n, w.edges, w.p, "c64", "min_fill", w.gamma, w.beta)
+    rng = np.random.default_rng(5)
+    for it in range(4):
+        g, b = rng.uniform(0, np.pi, 2), rng.uniform(0, np.pi, 2)
+        net.set_params(g, b)
+        e = net.energy_grad("batched")[0]
+        x = torch.randn(1 << 16, device="cuda").sum().item()  # unrelated eager work between replays
+        ref = sum(0.5 * (1 - ball.zz_edge(w.n, w.edges, g, b, j, k).real) for j, k in w.edges[:: 9])
+        zz = net.edge_results()[:: 9]
+        assert abs(sum(0.5 * (1 - zz.real)) - ref) < 1e-4, (it, x)
+        assert np.isfinite(e)
+
+
+def test_forced_split_buckets_and_atomics():
+    """Force every bucket wider than 4 union bits through the multi-workgroup
+    tile items, with partial sums spilled to atomics."""
+    w = workload("p3_n244")
+    edges = w.edges[:40]
+    n = w.n
+    ref = np.array([tn.zz_edge(n, edges, w.gamma, w.beta, j, k) for j, k in edges])
+    for tune in (dict(seq_max_bits=4, loop_cap=1, tile_blocks=2), dict(seq_max_bits=6, loop_cap=0, lane_cap=3)):
+        net = make(n, edges, w.p, "c128", "min_fill", w.gamma, w.beta, **tune)
+        for mode in MODES:
+            e, dg, db = net.energy_grad(mode)
+            np.testing.assert_allclose(net.edge_results(), ref, atol=1e-10)
+            if mode == "plain":
+                dgp, dbp = dg, db
+        np.testing.assert_allclose(dg, dgp, atol=1e-10)
+        np.testing.assert_allclose(db, dbp, atol=1e-10)

@@ -1,0 +1,131 @@
+"""Host-side tests of the C-ABI library (no GPU): symbol exports, the planner's
+light cones, networks and orders, plan invariants, and error handling."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ball
+from paper_2106_15740_amd import QaoaNet, QtnError
+from paper_2106_15740_amd import _lib as L
+from workloads import random_regular_graph, workload
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qtn.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = sorted(set(re.findall(r"\b(qtn_[a-z_]+)\s*\(", text)))
+    lib = L.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(L.EXPORTS)
+
+
+def tree_counts(p):
+    """Closed-form sizes of a tree-like light cone of a 3-regular graph: n_d =
+    2*2^d qubits at distance d; each carries 2(p-d)+1 indices; |+> twice, two
+    mixers per kept layer, ZZ pairs on the edge itself (p layers) and on each
+    tree edge from distance d to d+1 (p-d layers), and two observable vectors."""
+    nd = [2 * 2 ** d for d in range(p + 1)]
+    qubits = sum(nd)
+    idx = sum(n * (2 * (p - d) + 1) for d, n in enumerate(nd))
+    zz = p + sum(nd[d + 1] * (p - d) for d in range(p))
+    tensors = 2 * qubits + 2 * sum(n * (p - d) for d, n in enumerate(nd)) + 2 * zz + 2
+    return qubits, idx, tensors
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_tree_like_cone_sizes(p):
+    n = 244
+    edges = random_regular_graph(n, 3, 0)
+    net = QaoaNet(n, edges, p, order="min_fill", device=None)
+    st = net.cone_stats()
+    q, i, t = tree_counts(p)
+    tree = st["n_qubits"] == q
+    assert tree.sum() > 0
+    assert np.all(st["n_indices"][tree] == i)
+    assert np.all(st["n_tensors"][tree] == t)
+    assert np.all(st["n_buckets"] == st["n_indices"])
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_cone_qubits_match_oracle_ball(p):
+    n = 60
+    edges = random_regular_graph(n, 3, 1)
+    net = QaoaNet(n, edges, p, device=None)
+    st = net.cone_stats()
+    for e in range(0, len(edges), 7):
+        assert st["n_qubits"][e] == ball.ball_size(n, edges, p, *edges[e])
+
+
+@pytest.mark.parametrize("name,order", [("p1_n10", "min_degree"), ("p2_n60", "min_fill"), ("p3_n244", "min_fill"),
+                                        ("p3_n244", "min_degree"), ("p4_n100", "min_fill")])
+def test_plan_invariants(name, order):
+    w = workload(name)
+    net = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=order, device=None)
+    net.validate()
+    info = net.info()
+    st = net.cone_stats()
+    assert info["n_cones"] == len(w.edges)
+    assert info["max_width"] == st["width"].max()
+    assert info["n_buckets"] == st["n_buckets"].sum()
+    assert info["ws_grad"] > info["ws_fwd"] > 0
+    assert info["n_items_fwd"] >= len(w.edges)
+
+
+def test_widths_of_the_workloads():
+    """Contraction widths of the diagonal network (the quantity the paper's cost
+    model 2^C is built on): small at p <= 3, as expected for light cones."""
+    w = workload("p2_n60")
+    net = QaoaNet(w.n, w.edges, w.p, order="min_fill", device=None)
+    assert 3 <= net.max_width <= 8
+    w = workload("p3_n244")
+    net = QaoaNet(w.n, w.edges, w.p, order="min_fill", device=None)
+    assert 6 <= net.max_width <= 14
+
+
+def test_tuning_roundtrip_and_validation():
+    w = workload("p2_n60")
+    net = QaoaNet(w.n, w.edges, w.p, device=None)
+    net.set_tuning(threads=128, lane_cap=6, seq_max_bits=12, tile_blocks=4, loop_cap=8)
+    t = net.tuning()
+    assert (t["threads"], t["lane_cap"], t["seq_max_bits"], t["tile_blocks"], t["loop_cap"]) == (128, 6, 12, 4, 8)
+    net.validate()
+    with pytest.raises(QtnError) as ei:
+        net.set_tuning(threads=100)
+    assert ei.value.status == L.QTN_EINVAL
+
+
+@pytest.mark.parametrize("edges,n,p", [([(0, 0)], 2, 1), ([(0, 1), (1, 0)], 2, 1), ([(0, 5)], 3, 1),
+                                       ([(0, 1)], 2, 0), ([(-1, 1)], 2, 1)])
+def test_invalid_graphs_rejected(edges, n, p):
+    with pytest.raises(QtnError) as ei:
+        QaoaNet(n, edges, p, device=None)
+    assert ei.value.status == L.QTN_EINVAL
+
+
+def test_host_only_context_refuses_contraction_and_bad_angles():
+    net = QaoaNet(4, [(0, 1), (1, 2)], 1, device=None)
+    with pytest.raises(QtnError) as ei:
+        net.set_params([float("nan")], [0.1])
+    assert ei.value.status == L.QTN_EINVAL
+    with pytest.raises(ValueError):
+        net.set_params([0.1, 0.2], [0.1])
+    net.set_params([0.1], [0.2])
+    lib = L.lib()
+    e = C.c_double()
+    st = lib.qtn_contract(net.handle, L.QTN_BATCHED, None, 0, None, None, C.byref(e))
+    assert st == L.QTN_ESTATE
+
+
+def test_empty_and_degenerate_graphs_plan():
+    net = QaoaNet(5, [], 2, device=None)
+    assert net.info()["n_cones"] == 0
+    net.validate()
+    net = QaoaNet(2, [(0, 1)], 3, device=None)
+    net.validate()
+    st = net.cone_stats()
+    assert st["n_qubits"][0] == 2
