@@ -100,6 +100,16 @@ qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const in
  * library).  *max_width_out (nullable) receives the contraction width. */
 qtn_status qtn_order(qtn_net* net, qtn_order_kind kind, int32_t* max_width_out);
 
+/* Randomized greedy order (the paper's order finder, Section V, is a
+ * randomized greedy run n_repeats times at a temperature): besides the
+ * deterministic greedy run, n_repeats runs pick the next index among all
+ * candidates with probability proportional to exp(-(score - min score) /
+ * temperature) (score: degree or fill-in), seeded by `seed` and the cone
+ * index; the run with the least work (sum over buckets of 2^|union|) is kept
+ * per cone.  n_repeats = 0 is qtn_order.  Same effects as qtn_order. */
+qtn_status qtn_order_rgreedy(qtn_net* net, qtn_order_kind kind, int32_t n_repeats, double temperature,
+                             uint64_t seed, int32_t* max_width_out);
+
 /* Bytes of device workspace that qtn_contract (with_grad = 0) or
  * qtn_energy_grad (with_grad = 1) need. */
 qtn_status qtn_workspace_size(const qtn_net* net, int32_t with_grad, size_t* bytes_out);

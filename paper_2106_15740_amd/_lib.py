@@ -17,7 +17,8 @@ STATUS_NAMES = {0: "QTN_OK", 1: "QTN_EINVAL", 2: "QTN_ENOMEM", 3: "QTN_EDEVICE",
                 5: "QTN_ESTATE"}
 
 EXPORTS = [
-    "qtn_create", "qtn_destroy", "qtn_last_error", "qtn_build", "qtn_order", "qtn_workspace_size",
+    "qtn_create", "qtn_destroy", "qtn_last_error", "qtn_build", "qtn_order", "qtn_order_rgreedy",
+    "qtn_workspace_size",
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_net_free",
@@ -68,6 +69,7 @@ def lib() -> C.CDLL:
         "qtn_last_error": (C.c_char_p, []),
         "qtn_build": (I32, [P, I32, I32, P, I32, I32, C.POINTER(P)]),
         "qtn_order": (I32, [P, I32, C.POINTER(I32)]),
+        "qtn_order_rgreedy": (I32, [P, I32, I32, D, C.c_uint64, C.POINTER(I32)]),
         "qtn_workspace_size": (I32, [P, I32, C.POINTER(SZ)]),
         "qtn_set_params": (I32, [P, P, P]),
         "qtn_contract": (I32, [P, I32, P, SZ, P, P, P]),

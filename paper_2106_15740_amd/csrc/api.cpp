@@ -357,11 +357,23 @@ qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const in
 }
 
 qtn_status qtn_order(qtn_net* n, qtn_order_kind kind, int32_t* max_width_out) {
+  return qtn_order_rgreedy(n, kind, 0, 0.0, 0, max_width_out);
+}
+
+qtn_status qtn_order_rgreedy(qtn_net* n, qtn_order_kind kind, int32_t n_repeats, double temperature, uint64_t seed,
+                             int32_t* max_width_out) {
   if (!n) return fail(QTN_EINVAL, "net is NULL");
   if (kind != QTN_ORDER_MIN_DEGREE && kind != QTN_ORDER_MIN_FILL) return fail(QTN_EINVAL, "unknown order kind");
+  if (n_repeats < 0 || !(temperature >= 0.0) || !std::isfinite(temperature))
+    return fail(QTN_EINVAL, "n_repeats must be >= 0 and temperature finite and >= 0");
   try {
     unsigned hw = std::thread::hardware_concurrency();
-    order_cones(n->P, (int)kind, (int)std::max(1u, std::min(hw, 16u)));
+    OrderOptions O;
+    O.kind = (int)kind;
+    O.repeats = n_repeats;
+    O.temperature = temperature;
+    O.seed = seed;
+    order_cones(n->P, O, (int)std::max(1u, std::min(hw, 16u)));
     layout_cones(n->P);
     if (n->P.max_width > MAXBITS - 1)
       return fail(QTN_EUNSUPPORTED, "contraction width " + std::to_string(n->P.max_width) + " exceeds 30");

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstring>
 #include <cmath>
+#include <climits>
 #include <numeric>
 #include <thread>
 #include <set>
@@ -116,8 +117,28 @@ void build_cones(Plan& P) {
 // ---------------------------------------------------------------- ordering
 // Greedy elimination on the interaction graph (indices adjacent iff they share
 // a leaf).  min-degree: fewest neighbours; min-fill: fewest new edges among
-// the neighbours.  Ties go to the lowest index id.
-static void order_one(Cone& C, int kind) {
+// the neighbours.  Deterministic runs break ties by the smaller degree, then
+// the lowest index id.  Randomized runs (the paper's order finder is a
+// randomized greedy with repeats and a temperature, Section V) pick among the
+// candidates with weights exp(-(score - min score) / temperature), and the
+// cheapest of all runs is kept.  Cost of an order: sum over buckets of
+// 2^|union| (the work of the contraction).
+namespace {
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct OrderRun {
+  std::vector<int> order;
+  int width = 0;
+  double cost = 0;
+};
+
+OrderRun order_run(const Cone& C, int kind, bool randomized, double temperature, uint64_t seed) {
   const int n = C.n_idx;
   const int nw = (n + 63) / 64;
   std::vector<uint64_t> adj((size_t)n * nw, 0);
@@ -129,8 +150,8 @@ static void order_one(Cone& C, int kind) {
       setb(row(l.b), l.a);
     }
   std::vector<char> alive(n, 1);
-  std::vector<int64_t> score(n, 0);
-  auto deg = [&](int v) {
+  std::vector<int64_t> prim(n, 0), deg(n, 0);
+  auto degree = [&](int v) {
     int d = 0;
     const uint64_t* r = row(v);
     for (int w = 0; w < nw; ++w) d += __builtin_popcountll(r[w]);
@@ -154,17 +175,49 @@ static void order_one(Cone& C, int kind) {
     }
     return f / 2;
   };
-  for (int v = 0; v < n; ++v) score[v] = kind == 1 ? fill(v) * 1024 + deg(v) : deg(v);
-  C.order.clear();
-  C.order.reserve(n);
-  int width = 0;
-  std::vector<int> nb, touched;
+  auto rescore = [&](int v) {
+    deg[v] = degree(v);
+    prim[v] = kind == 1 ? fill(v) : deg[v];
+  };
+  for (int v = 0; v < n; ++v) rescore(v);
+  OrderRun R;
+  R.order.reserve(n);
+  std::vector<int> nb, touched, cand;
+  std::vector<double> wts;
   std::vector<char> mark(n, 0);
+  uint64_t rng = seed;
   for (int step = 0; step < n; ++step) {
-    int best = -1;
-    for (int v = 0; v < n; ++v)
-      if (alive[v] && (best < 0 || score[v] < score[best])) best = v;
-    const int v = best;
+    int v = -1;
+    if (!randomized) {
+      for (int x = 0; x < n; ++x)
+        if (alive[x] && (v < 0 || prim[x] < prim[v] || (prim[x] == prim[v] && deg[x] < deg[v]))) v = x;
+    } else {
+      int64_t mn = INT64_MAX;
+      for (int x = 0; x < n; ++x)
+        if (alive[x]) mn = std::min(mn, prim[x]);
+      cand.clear();
+      wts.clear();
+      double tot = 0;
+      const double T = std::max(temperature, 1e-12);
+      for (int x = 0; x < n; ++x) {
+        if (!alive[x]) continue;
+        const double d = (double)(prim[x] - mn) / T;
+        if (d > 30.0) continue;
+        const double wgt = std::exp(-d);
+        cand.push_back(x);
+        wts.push_back(wgt);
+        tot += wgt;
+      }
+      double r = (double)(splitmix64(rng) >> 11) * (1.0 / 9007199254740992.0) * tot;
+      v = cand.back();
+      for (size_t i = 0; i < cand.size(); ++i) {
+        r -= wts[i];
+        if (r <= 0) {
+          v = cand[i];
+          break;
+        }
+      }
+    }
     nb.clear();
     uint64_t* rv = row(v);
     for (int w = 0; w < nw; ++w) {
@@ -174,7 +227,8 @@ static void order_one(Cone& C, int kind) {
         bits &= bits - 1;
       }
     }
-    width = std::max(width, (int)nb.size());
+    R.width = std::max(R.width, (int)nb.size());
+    R.cost += std::ldexp(1.0, (int)nb.size() + 1);
     for (int a : nb) {
       uint64_t* ra = row(a);
       for (int w = 0; w < nw; ++w) ra[w] |= rv[w];
@@ -183,7 +237,7 @@ static void order_one(Cone& C, int kind) {
     }
     std::fill(rv, rv + nw, 0);
     alive[v] = 0;
-    C.order.push_back(v);
+    R.order.push_back(v);
     touched.clear();
     for (int a : nb)
       if (!mark[a]) {
@@ -209,11 +263,24 @@ static void order_one(Cone& C, int kind) {
     }
     for (int a : touched) {
       mark[a] = 0;
-      score[a] = kind == 1 ? fill(a) * 1024 + deg(a) : deg(a);
+      rescore(a);
     }
   }
-  C.width = width;
+  return R;
 }
+
+void order_one(Cone& C, const OrderOptions& O, uint64_t cone_seed) {
+  OrderRun best = order_run(C, O.kind, false, 0.0, 0);
+  uint64_t s = O.seed ^ (cone_seed * 0xD1B54A32D192ED03ull);
+  for (int r = 0; r < O.repeats; ++r) {
+    OrderRun R = order_run(C, O.kind, true, O.temperature, splitmix64(s));
+    if (R.cost < best.cost || (R.cost == best.cost && R.width < best.width)) best = std::move(R);
+  }
+  C.order = std::move(best.order);
+  C.width = best.width;
+}
+
+}  // namespace
 
 // Symbolic bucket elimination (Section III.B): the bucket of v holds every
 // tensor whose earliest-eliminated index is v; its output carries the union of
@@ -275,21 +342,21 @@ static void buckets_one(Cone& C) {
   C.width = width;
 }
 
-void order_cones(Plan& P, int order_kind, int n_threads) {
+void order_cones(Plan& P, const OrderOptions& O, int n_threads) {
   const size_t nc = P.cones.size();
   n_threads = std::max(1, std::min<int>(n_threads, (int)nc));
   std::vector<std::thread> th;
   for (int t = 0; t < n_threads; ++t)
     th.emplace_back([&, t]() {
       for (size_t c = t; c < nc; c += n_threads) {
-        order_one(P.cones[c], order_kind);
+        order_one(P.cones[c], O, (uint64_t)c + 1);
         buckets_one(P.cones[c]);
       }
     });
   for (auto& x : th) x.join();
   P.max_width = 0;
   for (auto& C : P.cones) P.max_width = std::max(P.max_width, C.width);
-  P.order_kind = order_kind;
+  P.order_kind = O.kind;
   P.ordered = true;
 }
 

@@ -88,8 +88,13 @@ struct Plan {
 // Returns "" on success, else an error message.
 std::string validate_graph(int32_t n, int32_t m, const int32_t* edges, int32_t p);
 void build_cones(Plan& P);
-// order_kind: 0 = min-degree, 1 = min-fill
-void order_cones(Plan& P, int order_kind, int n_threads);
+struct OrderOptions {
+  int kind = 0;              // 0 = min-degree, 1 = min-fill
+  int repeats = 0;           // randomized runs on top of the deterministic one
+  double temperature = 0.0;  // Boltzmann temperature of the randomized choice
+  uint64_t seed = 0;
+};
+void order_cones(Plan& P, const OrderOptions& O, int n_threads);
 void layout_cones(Plan& P);
 std::string build_programs(Plan& P, int elem_bytes);
 // Persistent-queue items for the forward (grad = false) or forward + adjoint

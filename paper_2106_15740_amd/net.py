@@ -46,12 +46,15 @@ class QaoaNet:
     """Light-cone tensor networks of every edge term of <gamma beta|C|gamma beta>.
 
     n, edges: the graph (vertices 0..n-1); p: QAOA depth; dtype "c64" or
-    "c128"; order "min_degree" or "min_fill"; device: HIP device id, or
-    None for a host-only planning network (statistics and plan checks only).
+    "c128"; order "min_degree" or "min_fill", deterministic, or with
+    repeats > 0 the randomized greedy (repeats, temperature, seed) keeping the
+    cheapest order per cone; device: HIP device id, or None for a host-only
+    planning network (statistics and plan checks only).
     """
 
     def __init__(self, n: int, edges: Sequence[Tuple[int, int]], p: int, dtype: str = "c64",
-                 order: str = "min_fill", device: Optional[int] = 0):
+                 order: str = "min_fill", device: Optional[int] = 0, repeats: int = 0,
+                 temperature: float = 0.02, seed: int = 0):
         self._lib = L.lib()
         self.ctx = Context(L.QTN_HOST_ONLY) if device is None else default_context(device)
         self.n, self.p, self.dtype, self.order = int(n), int(p), dtype, order
@@ -64,7 +67,11 @@ class QaoaNet:
                                     self.p, _DTYPES[dtype], C.byref(h)))
         self.handle = h
         w = C.c_int32()
-        L.check(self._lib.qtn_order(self.handle, _ORDERS[order], C.byref(w)))
+        if repeats > 0:
+            L.check(self._lib.qtn_order_rgreedy(self.handle, _ORDERS[order], int(repeats), float(temperature),
+                                                int(seed), C.byref(w)))
+        else:
+            L.check(self._lib.qtn_order(self.handle, _ORDERS[order], C.byref(w)))
         self.max_width = w.value
         self._ws = {}
 
