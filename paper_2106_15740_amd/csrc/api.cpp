@@ -75,6 +75,7 @@ struct qtn_net {
   size_t leaf_bytes = 0;
   bool params_set = false;
   int grid = 0;
+  int max_nin = 1;
   GraphCache graph[2];
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
   bool ev_pending = false;
@@ -134,6 +135,9 @@ qtn_status rebuild_programs(qtn_net* n) {
   if (!err.empty()) return fail(QTN_EUNSUPPORTED, err);
   build_items(n->P, false);
   build_items(n->P, true);
+  n->max_nin = 1;
+  for (const OpDesc& d : n->P.ops)
+    if (d.kind == OP_CONTRACT) n->max_nin = std::max(n->max_nin, (int)d.n_in);
   if (n->ctx->device < 0) {  // host-only context: plan without upload
     for (int g = 0; g < 2; ++g)
       n->prog[g].n_nodes = (int32_t)(g ? n->P.node_init_grad.size() : n->P.node_init_fwd.size());
@@ -201,7 +205,7 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
     int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
     HIPCHECK(launch_reset(ctl, pg.init, pg.n_nodes, st));
     const int grid = std::max(1, std::min<int>(n->grid, std::max(1, pg.n_items)));
-    HIPCHECK(launch_persistent(n->c128, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env, T.threads, grid,
+    HIPCHECK(launch_persistent(n->c128, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env, T.threads, grid,
                                kSpinLimit, st));
   }
   HIPCHECK(launch_final(n->c128, env.res, env.res_stride, (int)n->P.cones.size(), n->P.p, grad ? 1 : 0, zz_out,

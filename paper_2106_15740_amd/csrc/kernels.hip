@@ -78,22 +78,44 @@ __device__ __forceinline__ uint32_t bit_stride(uint32_t m, uint32_t u) {
 }
 
 // ------------------------------------------------------------------ contraction op
-// Runs the blocks of one OP_CONTRACT assigned to this workgroup: block index
-// blk = blk_begin + (wg_rank + k*wg_count)*nsub + sub for k = 0, 1, ...
+// Runs the blocks [blk_begin, blk_end) of one OP_CONTRACT that fall to this
+// workgroup.  A workgroup step covers nsub consecutive blocks (one per
+// sub-block); the steps are cut into aligned power-of-two chunks, chunk
+// wg_rank, wg_rank + wg_count, ... go to this workgroup, and each chunk is
+// walked in Gray-code order so that consecutive steps differ in one block bit
+// and every input offset moves by a single stride.  All threads take part in
+// every step (tails are masked), so the LDS reduction may synchronise.
+
+// Outputs per thread (2^nu) allowed for NIN inputs; the planner applies the
+// same bound.
 template <typename R, int NIN>
-__device__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
-                              int64_t blk_end, int64_t wg_rank, int64_t wg_count) {
+struct MaxU {
+  static constexpr int value = (sizeof(R) == 4 && NIN <= 2) ? 2 : 1;
+};
+
+template <typename E>
+struct RedBuf {
+  E v[512 * 2];
+};
+
+template <typename R, int NIN>
+__device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                              int64_t blk_end, int64_t wg_rank, int64_t wg_count,
+                              RedBuf<typename CT<R>::E>* __restrict__ red) {
   using E = typename CT<R>::E;
+  constexpr int MAXU = MaxU<R, NIN>::value;
   const int tid = threadIdx.x;
-  const int nl = d.nl, nk = d.nk;
+  const int nl = d.nl, nu = d.nu, nk = d.nk;
   const int lanes = 1 << nl;
-  const int nsub = blockDim.x >> nl;
+  const int sbits = 31 - __clz(blockDim.x >> nl);  // log2(nsub)
+  const int nsub = 1 << sbits;
   const int sub = tid >> nl;
   const int lane = tid & (lanes - 1);
-  if (sub >= nsub) return;  // never: blockDim is a multiple of 2^nl
   const uint32_t out_mask = d.out_mask;
   const bool out_pair = out_mask & 1u;
   const bool atomic = d.flags & F_ATOMIC;
+  const bool ldsred = d.flags & F_LDSRED;
+  const int U = 1 << nu;
 
   uint32_t mask[NIN];
   uint32_t loff[NIN];
@@ -110,105 +132,171 @@ __device__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ a
   uint32_t lout = 0;
   for (int j = 0; j < nl; ++j)
     if ((lane >> j) & 1) lout += bit_stride(out_mask, d.zbit[j]);
+  uint32_t us0[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) us0[i] = (MAXU > 1 && nu > 0) ? bit_stride(mask[i], d.zbit[nl]) : 0u;
+  const uint32_t uo0 = (MAXU > 1 && nu > 0) ? bit_stride(out_mask, d.zbit[nl]) : 0u;
   E* outp = arena + d.out_off;
   const uint32_t lane_sum = d.lane_sum;
-  const int zb0 = nl + nk;
+  const int zk0 = nl + nu;
+  const int zb0 = nl + nu + nk;
   const int nb = d.nb;
   const int64_t nloop = int64_t(1) << nk;
 
-  const int64_t step = wg_count * nsub;
-  for (int64_t base = blk_begin + wg_rank * nsub; base < blk_end; base += step) {
-    int64_t blk = base + sub;
-    const bool valid = blk < blk_end;
-    if (!valid) blk = blk_begin;
+  // workgroup steps and chunks (all powers of two)
+  const int64_t nblk = blk_end - blk_begin;
+  const int64_t steps = (nblk + nsub - 1) >> sbits;
+  int64_t chunk = steps / wg_count;
+  chunk = chunk < 1 ? 1 : (int64_t(1) << (63 - __clzll((unsigned long long)chunk)));
+  const int64_t nchunks = (steps + chunk - 1) / chunk;
+
+#pragma unroll 1
+  for (int64_t ch = wg_rank; ch < nchunks; ch += wg_count) {
+    const int64_t q0 = ch * chunk;
+    int64_t blk = blk_begin + (q0 << sbits) + sub;
+    bool valid = blk < blk_end;
     uint32_t boff[NIN];
 #pragma unroll
     for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
     uint32_t bout = lout;
-    for (int j = 0; j < nb; ++j)
-      if ((blk >> j) & 1) {
-        const uint32_t u = d.zbit[zb0 + j];
+    {
+      const int64_t b = valid ? blk : blk_begin;
+      for (int j = 0; j < nb; ++j)
+        if ((b >> j) & 1) {
+          const uint32_t u = d.zbit[zb0 + j];
 #pragma unroll
-        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
-        bout += bit_stride(out_mask, u);
-      }
-    E acc0 = {0, 0}, acc1 = {0, 0};
-    uint32_t koff[NIN];
-#pragma unroll
-    for (int i = 0; i < NIN; ++i) koff[i] = 0;
-    uint32_t gray = 0;
-    for (int64_t it = 0; it < nloop; ++it) {
-      if (it) {
-        const int fb = __ffsll((unsigned long long)it) - 1;  // Gray code: one loop bit flips
-        const uint32_t u = d.zbit[nl + fb];
-        gray ^= 1u << fb;
-        const bool up = (gray >> fb) & 1u;
+          for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+          bout += bit_stride(out_mask, u);
+        }
+    }
+#pragma unroll 1
+    for (int64_t c = 0; c < chunk; ++c) {
+      if (c) {
+        // Gray step: block bit sbits + t flips
+        const int t = __ffsll((unsigned long long)c) - 1;
+        const int64_t g = c ^ (c >> 1);
+        const bool up = (g >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
 #pragma unroll
         for (int i = 0; i < NIN; ++i) {
-          const uint32_t s = bit_stride(mask[i], u);
-          koff[i] = up ? koff[i] + s : koff[i] - s;
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
         }
+        const uint32_t so = bit_stride(out_mask, u);
+        bout = up ? bout + so : bout - so;
+        blk = blk_begin + ((q0 + g) << sbits) + sub;
+        valid = blk < blk_end;
       }
-      E p0, p1;
+      if (q0 + c >= steps) break;  // uniform
+      E acc0[MAXU], acc1[MAXU];
 #pragma unroll
-      for (int i = 0; i < NIN; ++i) {
-        const uint32_t o = boff[i] + koff[i];
-        E a0, a1;
-        if (mask[i] & 1u) {
-          load_pair(inp[i] + o, a0, a1);
-        } else {
-          a0 = inp[i][o];
-          a1 = a0;
+      for (int k = 0; k < MAXU; ++k) {
+        acc0[k] = E{0, 0};
+        acc1[k] = E{0, 0};
+      }
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = valid ? boff[i] : loff[i];
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int64_t it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffsll((unsigned long long)it) - 1;  // Gray code over the summed loop bits
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
         }
-        if (i == 0) {
-          p0 = a0;
-          p1 = a1;
-        } else {
-          p0 = cmul(p0, a0);
-          p1 = cmul(p1, a1);
+#pragma unroll
+        for (int k = 0; k < MAXU; ++k) {
+          if (k < U) {
+            E p0, p1;
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+              const uint32_t o = koff[i] + (k ? us0[i] : 0u);
+              E a0, a1;
+              if (mask[i] & 1u) {
+                load_pair(inp[i] + o, a0, a1);
+              } else {
+                a0 = inp[i][o];
+                a1 = a0;
+              }
+              if (i == 0) {
+                p0 = a0;
+                p1 = a1;
+              } else {
+                p0 = cmul(p0, a0);
+                p1 = cmul(p1, a1);
+              }
+            }
+            acc0[k] = cadd(acc0[k], p0);
+            acc1[k] = cadd(acc1[k], p1);
+          }
         }
       }
-      acc0 = cadd(acc0, p0);
-      acc1 = cadd(acc1, p1);
-    }
-    if (lane_sum) {
-      for (int j = 0; j < 6; ++j)
-        if ((lane_sum >> j) & 1) {
-          acc0 = cadd(acc0, shfl_xor_c(acc0, 1 << j));
-          acc1 = cadd(acc1, shfl_xor_c(acc1, 1 << j));
+#pragma unroll
+      for (int k = 0; k < MAXU; ++k) {
+        if (k < U) {  // uniform
+          E s0 = acc0[k], s1 = acc1[k];
+          if (!out_pair) s0 = cadd(s0, s1);
+          if (lane_sum & 63u) {
+            for (int j = 0; j < 6; ++j)
+              if ((lane_sum >> j) & 1) {
+                s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+                if (out_pair) s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+              }
+          }
+          if (ldsred) {
+            // lanes of the same sub-block in other wavefronts: combine in LDS
+            __syncthreads();
+            red->v[2 * tid] = s0;
+            red->v[2 * tid + 1] = s1;
+            __syncthreads();
+            const uint32_t hi = lane_sum & ~63u;
+            if ((lane & hi) == 0)
+              for (uint32_t m = hi; m; m = (m - 1) & hi) {
+                s0 = cadd(s0, red->v[2 * (tid ^ (int)m)]);
+                s1 = cadd(s1, red->v[2 * (tid ^ (int)m) + 1]);
+              }
+          }
+          if (valid && (lane & lane_sum) == 0) {
+            const uint32_t o = bout + (k ? uo0 : 0u);
+            if (out_pair) {
+              if (atomic) {
+                atomic_add_c(outp + o, s0);
+                atomic_add_c(outp + o + 1, s1);
+              } else {
+                store_pair(outp + o, s0, s1);
+              }
+            } else {
+              if (atomic)
+                atomic_add_c(outp + o, s0);
+              else
+                outp[o] = s0;
+            }
+          }
         }
-    }
-    if (valid && (lane & lane_sum) == 0) {
-      if (out_pair) {
-        if (atomic) {
-          atomic_add_c(outp + bout, acc0);
-          atomic_add_c(outp + bout + 1, acc1);
-        } else {
-          store_pair(outp + bout, acc0, acc1);
-        }
-      } else {
-        const E s = cadd(acc0, acc1);
-        if (atomic)
-          atomic_add_c(outp + bout, s);
-        else
-          outp[bout] = s;
       }
     }
   }
 }
 
-template <typename R>
-__device__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1, int64_t r,
-                                  int64_t c) {
+template <typename R, int MAXNIN>
+__device__ __forceinline__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1, int64_t r,
+                                  int64_t c, RedBuf<typename CT<R>::E>* red) {
   switch (d.n_in) {
-    case 1: exec_contract<R, 1>(d, arena, b0, b1, r, c); break;
-    case 2: exec_contract<R, 2>(d, arena, b0, b1, r, c); break;
-    case 3: exec_contract<R, 3>(d, arena, b0, b1, r, c); break;
-    case 4: exec_contract<R, 4>(d, arena, b0, b1, r, c); break;
-    case 5: exec_contract<R, 5>(d, arena, b0, b1, r, c); break;
-    case 6: exec_contract<R, 6>(d, arena, b0, b1, r, c); break;
-    case 7: exec_contract<R, 7>(d, arena, b0, b1, r, c); break;
-    default: exec_contract<R, 8>(d, arena, b0, b1, r, c); break;
+    case 1: exec_contract<R, 1>(d, arena, b0, b1, r, c, red); break;
+    case 2: exec_contract<R, 2>(d, arena, b0, b1, r, c, red); break;
+    case 3: exec_contract<R, 3>(d, arena, b0, b1, r, c, red); break;
+    case 4: if constexpr (MAXNIN >= 4) exec_contract<R, 4>(d, arena, b0, b1, r, c, red); break;
+    case 5: if constexpr (MAXNIN >= 5) exec_contract<R, 5>(d, arena, b0, b1, r, c, red); break;
+    case 6: if constexpr (MAXNIN >= 6) exec_contract<R, 6>(d, arena, b0, b1, r, c, red); break;
+    case 7: if constexpr (MAXNIN >= 7) exec_contract<R, 7>(d, arena, b0, b1, r, c, red); break;
+    default: if constexpr (MAXNIN >= 8) exec_contract<R, 8>(d, arena, b0, b1, r, c, red); break;
   }
 }
 
@@ -216,7 +304,7 @@ __device__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int
 // Leaf-product table of one bucket: entry e = prod over the bucket's leaves of
 // leaf[e restricted to the leaf's indices].
 template <typename R>
-__device__ void exec_leaf(const OpDesc& d, typename CT<R>::E* arena, const Env& env, int64_t wg_rank,
+__device__ __forceinline__ void exec_leaf(const OpDesc& d, typename CT<R>::E* arena, const Env& env, int64_t wg_rank,
                           int64_t wg_count) {
   using E = typename CT<R>::E;
   const E* vals = reinterpret_cast<const E*>(env.leafvals);
@@ -265,7 +353,7 @@ __device__ double2 block_sum(double2 v) {
 // dR/dtheta += sum_e Lbar[e] * d(leaf product)/dtheta [e], split per leaf:
 // the derivative of one leaf times the product of the others.
 template <typename R>
-__device__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
+__device__ __forceinline__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
   using E = typename CT<R>::E;
   const E* vals = reinterpret_cast<const E*>(env.leafvals);
   const E* dvals = reinterpret_cast<const E*>(env.dleafvals);
@@ -299,7 +387,7 @@ __device__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E* arena, const E
 // Cone value R = product of the scalar outputs; with F_GRAD also the seed
 // dR/dO_s = product of the other scalars, and zeroed gradient accumulators.
 template <typename R>
-__device__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
+__device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
   using E = typename CT<R>::E;
   double* res = env.res + (int64_t)d.cone * env.res_stride;
   const int ns = d.n_in;
@@ -331,19 +419,27 @@ __device__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env
 }
 
 template <typename R>
-__device__ void exec_zero(const OpDesc& d, typename CT<R>::E* arena, int64_t wg_rank, int64_t wg_count) {
+__device__ __forceinline__ void exec_zero(const OpDesc& d, typename CT<R>::E* arena, int64_t wg_rank, int64_t wg_count) {
   using E = typename CT<R>::E;
   E* out = arena + d.out_off;
   const int64_t n = d.in_off[0];
   for (int64_t e = wg_rank * blockDim.x + threadIdx.x; e < n; e += wg_count * blockDim.x) out[e] = E{0, 0};
 }
 
-template <typename R>
-__device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank, int64_t wg_count) {
+// MAXNIN < 0: contraction ops have exactly -MAXNIN inputs (plain launches are
+// specialised per input count on the host); else up to MAXNIN inputs.
+template <typename R, int MAXNIN>
+__device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank,
+                                        int64_t wg_count, RedBuf<typename CT<R>::E>* red) {
   using E = typename CT<R>::E;
   E* arena = reinterpret_cast<E*>(env.arena);
   switch (d.kind) {
-    case OP_CONTRACT: exec_contract_any<R>(d, arena, b0, b1, wg_rank, wg_count); break;
+    case OP_CONTRACT:
+      if constexpr (MAXNIN < 0)
+        exec_contract<R, -MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
+      else
+        exec_contract_any<R, MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
+      break;
     case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
     case OP_RESULT:
       if (wg_rank == 0) exec_result<R>(d, arena, env);
@@ -358,21 +454,41 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
 
 // ------------------------------------------------------------------ kernels
 // One op per launch (the plain per-edge loop).
-template <typename R>
+template <typename R, int NIN>
 __global__ void __launch_bounds__(512) op_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  __shared__ RedBuf<typename CT<R>::E> red;
   const OpDesc& d = ops[op];
-  const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
-  exec_op<R>(d, env, 0, nblocks, blockIdx.x, gridDim.x);
+  const int64_t nblocks = int64_t(1) << d.nb;
+  const int64_t G = gridDim.x;
+  int64_t w = blockIdx.x;
+  if (G % 8 == 0) w = (w % 8) * (G / 8) + w / 8;
+  exec_contract<R, NIN>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, w, G, &red);
+}
+
+// Leaf tables, results, zeroing and leaf gradients (one op per launch).
+template <typename R>
+__global__ void __launch_bounds__(512) misc_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  __shared__ RedBuf<typename CT<R>::E> red;
+  const OpDesc& d = ops[op];
+  const int64_t nblocks = 1;
+  // workgroups are dispatched round-robin over the 8 XCDs: give each XCD a
+  // contiguous range of logical workgroups (and so of blocks), so blocks that
+  // share input data meet in the same L2
+  const int64_t G = gridDim.x;
+  int64_t w = blockIdx.x;
+  if (G % 8 == 0) w = (w % 8) * (G / 8) + w / 8;
+  exec_op<R, 1>(d, env, 0, nblocks, w, G, &red);
 }
 
 // Persistent sweep: workgroups pop items from a device queue in topological
 // order; an item waits until its node counter is zero, runs, then releases
 // its successor nodes.  Every item waits only on items earlier in the queue,
 // which were already taken by running workgroups, so the sweep always drains.
-template <typename R>
+template <typename R, int MAXNIN>
 __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items,
                                                           int n_items, const int32_t* __restrict__ succ, int32_t* ctl,
                                                           Env env, long long spin_limit) {
+  __shared__ RedBuf<typename CT<R>::E> red;
   __shared__ int s_item;
   __shared__ int s_abort;
   int32_t* head = ctl;
@@ -410,7 +526,7 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
         const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
         const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
         const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
-        exec_op<R>(d, env, b0, b1, 0, 1);
+        exec_op<R, MAXNIN>(d, env, b0, b1, 0, 1, &red);
         __syncthreads();
       }
     }
@@ -471,8 +587,24 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
     grid = (h.in_off[0] + threads - 1) / threads;
   }
   if (grid > max_grid) grid = max_grid;
+  if (grid > 8) grid = grid / 8 * 8;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(op_kernel<R>, dim3((unsigned)grid), dim3(threads), 0, st, d_ops, op, env);
+  const dim3 g((unsigned)grid), b(threads);
+  if (h.kind != OP_CONTRACT) {
+    hipLaunchKernelGGL((misc_kernel<R>), g, b, 0, st, d_ops, op, env);
+    return hipGetLastError();
+  }
+  switch (h.n_in) {
+    case 1: hipLaunchKernelGGL((op_kernel<R, 1>), g, b, 0, st, d_ops, op, env); break;
+    case 2: hipLaunchKernelGGL((op_kernel<R, 2>), g, b, 0, st, d_ops, op, env); break;
+    case 3: hipLaunchKernelGGL((op_kernel<R, 3>), g, b, 0, st, d_ops, op, env); break;
+    case 4: hipLaunchKernelGGL((op_kernel<R, 4>), g, b, 0, st, d_ops, op, env); break;
+    case 5: hipLaunchKernelGGL((op_kernel<R, 5>), g, b, 0, st, d_ops, op, env); break;
+    case 6: hipLaunchKernelGGL((op_kernel<R, 6>), g, b, 0, st, d_ops, op, env); break;
+    case 7: hipLaunchKernelGGL((op_kernel<R, 7>), g, b, 0, st, d_ops, op, env); break;
+    case 8: hipLaunchKernelGGL((op_kernel<R, 8>), g, b, 0, st, d_ops, op, env); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -489,16 +621,25 @@ hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_persistent(bool c128, const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
-                             int32_t* ctl, const Env& env, int threads, int grid, long long spin_limit,
-                             hipStream_t st) {
-  if (c128)
-    hipLaunchKernelGGL(persistent_kernel<double>, dim3(grid), dim3(threads), 0, st, ops, items, n_items, succ, ctl,
-                       env, spin_limit);
+template <typename R>
+static hipError_t launch_persistent_t(int max_nin, const OpDesc* ops, const QItem* items, int n_items,
+                                      const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
+                                      long long spin_limit, hipStream_t st) {
+  const dim3 g(grid), b(threads);
+  if (max_nin <= 3)
+    hipLaunchKernelGGL((persistent_kernel<R, 3>), g, b, 0, st, ops, items, n_items, succ, ctl, env, spin_limit);
+  else if (max_nin <= 5)
+    hipLaunchKernelGGL((persistent_kernel<R, 5>), g, b, 0, st, ops, items, n_items, succ, ctl, env, spin_limit);
   else
-    hipLaunchKernelGGL(persistent_kernel<float>, dim3(grid), dim3(threads), 0, st, ops, items, n_items, succ, ctl,
-                       env, spin_limit);
+    hipLaunchKernelGGL((persistent_kernel<R, 8>), g, b, 0, st, ops, items, n_items, succ, ctl, env, spin_limit);
   return hipGetLastError();
+}
+
+hipError_t launch_persistent(bool c128, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
+                             const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
+                             long long spin_limit, hipStream_t st) {
+  return c128 ? launch_persistent_t<double>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, spin_limit, st)
+              : launch_persistent_t<float>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, spin_limit, st);
 }
 
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,

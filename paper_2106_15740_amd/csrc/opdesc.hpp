@@ -19,22 +19,25 @@ enum OpKind : int32_t {
 enum OpFlags : int32_t {
   F_ATOMIC = 1,  // output receives partial sums from several blocks / waves
   F_GRAD = 2,    // OP_RESULT also writes adjoint seeds
+  F_LDSRED = 4,  // summed lane bits >= 6: partial sums are combined across wavefronts in LDS
 };
 
 // A contraction op iterates the union index u of a bucket.  Bit 0 of u is the
 // eliminated index and is handled inside each thread as a pair (x_v = 0, 1).
 // The other union bits are listed in zbit[] in iteration order: the first nl
-// are lanes of a sub-block of 2^nl threads, the next nk are a per-thread loop,
-// the last nb enumerate blocks.  Input i reads element pext(u, in_mask[i]) at
-// in_off[i]; the output is written at pext(u, out_mask).
+// are lanes of a sub-block of 2^nl threads, the next nu are output bits
+// unrolled inside a thread, the next nk are a per-thread summation loop, the
+// last nb enumerate blocks.  Input i reads element pext(u, in_mask[i]) at
+// in_off[i]; the output is written at pext(u, out_mask).  lane_sum marks the
+// lane bits that are summed (reduced across lanes after the loop).
 struct alignas(16) OpDesc {
   int32_t kind;
   int32_t n_in;
   int32_t nbits;      // union bits (contract) / table rank (leaf, leafgrad)
-  int32_t nl, nk, nb;
+  int32_t nl, nu, nk, nb;
   int32_t flags;
   uint32_t out_mask;
-  uint32_t lane_sum;  // lane z-bits (< 6) that are summed by wavefront shuffles
+  uint32_t lane_sum;  // lane z-bits that are summed (shuffles below bit 6, LDS above)
   int32_t cone;
   int32_t aux0, aux1;  // leaf ref range for OP_LEAF / OP_LEAFGRAD
   int64_t out_off;

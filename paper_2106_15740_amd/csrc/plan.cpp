@@ -425,32 +425,70 @@ struct Ctx {
 void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T) {
   std::vector<int> freeb, sumb;
   for (int u = 1; u < nbits; ++u) ((out_mask >> u) & 1 ? freeb : sumb).push_back(u);
-  int max_lanes = std::min(T.lane_cap, 31 - __builtin_clz((unsigned)std::max(T.threads, 1)));
-  std::vector<int> lanes, loop, blocks;
+  const int max_lanes = std::min(T.lane_cap, 31 - __builtin_clz((unsigned)std::max(T.threads, 1)));
+  std::vector<int> lanes, unroll, loop, blocks;
   size_t fi = 0, si = 0;
+  // lanes: the lowest output bits (coalesced stores and, since every tensor
+  // keeps its indices in elimination order, mostly coalesced loads); small
+  // outputs fill the remaining lanes with summed bits (shuffle / LDS reduce)
   while (fi < freeb.size() && (int)lanes.size() < max_lanes) lanes.push_back(freeb[fi++]);
   d.lane_sum = 0;
-  while (si < sumb.size() && (int)lanes.size() < std::min(6, max_lanes)) {
+  while (si < sumb.size() && (int)lanes.size() < max_lanes) {
     d.lane_sum |= 1u << lanes.size();
     lanes.push_back(sumb[si++]);
   }
-  const int loop_cap = seq ? 31 : T.loop_cap;
-  while (si < sumb.size() && (int)loop.size() < loop_cap) loop.push_back(sumb[si++]);
-  while (fi < freeb.size()) blocks.push_back(freeb[fi++]);
+  std::vector<int> rfree(freeb.begin() + fi, freeb.end()), rsum(sumb.begin() + si, sumb.end());
+  if (!seq) {
+    // several outputs per thread: more loads in flight, block offsets amortised
+    // (bounded by the register budget of the kernel variant for this input count)
+    const int nin = d.n_in;
+    const int lim = (T.elem_bytes == 8 && nin <= 2) ? 1 : 0;
+    const int cap = std::min(T.unroll_cap, lim);
+    while ((int)unroll.size() < cap && rfree.size() > unroll.size() + 2) unroll.push_back(rfree[unroll.size()]);
+    rfree.erase(rfree.begin(), rfree.begin() + unroll.size());
+  }
+  int nk;
+  if (seq) {
+    nk = (int)rsum.size();
+  } else {
+    // keep enough blocks to fill the chip: 2^(lanes + blocks) >= 2^par_bits threads
+    const int need = std::max(0, T.par_bits - (int)lanes.size() - (int)rfree.size());
+    nk = std::max(0, (int)rsum.size() - need);
+    nk = std::min(nk, T.loop_cap);
+    nk = std::max(nk, std::min((int)rsum.size(), 3));
+  }
+  loop.assign(rsum.begin(), rsum.begin() + nk);
+  // block bits: the bits that large inputs lack vary fastest, so the blocks
+  // that re-read the same input data run close together (and, with the
+  // XCD-contiguous block mapping, on the same L2)
+  std::vector<std::pair<double, int>> keyed;
+  for (int u : rfree) {
+    double w = 0;
+    for (int i = 0; i < d.n_in; ++i)
+      if (!((d.in_mask[i] >> u) & 1)) {
+        const int r = __builtin_popcount(d.in_mask[i]);
+        if (r >= 16) w += std::ldexp(1.0, r);
+      }
+    keyed.push_back({-w, u});
+  }
+  std::stable_sort(keyed.begin(), keyed.end());
+  for (auto& kv : keyed) blocks.push_back(kv.second);
   bool atomic = false;
-  while (si < sumb.size()) {
-    blocks.push_back(sumb[si++]);
+  for (size_t t = nk; t < rsum.size(); ++t) {
+    blocks.push_back(rsum[t]);
     atomic = true;
   }
   d.nl = (int)lanes.size();
+  d.nu = (int)unroll.size();
   d.nk = (int)loop.size();
   d.nb = (int)blocks.size();
   int z = 0;
   for (int u : lanes) d.zbit[z++] = (uint8_t)u;
+  for (int u : unroll) d.zbit[z++] = (uint8_t)u;
   for (int u : loop) d.zbit[z++] = (uint8_t)u;
   for (int u : blocks) d.zbit[z++] = (uint8_t)u;
   for (; z < 32; ++z) d.zbit[z] = 0;
-  d.flags = atomic ? F_ATOMIC : 0;
+  d.flags = (atomic ? F_ATOMIC : 0) | ((d.lane_sum >> 6) ? F_LDSRED : 0);
 }
 
 OpDesc blank(int kind, int cone) {
@@ -464,7 +502,7 @@ OpDesc blank(int kind, int cone) {
 }  // namespace
 
 std::string build_programs(Plan& P, int elem_bytes) {
-  (void)elem_bytes;
+  P.tune.elem_bytes = elem_bytes;
   const TuneParams& T = P.tune;
   P.ops.clear();
   P.leafrefs.clear();
@@ -742,18 +780,23 @@ std::string validate_plan(const Plan& P) {
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const OpDesc& d = P.ops[o];
     if (d.kind != OP_CONTRACT) continue;
-    if (d.nl + d.nk + d.nb != d.nbits - 1) return "op " + S(o) + "bit partition does not cover the union";
+    if (d.nl + d.nu + d.nk + d.nb != d.nbits - 1) return "op " + S(o) + "bit partition does not cover the union";
+    if (d.nu > ((P.tune.elem_bytes == 8 && d.n_in <= 2) ? 1 : 0)) return "op " + S(o) + "too many unroll bits";
     uint32_t seen = 0;
     bool summed_block = false;
     for (int z = 0; z < d.nbits - 1; ++z) {
       const uint32_t u = d.zbit[z];
       if (u < 1 || (int)u >= d.nbits || (seen >> u) & 1) return "op " + S(o) + "bad zbit";
       seen |= 1u << u;
-      if (z >= d.nl + d.nk && !((d.out_mask >> u) & 1)) summed_block = true;
+      if (z >= d.nl && z < d.nl + d.nu && !((d.out_mask >> u) & 1)) return "op " + S(o) + "summed unroll bit";
+      if (z >= d.nl + d.nu + d.nk && !((d.out_mask >> u) & 1)) summed_block = true;
     }
-    for (int z = 0; z < 6; ++z)
+    for (int z = 0; z < 32; ++z)
       if ((d.lane_sum >> z) & 1)
         if (z >= d.nl || (d.out_mask >> d.zbit[z]) & 1) return "op " + S(o) + "bad lane reduction bit";
+    for (int z = 0; z < d.nl; ++z)
+      if (!((d.lane_sum >> z) & 1) && !((d.out_mask >> d.zbit[z]) & 1)) return "op " + S(o) + "unreduced summed lane bit";
+    if (bool(d.lane_sum >> 6) != bool(d.flags & F_LDSRED)) return "op " + S(o) + "LDS reduction flag mismatch";
     if (summed_block != bool(d.flags & F_ATOMIC)) return "op " + S(o) + "atomic flag mismatch";
     for (int i = 0; i < d.n_in; ++i)
       if (d.in_off[i] < 0 || d.in_off[i] + (int64_t(1) << __builtin_popcount(d.in_mask[i])) > P.arena_grad)

@@ -63,6 +63,9 @@ struct TuneParams {
   int seq_max_bits = 16;    // ops with more union bits run as multi-workgroup tiles
   int tile_blocks = 8;      // blocks of a wide op handled by one queue item
   int loop_cap = 12;        // summed bits kept inside a thread before spilling to atomics
+  int unroll_cap = 1;       // output bits handled inside one thread of a wide op (<= 1)
+  int par_bits = 19;        // a wide op aims at >= 2^par_bits threads
+  int elem_bytes = 8;       // 8: complex64, 16: complex128 (set by build_programs)
 };
 
 struct Plan {
