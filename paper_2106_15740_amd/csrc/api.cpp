@@ -183,6 +183,7 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
   (void)hipGetLastError();
   HIPCHECK(hipMemcpyAsync(n->d_leafvals, n->h_leafvals, n->leaf_bytes, hipMemcpyHostToDevice, st));
   const TuneParams& T = n->P.tune;
+  HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, n->P.leaf_hi, env, T.threads, st));
   if (mode == QTN_PLAIN) {
     for (size_t c = 0; c < n->P.cones.size(); ++c) {
       auto run = [&](int32_t lo, int32_t hi) -> qtn_status {
@@ -208,6 +209,7 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
     HIPCHECK(launch_persistent(n->c128, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env, T.threads, grid,
                                kSpinLimit, st));
   }
+  if (grad) HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, n->P.lgrad_hi, env, T.threads, st));
   HIPCHECK(launch_final(n->c128, env.res, env.res_stride, (int)n->P.cones.size(), n->P.p, grad ? 1 : 0, zz_out,
                         reinterpret_cast<double*>(w + L.fin_off), st));
   HIPCHECK(hipMemcpyAsync(n->h_fin, w + L.fin_off, (1 + 2 * n->P.p) * sizeof(double), hipMemcpyDeviceToHost, st));

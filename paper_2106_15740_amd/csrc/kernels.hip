@@ -10,6 +10,8 @@
 // 16-byte load and sums the pair in registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace qtn {
@@ -480,6 +482,8 @@ __global__ void __launch_bounds__(512) misc_kernel(const OpDesc* __restrict__ op
   exec_op<R, 1>(d, env, 0, nblocks, w, G, &red);
 }
 
+constexpr int DESC_CHUNK = 16;
+
 // Persistent sweep: workgroups pop items from a device queue in topological
 // order; an item waits until its node counter is zero, runs, then releases
 // its successor nodes.  Every item waits only on items earlier in the queue,
@@ -489,6 +493,7 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
                                                           int n_items, const int32_t* __restrict__ succ, int32_t* ctl,
                                                           Env env, long long spin_limit) {
   __shared__ RedBuf<typename CT<R>::E> red;
+  __shared__ OpDesc sdesc[DESC_CHUNK];
   __shared__ int s_item;
   __shared__ int s_abort;
   int32_t* head = ctl;
@@ -521,12 +526,23 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
     }
     __syncthreads();
     if (!s_abort) {
-      for (int op = I.op_lo; op < I.op_hi; ++op) {
-        const OpDesc& d = ops[op];
-        const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
-        const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
-        const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
-        exec_op<R, MAXNIN>(d, env, b0, b1, 0, 1, &red);
+      // descriptors are staged through LDS in chunks: one bulk copy instead of
+      // a dependent global load per op
+      for (int op0 = I.op_lo; op0 < I.op_hi; op0 += DESC_CHUNK) {
+        const int nd = min(DESC_CHUNK, I.op_hi - op0);
+        constexpr int W = sizeof(OpDesc) / sizeof(uint4);
+        const uint4* src = reinterpret_cast<const uint4*>(ops + op0);
+        uint4* dst = reinterpret_cast<uint4*>(sdesc);
+        for (int t = threadIdx.x; t < nd * W; t += blockDim.x) dst[t] = src[t];
+        __syncthreads();
+        for (int j = 0; j < nd; ++j) {
+          const OpDesc& d = sdesc[j];
+          if (j > 0 && (d.flags & F_SYNC)) __syncthreads();
+          const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
+          const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
+          const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
+          exec_op<R, MAXNIN>(d, env, b0, b1, 0, 1, &red);
+        }
         __syncthreads();
       }
     }
@@ -535,6 +551,18 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
       for (int s = I.succ_lo; s < I.succ_hi; ++s)
         __hip_atomic_fetch_add(node_cnt + succ[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
+  }
+}
+
+// Independent small ops of every cone in one launch: the leaf-product tables
+// before a sweep, the leaf gradients after the adjoint sweep.  One workgroup
+// per op.
+template <typename R>
+__global__ void __launch_bounds__(512) batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env) {
+  __shared__ RedBuf<typename CT<R>::E> red;
+  for (int op = lo + blockIdx.x; op < hi; op += gridDim.x) {
+    exec_op<R, 1>(ops[op], env, 0, 1, 0, 1, &red);
     __syncthreads();
   }
 }
@@ -612,6 +640,16 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
                      int max_grid, hipStream_t st) {
   return c128 ? launch_op_t<double>(d_ops, h, op, env, threads, max_grid, st)
               : launch_op_t<float>(d_ops, h, op, env, threads, max_grid, st);
+}
+
+hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st) {
+  if (hi <= lo) return hipSuccess;
+  const int grid = std::min(hi - lo, 8192);
+  if (c128)
+    hipLaunchKernelGGL(batch_kernel<double>, dim3(grid), dim3(threads), 0, st, d_ops, lo, hi, env);
+  else
+    hipLaunchKernelGGL(batch_kernel<float>, dim3(grid), dim3(threads), 0, st, d_ops, lo, hi, env);
+  return hipGetLastError();
 }
 
 hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st) {

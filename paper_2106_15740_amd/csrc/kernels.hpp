@@ -20,6 +20,8 @@ struct Env {
 
 hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads,
                      int max_grid, hipStream_t st);
+// ops [lo, hi) (OP_LEAF or OP_LEAFGRAD), one workgroup each
+hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st);
 hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st);
 // max_nin: the largest input count of any contraction op in the items.
 hipError_t launch_persistent(bool c128, int max_nin, const OpDesc* ops, const QItem* items, int n_items,

@@ -20,6 +20,7 @@ enum OpFlags : int32_t {
   F_ATOMIC = 1,  // output receives partial sums from several blocks / waves
   F_GRAD = 2,    // OP_RESULT also writes adjoint seeds
   F_LDSRED = 4,  // summed lane bits >= 6: partial sums are combined across wavefronts in LDS
+  F_SYNC = 8,    // in a sequential program: barrier before this op (it depends on an op since the last one)
 };
 
 // A contraction op iterates the union index u of a bucket.  Bit 0 of u is the

@@ -501,6 +501,54 @@ OpDesc blank(int kind, int cone) {
 
 }  // namespace
 
+// F_SYNC marks the ops of a cone program that must wait for the whole
+// workgroup before they start, because they read or overwrite data written by
+// an op since the previous barrier.  Independent consecutive ops (e.g. the
+// buckets of unrelated branches of the elimination tree) run without one.
+static void mark_barriers(Plan& P) {
+  struct Rng {
+    int64_t lo, hi;
+  };
+  auto overlaps = [](const std::vector<Rng>& v, int64_t lo, int64_t hi) {
+    for (const Rng& r : v)
+      if (lo < r.hi && r.lo < hi) return true;
+    return false;
+  };
+  auto run = [&](int32_t lo, int32_t hi, std::vector<Rng>& dirty) {
+    for (int32_t o = lo; o < hi; ++o) {
+      OpDesc& d = P.ops[o];
+      std::vector<Rng> rd, wr;
+      if (d.kind == OP_CONTRACT) {
+        for (int i = 0; i < d.n_in; ++i) rd.push_back({d.in_off[i], d.in_off[i] + (int64_t(1) << __builtin_popcount(d.in_mask[i]))});
+        wr.push_back({d.out_off, d.out_off + (int64_t(1) << __builtin_popcount(d.out_mask))});
+      } else if (d.kind == OP_RESULT) {
+        for (int i = 0; i < d.n_in; ++i) rd.push_back({d.in_off[i], d.in_off[i] + 1});
+        if (d.flags & F_GRAD)
+          for (int i = 0; i < d.n_in; ++i) wr.push_back({d.in_off[d.n_in + i], d.in_off[d.n_in + i] + 1});
+      } else if (d.kind == OP_ZERO) {
+        wr.push_back({d.out_off, d.out_off + d.in_off[0]});
+      }
+      bool need = false;
+      for (const Rng& r : rd) need |= overlaps(dirty, r.lo, r.hi);
+      for (const Rng& r : wr) need |= overlaps(dirty, r.lo, r.hi);
+      if (need) {
+        d.flags |= F_SYNC;
+        dirty.clear();
+      } else {
+        d.flags &= ~F_SYNC;
+      }
+      dirty.insert(dirty.end(), wr.begin(), wr.end());
+    }
+  };
+  for (size_t c = 0; c < P.cones.size(); ++c) {
+    std::vector<Rng> dirty;
+    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1, dirty);  // forward program ends with its result op
+    dirty.clear();
+    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c], dirty);      // gradient program: forward ops, then the adjoint range
+    run(P.cone_adj_lo[c], P.cone_adj_hi[c], dirty);
+  }
+}
+
 std::string build_programs(Plan& P, int elem_bytes) {
   P.tune.elem_bytes = elem_bytes;
   const TuneParams& T = P.tune;
@@ -512,6 +560,7 @@ std::string build_programs(Plan& P, int elem_bytes) {
   P.cone_adj_lo.assign(nc, 0);
   P.cone_adj_hi.assign(nc, 0);
   std::vector<std::vector<int32_t>> zero_ops(nc);
+  std::vector<OpDesc> leaf_ops, lgrad_ops;
   for (size_t c = 0; c < nc; ++c) {
     Cone& C = P.cones[c];
     const int64_t base = 0;  // offsets are absolute arena offsets
@@ -520,7 +569,8 @@ std::string build_programs(Plan& P, int elem_bytes) {
     if (C.scalars.size() > MAXIN / 2) return "more than 4 disconnected components in one light cone";
     C.fwd_bytes_alg = C.bwd_bytes_alg = C.fwd_flops = 0;
     P.cone_fwd_lo[c] = (int32_t)P.ops.size();
-    // leaf-product tables
+    // leaf-product tables (one batched launch for all cones, before the sweep)
+    std::vector<int32_t> ref_lo(C.buckets.size(), -1), ref_n(C.buckets.size(), 0);
     for (size_t b = 0; b < C.buckets.size(); ++b) {
       const Bucket& Bk = C.buckets[b];
       if (!Bk.lam_mask) continue;
@@ -542,7 +592,9 @@ std::string build_programs(Plan& P, int elem_bytes) {
         P.leafrefs.push_back(r);
       }
       d.aux1 = (int32_t)P.leafrefs.size() - d.aux0;
-      P.ops.push_back(d);
+      ref_lo[b] = d.aux0;
+      ref_n[b] = d.aux1;
+      leaf_ops.push_back(d);
     }
     // forward buckets
     for (size_t b = 0; b < C.buckets.size(); ++b) {
@@ -646,18 +698,13 @@ std::string build_programs(Plan& P, int elem_bytes) {
         partition_bits(d, nbits, d.out_mask, seq, T);
         if (d.flags & F_ATOMIC) zero_ops[c].push_back((int32_t)P.ops.size());
         P.ops.push_back(d);
+        // leaf gradient of this bucket: one batched launch after the sweep
         OpDesc g = blank(OP_LEAFGRAD, (int)c);
         g.nbits = Bk.lam_rank();
         g.in_off[0] = C.lamadj_off[bb];
-        // the OP_LEAF record of this bucket holds the leaf refs
-        g.aux0 = -1;
-        for (int32_t o = P.cone_fwd_lo[c]; o < P.cone_fwd_hi[c]; ++o)
-          if (P.ops[o].kind == OP_LEAF && P.ops[o].out_off == C.lam_off[bb]) {
-            g.aux0 = P.ops[o].aux0;
-            g.aux1 = P.ops[o].aux1;
-            break;
-          }
-        P.ops.push_back(g);
+        g.aux0 = ref_lo[bb];
+        g.aux1 = ref_n[bb];
+        lgrad_ops.push_back(g);
       }
     }
     P.cone_adj_hi[c] = (int32_t)P.ops.size();
@@ -692,6 +739,13 @@ std::string build_programs(Plan& P, int elem_bytes) {
     }
     P.ops.swap(ops);
   }
+  mark_barriers(P);
+  P.leaf_lo = (int32_t)P.ops.size();
+  P.ops.insert(P.ops.end(), leaf_ops.begin(), leaf_ops.end());
+  P.leaf_hi = (int32_t)P.ops.size();
+  P.lgrad_lo = P.leaf_hi;
+  P.ops.insert(P.ops.end(), lgrad_ops.begin(), lgrad_ops.end());
+  P.lgrad_hi = (int32_t)P.ops.size();
   return "";
 }
 

@@ -79,6 +79,8 @@ struct Plan {
   std::vector<OpDesc> ops;          // all ops of all cones
   std::vector<int32_t> cone_fwd_lo, cone_fwd_hi, cone_adj_lo, cone_adj_hi;
   std::vector<LeafRef> leafrefs;
+  int32_t leaf_lo = 0, leaf_hi = 0;    // all OP_LEAF ops (run before the sweep)
+  int32_t lgrad_lo = 0, lgrad_hi = 0;  // all OP_LEAFGRAD ops (run after the adjoint sweep)
   std::vector<int64_t> cone_base;   // element offset of each cone in the arena
   int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
   // persistent-queue items (forward-only and forward+gradient programs)
