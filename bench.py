@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--repeats", type=int, default=10,
+                    help="randomized greedy order: runs per cone on top of the deterministic one (0: deterministic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the light-cone sweep is not sharded across GPUs in this "
@@ -108,7 +110,7 @@ def main():
     from paper_2106_15740_amd import QaoaNet
 
     t0 = time.perf_counter()
-    net = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=w.order, device=0)
+    net = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=w.order, device=0, repeats=args.repeats)
     plan_s = time.perf_counter() - t0
     net.set_params(w.gamma, w.beta)
     info = net.info()
@@ -160,7 +162,8 @@ def main():
                                f"{w.dtype}, {w.order.replace('_', '-')} order, batched persistent sweep "
                                f"(energy + gradient)",
                    "n_vertices": w.n, "n_edges": len(w.edges), "p": w.p, "order": w.order,
-                   "max_width": info["max_width"], "buckets": info["n_buckets"]},
+                   "repeats": args.repeats, "max_width": info["max_width"], "buckets": info["n_buckets"],
+                   "lds_resident_cones": info["n_lds_cones"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
                      "kernel": "persistent_kernel", "kernel_ms": k_avg_ms,

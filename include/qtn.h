@@ -61,6 +61,7 @@ typedef struct {
   int32_t tile_blocks;  /* blocks of a split bucket handled by one queue item */
   int32_t loop_cap;     /* summed bits looped inside a thread before partial sums go to atomics */
   int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
+  int32_t lds_kb;       /* LDS window (KiB) for light cones that run LDS-resident in the batched sweep (0: none) */
 } qtn_tuning;
 
 typedef struct {
@@ -76,6 +77,8 @@ typedef struct {
   double bwd_bytes;         /* algorithmic bytes of the adjoint sweep */
   double fwd_flops;         /* complex multiply = 6, add = 2 */
   size_t ws_fwd, ws_grad;   /* workspace bytes: forward only / forward + gradient */
+  int32_t n_lds_cones;      /* light cones that run LDS-resident in the batched sweep */
+  int32_t lds_window;       /* bytes of LDS window each persistent workgroup reserves for them */
 } qtn_info;
 
 /* Context bound to HIP device `device` (hipSetDevice is called on it).  Owns a

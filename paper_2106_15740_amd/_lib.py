@@ -33,7 +33,8 @@ class QtnError(RuntimeError):
 
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("lane_cap", C.c_int32), ("seq_max_bits", C.c_int32),
-                ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32)]
+                ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32),
+                ("lds_kb", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -44,7 +45,7 @@ class Info(C.Structure):
                 ("n_buckets", C.c_int64), ("n_ops_fwd", C.c_int64), ("n_ops_grad", C.c_int64),
                 ("n_items_fwd", C.c_int64), ("n_items_grad", C.c_int64), ("fwd_bytes", C.c_double),
                 ("bwd_bytes", C.c_double), ("fwd_flops", C.c_double), ("ws_fwd", C.c_size_t),
-                ("ws_grad", C.c_size_t)]
+                ("ws_grad", C.c_size_t), ("n_lds_cones", C.c_int32), ("lds_window", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -206,8 +206,9 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
     int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
     HIPCHECK(launch_reset(ctl, pg.init, pg.n_nodes, st));
     const int grid = std::max(1, std::min<int>(n->grid, std::max(1, pg.n_items)));
+    const size_t lds_bytes = (size_t)n->P.lds_elems * n->elem;
     HIPCHECK(launch_persistent(n->c128, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env, T.threads, grid,
-                               kSpinLimit, st));
+                               lds_bytes, kSpinLimit, st));
   }
   if (grad) HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, n->P.lgrad_hi, env, T.threads, st));
   HIPCHECK(launch_final(n->c128, env.res, env.res_stride, (int)n->P.cones.size(), n->P.p, grad ? 1 : 0, zz_out,
@@ -551,6 +552,8 @@ qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
   out->n_items_grad = (int64_t)n->P.items_grad.size();
   out->ws_fwd = ws_layout(n, false).total;
   out->ws_grad = ws_layout(n, true).total;
+  for (char l : n->P.cone_lds) out->n_lds_cones += l ? 1 : 0;
+  out->lds_window = (int32_t)(n->P.lds_elems * n->elem);
   return QTN_OK;
 }
 
@@ -578,6 +581,7 @@ qtn_status qtn_get_tuning(const qtn_net* n, qtn_tuning* out) {
   out->tile_blocks = n->P.tune.tile_blocks;
   out->loop_cap = n->P.tune.loop_cap;
   out->grid = n->grid;
+  out->lds_kb = n->P.tune.lds_kb;
   return QTN_OK;
 }
 
@@ -590,11 +594,13 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->tile_blocks < 1) return fail(QTN_EINVAL, "tile_blocks must be >= 1");
   if (t->loop_cap < 0 || t->loop_cap > 31) return fail(QTN_EINVAL, "loop_cap must be in 0..31");
   if (t->grid < 0) return fail(QTN_EINVAL, "grid must be >= 0");
+  if (t->lds_kb < 0 || t->lds_kb > 128) return fail(QTN_EINVAL, "lds_kb must be in 0..128");
   n->P.tune.threads = th;
   n->P.tune.lane_cap = t->lane_cap;
   n->P.tune.seq_max_bits = t->seq_max_bits;
   n->P.tune.tile_blocks = t->tile_blocks;
   n->P.tune.loop_cap = t->loop_cap;
+  n->P.tune.lds_kb = t->lds_kb;
   n->grid = t->grid ? t->grid : 8 * n->ctx->n_cu;
   if (!n->P.ordered) return QTN_OK;
   return rebuild_programs(n);

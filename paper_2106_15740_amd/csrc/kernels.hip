@@ -100,10 +100,10 @@ struct RedBuf {
   E v[512 * 2];
 };
 
-template <typename R, int NIN>
+template <typename R, int NIN, bool USE_LDS = false>
 __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
                               int64_t blk_end, int64_t wg_rank, int64_t wg_count,
-                              RedBuf<typename CT<R>::E>* __restrict__ red) {
+                              RedBuf<typename CT<R>::E>* __restrict__ red, typename CT<R>::E* lds = nullptr) {
   using E = typename CT<R>::E;
   constexpr int MAXU = MaxU<R, NIN>::value;
   const int tid = threadIdx.x;
@@ -125,7 +125,10 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
 #pragma unroll
   for (int i = 0; i < NIN; ++i) {
     mask[i] = d.in_mask[i];
-    inp[i] = arena + d.in_off[i];
+    if constexpr (USE_LDS)
+      inp[i] = ((d.lds_mask >> i) & 1u) ? lds + d.lds_off[i] : arena + d.in_off[i];
+    else
+      inp[i] = arena + d.in_off[i];
     uint32_t o = 0;
     for (int j = 0; j < nl; ++j)
       if ((lane >> j) & 1) o += bit_stride(mask[i], d.zbit[j]);
@@ -138,7 +141,11 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
 #pragma unroll
   for (int i = 0; i < NIN; ++i) us0[i] = (MAXU > 1 && nu > 0) ? bit_stride(mask[i], d.zbit[nl]) : 0u;
   const uint32_t uo0 = (MAXU > 1 && nu > 0) ? bit_stride(out_mask, d.zbit[nl]) : 0u;
-  E* outp = arena + d.out_off;
+  E* outp;
+  if constexpr (USE_LDS)
+    outp = ((d.lds_mask >> MAXIN) & 1u) ? lds + d.lds_off[MAXIN] : arena + d.out_off;
+  else
+    outp = arena + d.out_off;
   const uint32_t lane_sum = d.lane_sum;
   const int zk0 = nl + nu;
   const int zb0 = nl + nu + nk;
@@ -287,18 +294,19 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
   }
 }
 
-template <typename R, int MAXNIN>
-__device__ __forceinline__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1, int64_t r,
-                                  int64_t c, RedBuf<typename CT<R>::E>* red) {
+template <typename R, int MAXNIN, bool USE_LDS>
+__device__ __forceinline__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                                  int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red,
+                                                  typename CT<R>::E* lds) {
   switch (d.n_in) {
-    case 1: exec_contract<R, 1>(d, arena, b0, b1, r, c, red); break;
-    case 2: exec_contract<R, 2>(d, arena, b0, b1, r, c, red); break;
-    case 3: exec_contract<R, 3>(d, arena, b0, b1, r, c, red); break;
-    case 4: if constexpr (MAXNIN >= 4) exec_contract<R, 4>(d, arena, b0, b1, r, c, red); break;
-    case 5: if constexpr (MAXNIN >= 5) exec_contract<R, 5>(d, arena, b0, b1, r, c, red); break;
-    case 6: if constexpr (MAXNIN >= 6) exec_contract<R, 6>(d, arena, b0, b1, r, c, red); break;
-    case 7: if constexpr (MAXNIN >= 7) exec_contract<R, 7>(d, arena, b0, b1, r, c, red); break;
-    default: if constexpr (MAXNIN >= 8) exec_contract<R, 8>(d, arena, b0, b1, r, c, red); break;
+    case 1: exec_contract<R, 1, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 2: exec_contract<R, 2, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 3: exec_contract<R, 3, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 4: if constexpr (MAXNIN >= 4) exec_contract<R, 4, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 5: if constexpr (MAXNIN >= 5) exec_contract<R, 5, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 6: if constexpr (MAXNIN >= 6) exec_contract<R, 6, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 7: if constexpr (MAXNIN >= 7) exec_contract<R, 7, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    default: if constexpr (MAXNIN >= 8) exec_contract<R, 8, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
   }
 }
 
@@ -389,14 +397,18 @@ __device__ __forceinline__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E
 // Cone value R = product of the scalar outputs; with F_GRAD also the seed
 // dR/dO_s = product of the other scalars, and zeroed gradient accumulators.
 template <typename R>
-__device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
+__device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env,
+                                            typename CT<R>::E* lds = nullptr) {
   using E = typename CT<R>::E;
   double* res = env.res + (int64_t)d.cone * env.res_stride;
   const int ns = d.n_in;
+  auto at = [&](int i) -> E* {
+    return (lds && ((d.lds_mask >> i) & 1u)) ? lds + d.lds_off[i] : arena + d.in_off[i];
+  };
   if (threadIdx.x == 0) {
     double2 prod = make_double2(1, 0);
     for (int s = 0; s < ns; ++s) {
-      const E x = arena[d.in_off[s]];
+      const E x = *at(s);
       prod = cmul(prod, make_double2(x.x, x.y));
     }
     res[0] = prod.x;
@@ -408,13 +420,13 @@ __device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* 
       double2 seed = make_double2(1, 0);
       for (int t = 0; t < ns; ++t)
         if (t != s) {
-          const E x = arena[d.in_off[t]];
+          const E x = *at(t);
           seed = cmul(seed, make_double2(x.x, x.y));
         }
       E o;
       o.x = (R)seed.x;
       o.y = (R)seed.y;
-      arena[d.in_off[ns + s]] = o;
+      *at(ns + s) = o;
     }
     for (int i = threadIdx.x; i < 4 * env.p; i += blockDim.x) res[2 + i] = 0.0;
   }
@@ -430,9 +442,10 @@ __device__ __forceinline__ void exec_zero(const OpDesc& d, typename CT<R>::E* ar
 
 // MAXNIN < 0: contraction ops have exactly -MAXNIN inputs (plain launches are
 // specialised per input count on the host); else up to MAXNIN inputs.
-template <typename R, int MAXNIN>
+template <typename R, int MAXNIN, bool USE_LDS = false>
 __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank,
-                                        int64_t wg_count, RedBuf<typename CT<R>::E>* red) {
+                                        int64_t wg_count, RedBuf<typename CT<R>::E>* red,
+                                        typename CT<R>::E* lds = nullptr) {
   using E = typename CT<R>::E;
   E* arena = reinterpret_cast<E*>(env.arena);
   switch (d.kind) {
@@ -440,11 +453,11 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
       if constexpr (MAXNIN < 0)
         exec_contract<R, -MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
       else
-        exec_contract_any<R, MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
+        exec_contract_any<R, MAXNIN, USE_LDS>(d, arena, b0, b1, wg_rank, wg_count, red, lds);
       break;
     case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
     case OP_RESULT:
-      if (wg_rank == 0) exec_result<R>(d, arena, env);
+      if (wg_rank == 0) exec_result<R>(d, arena, env, USE_LDS ? lds : nullptr);
       break;
     case OP_ZERO: exec_zero<R>(d, arena, wg_rank, wg_count); break;
     case OP_LEAFGRAD:
@@ -494,6 +507,7 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
                                                           Env env, long long spin_limit) {
   __shared__ RedBuf<typename CT<R>::E> red;
   __shared__ OpDesc sdesc[DESC_CHUNK];
+  extern __shared__ __align__(16) char dyn_lds[];
   __shared__ int s_item;
   __shared__ int s_abort;
   int32_t* head = ctl;
@@ -526,24 +540,41 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
     }
     __syncthreads();
     if (!s_abort) {
+      using E = typename CT<R>::E;
+      E* lds = nullptr;
+      if (I.copyin >= 0) {
+        // LDS-resident cone: bring its leaf-product block into the LDS window
+        const OpDesc& cp = ops[I.copyin];
+        const E* src = reinterpret_cast<const E*>(env.arena) + cp.in_off[0];
+        lds = reinterpret_cast<E*>(dyn_lds);
+        for (int64_t t = threadIdx.x; t < cp.in_off[1]; t += blockDim.x) lds[t] = src[t];
+        __syncthreads();
+      }
       // descriptors are staged through LDS in chunks: one bulk copy instead of
       // a dependent global load per op
-      for (int op0 = I.op_lo; op0 < I.op_hi; op0 += DESC_CHUNK) {
-        const int nd = min(DESC_CHUNK, I.op_hi - op0);
-        constexpr int W = sizeof(OpDesc) / sizeof(uint4);
-        const uint4* src = reinterpret_cast<const uint4*>(ops + op0);
-        uint4* dst = reinterpret_cast<uint4*>(sdesc);
-        for (int t = threadIdx.x; t < nd * W; t += blockDim.x) dst[t] = src[t];
-        __syncthreads();
-        for (int j = 0; j < nd; ++j) {
-          const OpDesc& d = sdesc[j];
-          if (j > 0 && (d.flags & F_SYNC)) __syncthreads();
-          const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
-          const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
-          const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
-          exec_op<R, MAXNIN>(d, env, b0, b1, 0, 1, &red);
+      for (int r = 0; r < 2; ++r) {
+        const int lo = r ? I.op2_lo : I.op_lo;
+        const int hi = r ? I.op2_hi : I.op_hi;
+        for (int op0 = lo; op0 < hi; op0 += DESC_CHUNK) {
+          const int nd = min(DESC_CHUNK, hi - op0);
+          constexpr int W = sizeof(OpDesc) / sizeof(uint4);
+          const uint4* src = reinterpret_cast<const uint4*>(ops + op0);
+          uint4* dst = reinterpret_cast<uint4*>(sdesc);
+          for (int t = threadIdx.x; t < nd * W; t += blockDim.x) dst[t] = src[t];
+          __syncthreads();
+          for (int j = 0; j < nd; ++j) {
+            const OpDesc& d = sdesc[j];
+            if (j > 0 && (d.flags & F_SYNC)) __syncthreads();
+            const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
+            const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
+            const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
+            if (lds)
+              exec_op<R, MAXNIN, true>(d, env, b0, b1, 0, 1, &red, lds);
+            else
+              exec_op<R, MAXNIN, false>(d, env, b0, b1, 0, 1, &red);
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
     }
     if (threadIdx.x == 0 && I.succ_hi > I.succ_lo) {
@@ -659,25 +690,38 @@ hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStrea
   return hipGetLastError();
 }
 
+template <typename R, int M>
+static hipError_t launch_persistent_m(const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
+                                      int32_t* ctl, const Env& env, int threads, int grid, size_t lds_bytes,
+                                      long long spin_limit, hipStream_t st) {
+  if (lds_bytes > 0) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&persistent_kernel<R, M>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((persistent_kernel<R, M>), dim3(grid), dim3(threads), lds_bytes, st, ops, items, n_items, succ,
+                     ctl, env, spin_limit);
+  return hipGetLastError();
+}
+
 template <typename R>
 static hipError_t launch_persistent_t(int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                                       const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
-                                      long long spin_limit, hipStream_t st) {
-  const dim3 g(grid), b(threads);
+                                      size_t lds_bytes, long long spin_limit, hipStream_t st) {
   if (max_nin <= 3)
-    hipLaunchKernelGGL((persistent_kernel<R, 3>), g, b, 0, st, ops, items, n_items, succ, ctl, env, spin_limit);
-  else if (max_nin <= 5)
-    hipLaunchKernelGGL((persistent_kernel<R, 5>), g, b, 0, st, ops, items, n_items, succ, ctl, env, spin_limit);
-  else
-    hipLaunchKernelGGL((persistent_kernel<R, 8>), g, b, 0, st, ops, items, n_items, succ, ctl, env, spin_limit);
-  return hipGetLastError();
+    return launch_persistent_m<R, 3>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
+  if (max_nin <= 5)
+    return launch_persistent_m<R, 5>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
+  return launch_persistent_m<R, 8>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
 }
 
 hipError_t launch_persistent(bool c128, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
-                             long long spin_limit, hipStream_t st) {
-  return c128 ? launch_persistent_t<double>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, spin_limit, st)
-              : launch_persistent_t<float>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, spin_limit, st);
+                             size_t lds_bytes, long long spin_limit, hipStream_t st) {
+  return c128 ? launch_persistent_t<double>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes,
+                                            spin_limit, st)
+              : launch_persistent_t<float>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes,
+                                           spin_limit, st);
 }
 
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,

@@ -24,9 +24,10 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
 hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st);
 hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st);
 // max_nin: the largest input count of any contraction op in the items.
+// lds_bytes: dynamic LDS window of LDS-resident items (0: none)
 hipError_t launch_persistent(bool c128, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
-                             long long spin_limit, hipStream_t st);
+                             size_t lds_bytes, long long spin_limit, hipStream_t st);
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
                         double* fin, hipStream_t st);
 

@@ -14,6 +14,7 @@ enum OpKind : int32_t {
   OP_RESULT = 2,    // cone value R = prod of scalar outputs; optional adjoint seeds
   OP_ZERO = 3,      // zero a range of the arena
   OP_LEAFGRAD = 4,  // dR/dtheta from the adjoint of one leaf-product table
+  OP_COPYIN = 5,    // copy a cone's leaf-product block into its LDS window (persistent sweep only)
 };
 
 enum OpFlags : int32_t {
@@ -45,6 +46,11 @@ struct alignas(16) OpDesc {
   int64_t in_off[MAXIN];
   uint32_t in_mask[MAXIN];
   uint8_t zbit[32];
+  // LDS-resident execution (persistent sweep): operand i (output: MAXIN) is
+  // at LDS element offset lds_off[i] when bit i of lds_mask is set
+  uint32_t lds_mask;
+  int32_t lds_off[MAXIN + 1];
+  int32_t pad_[2];
 };
 
 struct LeafRef {
@@ -52,17 +58,19 @@ struct LeafRef {
   int8_t pa, pb;  // bit positions inside the leaf-product table (pb < 0: rank 1)
 };
 
-// Persistent-queue work item: ops [op_lo, op_hi) run in sequence by one
-// workgroup over all their blocks (blk_hi < 0), or blocks [blk_lo, blk_hi) of
-// the single op op_lo.  The item may start once node_cnt[node] reaches zero
-// (node < 0: no dependency) and on completion decrements node_cnt[s] for every
-// s in succ[succ_lo, succ_hi).
+// Persistent-queue work item: ops [op_lo, op_hi) then [op2_lo, op2_hi) run
+// in sequence by one workgroup over all their blocks (blk_hi < 0), or blocks
+// [blk_lo, blk_hi) of the single op op_lo.  The item may start once
+// node_cnt[node] reaches zero (node < 0: no dependency) and on completion
+// decrements node_cnt[s] for every s in succ[succ_lo, succ_hi).
 struct QItem {
   int32_t op_lo, op_hi;
+  int32_t op2_lo, op2_hi;  // second range (-1: none)
   int32_t blk_lo, blk_hi;
   int32_t node;
   int32_t succ_lo, succ_hi;
-  int32_t pad;
+  int32_t copyin;  // >= 0: the item runs LDS-resident; this op fills the LDS window first
+  int32_t pad[2];
 };
 
 }  // namespace qtn

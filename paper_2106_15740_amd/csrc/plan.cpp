@@ -13,6 +13,7 @@
 #include <climits>
 #include <numeric>
 #include <thread>
+#include <unordered_map>
 #include <set>
 
 namespace qtn {
@@ -378,17 +379,23 @@ void layout_cones(Plan& P) {
     C.lam_off.assign(nb, -1);
     C.adj_off.assign(nb, -1);
     C.lamadj_off.assign(nb, -1);
-    for (size_t b = 0; b < nb; ++b) {
-      int64_t sz = int64_t(1) << C.buckets[b].out_rank();
-      off = align_elems(off, sz);
-      C.out_off[b] = off;
-      off += std::max<int64_t>(sz, 2);
+    // the cone's leaf-product tables form one contiguous block (copied into
+    // LDS as a whole when the cone runs LDS-resident)
+    off = align_elems(off, 64);
+    C.lam_base = off;
+    for (size_t b = 0; b < nb; ++b)
       if (C.buckets[b].lam_mask) {
         int64_t sl = int64_t(1) << C.buckets[b].lam_rank();
         off = align_elems(off, sl);
         C.lam_off[b] = off;
         off += sl;
       }
+    C.lam_size = off - C.lam_base;
+    for (size_t b = 0; b < nb; ++b) {
+      int64_t sz = int64_t(1) << C.buckets[b].out_rank();
+      off = align_elems(off, sz);
+      C.out_off[b] = off;
+      off += std::max<int64_t>(sz, 2);
     }
   }
   P.arena_fwd = align_elems(off, 64);
@@ -501,51 +508,181 @@ OpDesc blank(int kind, int cone) {
 
 }  // namespace
 
+// LDS-resident cones: when every op of a cone's program fits one workgroup,
+// its tensors can live in LDS for the whole persistent sweep.  Lifetimes are
+// taken over the gradient program (forward ops, result, adjoint ops), which
+// covers the forward-only program too; buffers are placed first-fit by
+// definition time.  The leaf-product block sits at LDS offset 0 for the whole
+// program.  The adjoints of the leaf tables stay in global memory (the leaf
+// gradients are batched after the sweep).  Ops keep their global offsets for
+// the plain per-op path; lds_off/lds_mask are used only by the persistent
+// kernel in items flagged as LDS-resident.
+static void lds_layout(Plan& P) {
+  const TuneParams& T = P.tune;
+  const int64_t budget = (int64_t)T.lds_kb * 1024 / std::max(1, T.elem_bytes);
+  P.cone_lds.assign(P.cones.size(), 0);
+  P.lds_elems = 0;
+  if (budget <= 0) return;
+  for (size_t c = 0; c < P.cones.size(); ++c) {
+    Cone& C = P.cones[c];
+    std::vector<int32_t> prog;
+    for (int32_t o = P.cone_fwd_lo[c]; o <= P.cone_fwd_hi[c]; ++o) prog.push_back(o);  // includes forward result
+    for (int32_t o = P.cone_adj_lo[c]; o < P.cone_adj_hi[c]; ++o) prog.push_back(o);
+    bool ok = true;
+    for (int32_t o : prog) {
+      const OpDesc& d = P.ops[o];
+      if (d.kind == OP_ZERO || (d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits)) ok = false;
+    }
+    if (!ok || C.lam_size > budget) continue;
+    // buffers by global offset: forward outputs and adjoint buffers
+    struct Buf {
+      int64_t goff, size;
+      int def = -1, last = -1;
+      int64_t loff = -1;
+    };
+    std::vector<Buf> bufs;
+    std::unordered_map<int64_t, int> id;
+    auto add = [&](int64_t g, int64_t sz) {
+      if (id.count(g)) return;
+      id[g] = (int)bufs.size();
+      bufs.push_back({g, std::max<int64_t>(sz, 2)});
+    };
+    for (size_t b = 0; b < C.buckets.size(); ++b) {
+      const int64_t sz = int64_t(1) << C.buckets[b].out_rank();
+      add(C.out_off[b], sz);
+      add(C.adj_off[b], sz);
+    }
+    auto in_lam = [&](int64_t g) { return g >= C.lam_base && g < C.lam_base + C.lam_size; };
+    auto touch = [&](int64_t g, int t, bool write) {
+      auto it = id.find(g);
+      if (it == id.end()) return;
+      Buf& B = bufs[it->second];
+      if (write && B.def < 0) B.def = t;
+      if (B.def < 0) B.def = t;
+      B.last = std::max(B.last, t);
+    };
+    for (size_t t = 0; t < prog.size(); ++t) {
+      const OpDesc& d = P.ops[prog[t]];
+      if (d.kind == OP_CONTRACT) {
+        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t, false);
+        touch(d.out_off, (int)t, true);
+      } else if (d.kind == OP_RESULT) {
+        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t, false);
+        if (d.flags & F_GRAD)
+          for (int i = 0; i < d.n_in; ++i) touch(d.in_off[d.n_in + i], (int)t, true);
+      }
+    }
+    // first fit, lifetimes [def, last]
+    std::vector<int> order;
+    for (size_t i = 0; i < bufs.size(); ++i)
+      if (bufs[i].def >= 0) order.push_back((int)i);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return bufs[a].def < bufs[b].def; });
+    const int64_t base0 = (C.lam_size + 63) / 64 * 64;
+    int64_t peak = base0;
+    std::vector<int> live;
+    for (int bi : order) {
+      Buf& B = bufs[bi];
+      live.erase(std::remove_if(live.begin(), live.end(), [&](int x) { return bufs[x].last < B.def; }), live.end());
+      std::vector<std::pair<int64_t, int64_t>> used;
+      for (int x : live) used.push_back({bufs[x].loff, bufs[x].loff + bufs[x].size});
+      std::sort(used.begin(), used.end());
+      const int64_t al = B.size >= 64 ? 64 : 2;
+      int64_t cand = base0;
+      for (auto& u : used) {
+        if (cand + B.size <= u.first) break;
+        cand = std::max(cand, (u.second + al - 1) / al * al);
+      }
+      B.loff = cand;
+      peak = std::max(peak, cand + B.size);
+      live.push_back(bi);
+    }
+    if (peak > budget) continue;
+    // commit: LDS offsets into the ops
+    P.cone_lds[c] = 1;
+    P.lds_elems = std::max(P.lds_elems, peak);
+    auto lds_of = [&](int64_t g, int32_t& out) -> bool {
+      if (in_lam(g)) {
+        out = (int32_t)(g - C.lam_base);
+        return true;
+      }
+      auto it = id.find(g);
+      if (it == id.end() || bufs[it->second].loff < 0) return false;
+      out = (int32_t)bufs[it->second].loff;
+      return true;
+    };
+    for (int32_t o : prog) {
+      OpDesc& d = P.ops[o];
+      d.lds_mask = 0;
+      if (d.kind == OP_CONTRACT) {
+        for (int i = 0; i < d.n_in; ++i)
+          if (lds_of(d.in_off[i], d.lds_off[i])) d.lds_mask |= 1u << i;
+        if (lds_of(d.out_off, d.lds_off[MAXIN])) d.lds_mask |= 1u << MAXIN;
+      } else if (d.kind == OP_RESULT) {
+        const int ns = d.n_in;
+        for (int i = 0; i < 2 * ns; ++i)
+          if (lds_of(d.in_off[i], d.lds_off[i])) d.lds_mask |= 1u << i;
+      }
+    }
+  }
+}
+
 // F_SYNC marks the ops of a cone program that must wait for the whole
 // workgroup before they start, because they read or overwrite data written by
-// an op since the previous barrier.  Independent consecutive ops (e.g. the
-// buckets of unrelated branches of the elimination tree) run without one.
+// an op since the previous barrier, or (LDS-resident cones, where dead buffers
+// are reused) overwrite data read since then.  Independent consecutive ops
+// (e.g. the buckets of unrelated branches of the elimination tree) run
+// without one.
 static void mark_barriers(Plan& P) {
   struct Rng {
+    int space;
     int64_t lo, hi;
   };
-  auto overlaps = [](const std::vector<Rng>& v, int64_t lo, int64_t hi) {
+  auto overlaps = [](const std::vector<Rng>& v, const Rng& x) {
     for (const Rng& r : v)
-      if (lo < r.hi && r.lo < hi) return true;
+      if (r.space == x.space && x.lo < r.hi && r.lo < x.hi) return true;
     return false;
   };
-  auto run = [&](int32_t lo, int32_t hi, std::vector<Rng>& dirty) {
+  auto run = [&](int32_t lo, int32_t hi, bool lds, std::vector<Rng>& dirty, std::vector<Rng>& rdset) {
     for (int32_t o = lo; o < hi; ++o) {
       OpDesc& d = P.ops[o];
       std::vector<Rng> rd, wr;
+      auto opnd = [&](int slot, int64_t goff, int64_t size) -> Rng {
+        if (lds && ((d.lds_mask >> slot) & 1)) return {1, d.lds_off[slot], d.lds_off[slot] + size};
+        return {0, goff, goff + size};
+      };
       if (d.kind == OP_CONTRACT) {
-        for (int i = 0; i < d.n_in; ++i) rd.push_back({d.in_off[i], d.in_off[i] + (int64_t(1) << __builtin_popcount(d.in_mask[i]))});
-        wr.push_back({d.out_off, d.out_off + (int64_t(1) << __builtin_popcount(d.out_mask))});
+        for (int i = 0; i < d.n_in; ++i)
+          rd.push_back(opnd(i, d.in_off[i], int64_t(1) << __builtin_popcount(d.in_mask[i])));
+        wr.push_back(opnd(MAXIN, d.out_off, int64_t(1) << __builtin_popcount(d.out_mask)));
       } else if (d.kind == OP_RESULT) {
-        for (int i = 0; i < d.n_in; ++i) rd.push_back({d.in_off[i], d.in_off[i] + 1});
+        for (int i = 0; i < d.n_in; ++i) rd.push_back(opnd(i, d.in_off[i], 1));
         if (d.flags & F_GRAD)
-          for (int i = 0; i < d.n_in; ++i) wr.push_back({d.in_off[d.n_in + i], d.in_off[d.n_in + i] + 1});
+          for (int i = 0; i < d.n_in; ++i) wr.push_back(opnd(d.n_in + i, d.in_off[d.n_in + i], 1));
       } else if (d.kind == OP_ZERO) {
-        wr.push_back({d.out_off, d.out_off + d.in_off[0]});
+        wr.push_back({0, d.out_off, d.out_off + d.in_off[0]});
       }
       bool need = false;
-      for (const Rng& r : rd) need |= overlaps(dirty, r.lo, r.hi);
-      for (const Rng& r : wr) need |= overlaps(dirty, r.lo, r.hi);
+      for (const Rng& r : rd) need |= overlaps(dirty, r);
+      for (const Rng& r : wr) need |= overlaps(dirty, r) || overlaps(rdset, r);
       if (need) {
         d.flags |= F_SYNC;
         dirty.clear();
+        rdset.clear();
       } else {
         d.flags &= ~F_SYNC;
       }
       dirty.insert(dirty.end(), wr.begin(), wr.end());
+      rdset.insert(rdset.end(), rd.begin(), rd.end());
     }
   };
   for (size_t c = 0; c < P.cones.size(); ++c) {
-    std::vector<Rng> dirty;
-    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1, dirty);  // forward program ends with its result op
+    const bool lds = !P.cone_lds.empty() && P.cone_lds[c];
+    std::vector<Rng> dirty, rdset;
+    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1, lds, dirty, rdset);  // forward program ends with its result op
     dirty.clear();
-    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c], dirty);      // gradient program: forward ops, then the adjoint range
-    run(P.cone_adj_lo[c], P.cone_adj_hi[c], dirty);
+    rdset.clear();
+    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c], lds, dirty, rdset);  // gradient program: forward ops, then the adjoint range
+    run(P.cone_adj_lo[c], P.cone_adj_hi[c], lds, dirty, rdset);
   }
 }
 
@@ -739,7 +876,18 @@ std::string build_programs(Plan& P, int elem_bytes) {
     }
     P.ops.swap(ops);
   }
+  lds_layout(P);
   mark_barriers(P);
+  // copy-in ops of the LDS-resident cones (leaf-product block -> LDS)
+  P.cone_copyin.assign(nc, -1);
+  for (size_t c = 0; c < nc; ++c)
+    if (P.cone_lds[c]) {
+      OpDesc d = blank(OP_COPYIN, (int)c);
+      d.in_off[0] = P.cones[c].lam_base;
+      d.in_off[1] = P.cones[c].lam_size;
+      P.cone_copyin[c] = (int32_t)P.ops.size();
+      P.ops.push_back(d);
+    }
   P.leaf_lo = (int32_t)P.ops.size();
   P.ops.insert(P.ops.end(), leaf_ops.begin(), leaf_ops.end());
   P.leaf_hi = (int32_t)P.ops.size();
@@ -857,6 +1005,13 @@ std::string validate_plan(const Plan& P) {
         return "op " + S(o) + "input range out of bounds";
     if (d.out_off < 0 || d.out_off + (int64_t(1) << __builtin_popcount(d.out_mask)) > P.arena_grad)
       return "op " + S(o) + "output range out of bounds";
+    for (int i = 0; i <= MAXIN; ++i)
+      if ((d.lds_mask >> i) & 1) {
+        const int64_t sz = int64_t(1) << __builtin_popcount(i == MAXIN ? d.out_mask : d.in_mask[i]);
+        if (i != MAXIN && i >= d.n_in) return "op " + S(o) + "LDS bit of a missing input";
+        if (d.lds_off[i] < 0 || d.lds_off[i] + sz > P.lds_elems) return "op " + S(o) + "LDS operand out of the window";
+        if ((d.lds_off[i] & 1) && ((i == MAXIN ? d.out_mask : d.in_mask[i]) & 1)) return "op " + S(o) + "odd LDS pair";
+      }
   }
   return "";
 }
@@ -869,8 +1024,10 @@ void build_items(Plan& P, bool grad) {
   items.clear();
   init.clear();
   succ.clear();
+  // a segment is up to two physical op ranges run in sequence (a cone's
+  // gradient program is its forward range followed by its adjoint range)
   struct Seg {
-    int32_t op_lo, op_hi;
+    int32_t r[4];
     bool wide;
     int64_t nblocks;
   };
@@ -891,24 +1048,38 @@ void build_items(Plan& P, bool grad) {
     } else {
       ranges.push_back({P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1});
     }
-    for (auto& r : ranges) {
-      int32_t open = -1;
-      for (int32_t o = r.first; o < r.second; ++o) {
+    Seg cur{{-1, -1, -1, -1}, false, 1};
+    int nr = 0;  // physical ranges used by the open narrow segment
+    auto close = [&]() {
+      if (nr) segs[c].push_back(cur);
+      cur = Seg{{-1, -1, -1, -1}, false, 1};
+      nr = 0;
+    };
+    for (auto& rg : ranges) {
+      bool open_here = false;
+      for (int32_t o = rg.first; o < rg.second; ++o) {
         const OpDesc& d = P.ops[o];
         const bool wide = d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits;
         if (d.kind == OP_CONTRACT) cost[c] += std::ldexp(1.0, d.nbits) * (d.n_in + 1);
         if (wide) {
-          if (open >= 0) segs[c].push_back({open, o, false, 1});
-          open = -1;
-          segs[c].push_back({o, o + 1, true, int64_t(1) << d.nb});
-        } else if (open < 0) {
-          open = o;
+          close();
+          open_here = false;
+          segs[c].push_back(Seg{{o, o + 1, -1, -1}, true, int64_t(1) << d.nb});
+        } else {
+          if (!open_here) {
+            if (nr == 2) close();
+            cur.r[2 * nr] = o;
+            cur.r[2 * nr + 1] = o + 1;
+            ++nr;
+            open_here = true;
+          } else {
+            cur.r[2 * nr - 1] = o + 1;
+          }
         }
       }
-      if (open >= 0) segs[c].push_back({open, r.second, false, 1});
     }
+    close();
   }
-  // node ids: one per segment
   std::vector<std::vector<int32_t>> node_of(nc);
   int32_t nn = 0;
   for (size_t c = 0; c < nc; ++c) {
@@ -918,7 +1089,6 @@ void build_items(Plan& P, bool grad) {
     }
   }
   init.assign(nn, 0);
-  std::vector<int32_t> nitems_of(nn, 0);
   auto n_items = [&](const Seg& g) -> int32_t {
     if (!g.wide) return 1;
     const int64_t tb = std::max(1, T.tile_blocks);
@@ -941,13 +1111,16 @@ void build_items(Plan& P, bool grad) {
       shi = slo + 1;
     }
     const int32_t wait_node = k.seg > 0 ? node : -1;
+    // a cone that runs LDS-resident is one narrow segment
+    const bool lds = !P.cone_lds.empty() && P.cone_lds[k.cone] && segs[k.cone].size() == 1 && !g.wide;
+    const int32_t cp = lds ? P.cone_copyin[k.cone] : -1;
     if (!g.wide) {
-      items.push_back({g.op_lo, g.op_hi, 0, -1, wait_node, slo, shi, 0});
+      items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, cp, {0, 0}});
     } else {
       const int64_t tb = std::max(1, T.tile_blocks);
       for (int64_t b = 0; b < g.nblocks; b += tb)
-        items.push_back({g.op_lo, g.op_hi, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node, slo,
-                         shi, 0});
+        items.push_back({g.r[0], g.r[1], -1, -1, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node,
+                         slo, shi, -1, {0, 0}});
     }
   }
 }

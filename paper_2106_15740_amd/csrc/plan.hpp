@@ -52,6 +52,7 @@ struct Cone {
   std::vector<int32_t> scalars;   // buckets whose output has rank 0
   // arena layout (element offsets relative to the cone's base)
   std::vector<int64_t> out_off, lam_off, adj_off, lamadj_off;
+  int64_t lam_base = 0, lam_size = 0;  // contiguous block of the leaf-product tables
   int64_t fwd_elems = 0;          // outputs + leaf tables
   int64_t total_elems = 0;        // + adjoint buffers
   double fwd_bytes_alg = 0, bwd_bytes_alg = 0, fwd_flops = 0;
@@ -66,6 +67,7 @@ struct TuneParams {
   int unroll_cap = 1;       // output bits handled inside one thread of a wide op (<= 1)
   int par_bits = 19;        // a wide op aims at >= 2^par_bits threads
   int elem_bytes = 8;       // 8: complex64, 16: complex128 (set by build_programs)
+  int lds_kb = 64;          // LDS window for LDS-resident cones (0: never)
 };
 
 struct Plan {
@@ -81,6 +83,9 @@ struct Plan {
   std::vector<LeafRef> leafrefs;
   int32_t leaf_lo = 0, leaf_hi = 0;    // all OP_LEAF ops (run before the sweep)
   int32_t lgrad_lo = 0, lgrad_hi = 0;  // all OP_LEAFGRAD ops (run after the adjoint sweep)
+  std::vector<char> cone_lds;          // cone runs LDS-resident in the persistent sweep
+  std::vector<int32_t> cone_copyin;    // its OP_COPYIN op (-1: none)
+  int64_t lds_elems = 0;               // largest LDS window needed (elements)
   std::vector<int64_t> cone_base;   // element offset of each cone in the arena
   int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
   // persistent-queue items (forward-only and forward+gradient programs)
