@@ -58,7 +58,7 @@ typedef struct {
   int32_t threads;      /* workgroup size: 64, 128, 256 or 512 */
   int32_t lane_cap;     /* max union bits mapped to the lanes of one sub-block (1..10) */
   int32_t seq_max_bits; /* buckets with more union bits than this are split across workgroups */
-  int32_t tile_blocks;  /* blocks of a split bucket handled by one queue item */
+  int32_t tile_blocks;  /* blocks of a split bucket handled by one queue item (power of two) */
   int32_t loop_cap;     /* summed bits looped inside a thread before partial sums go to atomics */
   int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
   int32_t lds_kb;       /* LDS window (KiB) for light cones that run LDS-resident in the batched sweep (0: none) */

@@ -591,7 +591,8 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (th != 64 && th != 128 && th != 256 && th != 512) return fail(QTN_EINVAL, "threads must be 64, 128, 256 or 512");
   if (t->lane_cap < 1 || t->lane_cap > 10) return fail(QTN_EINVAL, "lane_cap must be in 1..10");
   if (t->seq_max_bits < 1 || t->seq_max_bits > 31) return fail(QTN_EINVAL, "seq_max_bits must be in 1..31");
-  if (t->tile_blocks < 1) return fail(QTN_EINVAL, "tile_blocks must be >= 1");
+  if (t->tile_blocks < 1 || (t->tile_blocks & (t->tile_blocks - 1)))
+    return fail(QTN_EINVAL, "tile_blocks must be a power of two");
   if (t->loop_cap < 0 || t->loop_cap > 31) return fail(QTN_EINVAL, "loop_cap must be in 0..31");
   if (t->grid < 0) return fail(QTN_EINVAL, "grid must be >= 0");
   if (t->lds_kb < 0 || t->lds_kb > 128) return fail(QTN_EINVAL, "lds_kb must be in 0..128");
@@ -615,10 +616,10 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
   qtn_tuning base;
   qtn_get_tuning(n, &base);
   std::vector<qtn_tuning> cand;
-  for (int th : {128, 256, 512})
+  for (int th : {64, 128, 256, 512})
     for (int lc : {6, 7, 8})
-      for (int sq : {14, 16, 18})
-        for (int tb : {4, 16}) {
+      for (int sq : {12, 14, 16})
+        for (int tb : {16, 64}) {
           if ((1 << lc) > th) continue;
           qtn_tuning t = base;
           t.threads = th;

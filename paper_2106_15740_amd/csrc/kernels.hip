@@ -129,14 +129,21 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
       inp[i] = ((d.lds_mask >> i) & 1u) ? lds + d.lds_off[i] : arena + d.in_off[i];
     else
       inp[i] = arena + d.in_off[i];
+    // lane offset: the strides of the lane bits are distinct powers of two
     uint32_t o = 0;
-    for (int j = 0; j < nl; ++j)
-      if ((lane >> j) & 1) o += bit_stride(mask[i], d.zbit[j]);
+#pragma unroll
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl && sh != LSH_NONE) o |= ((uint32_t)(lane >> j) & 1u) << sh;
+    }
     loff[i] = o;
   }
   uint32_t lout = 0;
-  for (int j = 0; j < nl; ++j)
-    if ((lane >> j) & 1) lout += bit_stride(out_mask, d.zbit[j]);
+#pragma unroll
+  for (int j = 0; j < MAXLANE; ++j) {
+    const uint32_t sh = d.lsh[MAXIN][j];
+    if (j < nl && sh != LSH_NONE) lout |= ((uint32_t)(lane >> j) & 1u) << sh;
+  }
   uint32_t us0[NIN];
 #pragma unroll
   for (int i = 0; i < NIN; ++i) us0[i] = (MAXU > 1 && nu > 0) ? bit_stride(mask[i], d.zbit[nl]) : 0u;
@@ -152,16 +159,20 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
   const int nb = d.nb;
   const int64_t nloop = int64_t(1) << nk;
 
-  // workgroup steps and chunks (all powers of two)
-  const int64_t nblk = blk_end - blk_begin;
-  const int64_t steps = (nblk + nsub - 1) >> sbits;
-  int64_t chunk = steps / wg_count;
-  chunk = chunk < 1 ? 1 : (int64_t(1) << (63 - __clzll((unsigned long long)chunk)));
-  const int64_t nchunks = (steps + chunk - 1) / chunk;
+  // workgroup steps and chunks: the block range (2^nb blocks, or an aligned
+  // power-of-two tile of them) and wg_count are powers of two
+  const int32_t nblk = (int32_t)(blk_end - blk_begin);
+  const int lg_nblk = 31 - __clz(nblk);
+  const int lg_st = lg_nblk > sbits ? lg_nblk - sbits : 0;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int64_t chunk = int64_t(1) << lg_chunk;
+  const int64_t steps = int64_t(1) << lg_st;
+  const int64_t nchunks = steps >> lg_chunk;
 
 #pragma unroll 1
   for (int64_t ch = wg_rank; ch < nchunks; ch += wg_count) {
-    const int64_t q0 = ch * chunk;
+    const int64_t q0 = ch << lg_chunk;
     int64_t blk = blk_begin + (q0 << sbits) + sub;
     bool valid = blk < blk_end;
     uint32_t boff[NIN];
@@ -170,13 +181,15 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
     uint32_t bout = lout;
     {
       const int64_t b = valid ? blk : blk_begin;
-      for (int j = 0; j < nb; ++j)
-        if ((b >> j) & 1) {
-          const uint32_t u = d.zbit[zb0 + j];
+      if (b) {
+        for (int j = 0; j < nb; ++j)
+          if ((b >> j) & 1) {
+            const uint32_t u = d.zbit[zb0 + j];
 #pragma unroll
-          for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
-          bout += bit_stride(out_mask, u);
-        }
+            for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+            bout += bit_stride(out_mask, u);
+          }
+      }
     }
 #pragma unroll 1
     for (int64_t c = 0; c < chunk; ++c) {
@@ -646,8 +659,9 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
     grid = (h.in_off[0] + threads - 1) / threads;
   }
   if (grid > max_grid) grid = max_grid;
-  if (grid > 8) grid = grid / 8 * 8;
   if (grid < 1) grid = 1;
+  // a power of two: the contraction executor splits its blocks by shifts
+  grid = int64_t(1) << (63 - __builtin_clzll((unsigned long long)grid));
   const dim3 g((unsigned)grid), b(threads);
   if (h.kind != OP_CONTRACT) {
     hipLaunchKernelGGL((misc_kernel<R>), g, b, 0, st, d_ops, op, env);

@@ -7,6 +7,8 @@ namespace qtn {
 
 constexpr int MAXIN = 8;     // tensor inputs of one contraction op
 constexpr int MAXBITS = 31;  // union bits of one bucket (output rank <= 30)
+constexpr int MAXLANE = 10;  // lane bits of one op
+constexpr uint8_t LSH_NONE = 0xff;
 
 enum OpKind : int32_t {
   OP_CONTRACT = 0,  // out[pext(u,out)] (+)= sum over unmasked bits of prod_i in_i[pext(u,mask_i)]
@@ -50,8 +52,13 @@ struct alignas(16) OpDesc {
   // at LDS element offset lds_off[i] when bit i of lds_mask is set
   uint32_t lds_mask;
   int32_t lds_off[MAXIN + 1];
-  int32_t pad_[2];
+  // lane offsets without bit arithmetic on the device: for operand i (output:
+  // MAXIN) and lane bit j < nl, the element stride is 1 << lsh[i][j], or 0
+  // when lsh[i][j] == LSH_NONE
+  uint8_t lsh[MAXIN + 1][MAXLANE];
+  uint8_t pad_[14];
 };
+static_assert(sizeof(OpDesc) % 16 == 0, "OpDesc is copied in 16-byte words");
 
 struct LeafRef {
   int16_t kind;

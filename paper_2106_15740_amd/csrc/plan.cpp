@@ -432,7 +432,7 @@ struct Ctx {
 void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T) {
   std::vector<int> freeb, sumb;
   for (int u = 1; u < nbits; ++u) ((out_mask >> u) & 1 ? freeb : sumb).push_back(u);
-  const int max_lanes = std::min(T.lane_cap, 31 - __builtin_clz((unsigned)std::max(T.threads, 1)));
+  const int max_lanes = std::min({T.lane_cap, MAXLANE, 31 - __builtin_clz((unsigned)std::max(T.threads, 1))});
   std::vector<int> lanes, unroll, loop, blocks;
   size_t fi = 0, si = 0;
   // lanes: the lowest output bits (coalesced stores and, since every tensor
@@ -496,6 +496,14 @@ void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const Tun
   for (int u : blocks) d.zbit[z++] = (uint8_t)u;
   for (; z < 32; ++z) d.zbit[z] = 0;
   d.flags = (atomic ? F_ATOMIC : 0) | ((d.lane_sum >> 6) ? F_LDSRED : 0);
+  auto lshift = [](uint32_t m, uint32_t u) -> uint8_t {
+    return ((m >> u) & 1u) ? (uint8_t)__builtin_popcount(m & ((1u << u) - 1u)) : LSH_NONE;
+  };
+  for (int i = 0; i <= MAXIN; ++i)
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t m = i == MAXIN ? out_mask : (i < d.n_in ? d.in_mask[i] : 0u);
+      d.lsh[i][j] = j < d.nl ? lshift(m, d.zbit[j]) : LSH_NONE;
+    }
 }
 
 OpDesc blank(int kind, int cone) {
@@ -1005,6 +1013,15 @@ std::string validate_plan(const Plan& P) {
         return "op " + S(o) + "input range out of bounds";
     if (d.out_off < 0 || d.out_off + (int64_t(1) << __builtin_popcount(d.out_mask)) > P.arena_grad)
       return "op " + S(o) + "output range out of bounds";
+    for (int i = 0; i <= MAXIN; ++i) {
+      if (i < MAXIN && i >= d.n_in) continue;
+      const uint32_t m = i == MAXIN ? d.out_mask : d.in_mask[i];
+      for (int j = 0; j < MAXLANE; ++j) {
+        const uint32_t st = j < d.nl && ((m >> d.zbit[j]) & 1) ? (1u << __builtin_popcount(m & ((1u << d.zbit[j]) - 1))) : 0u;
+        const uint32_t got = d.lsh[i][j] == LSH_NONE ? 0u : (1u << d.lsh[i][j]);
+        if (st != got) return "op " + S(o) + "lane shift table mismatch";
+      }
+    }
     for (int i = 0; i <= MAXIN; ++i)
       if ((d.lds_mask >> i) & 1) {
         const int64_t sz = int64_t(1) << __builtin_popcount(i == MAXIN ? d.out_mask : d.in_mask[i]);
