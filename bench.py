@@ -1,20 +1,25 @@
 """Benchmark: QAOA-MaxCut light cones per second (energy + gradient), p = 3.
 
-Workload: seeded random 3-regular graph, N = 244 vertices (366 edges), QAOA
-depth p = 3, angles ~ U(0, pi), complex64 with FP32 accumulation, min-fill
-order.  One step = one forward sweep of every edge's light-cone network plus
-the adjoint sweep (energy and dE/dgamma, dE/dbeta), in the batched form: one
-persistent launch over a device work queue, replayed from a hipGraph.  Inputs
-(plan and leaf tables) are resident in HBM before timing starts; each step
-re-uploads the 4p+2 leaf values (a few hundred bytes) as the sweep's first node.
+Headline workload: seeded random 3-regular graph, N = 244 vertices (366
+edges), QAOA depth p = 3, angles ~ U(0, pi), complex64 with FP32 accumulation,
+min-fill randomized greedy order (10 repeats).  One step = one forward sweep of
+every edge's light-cone network plus the adjoint sweep (energy, dE/dgamma,
+dE/dbeta) in the batched form: one persistent launch over a device work
+queue, replayed from a hipGraph, tile shapes from the library's autotuner.
+The plan and leaf tables are resident in HBM before timing starts; each step
+re-uploads the 4p+2 leaf values (a few hundred bytes) as the sweep's first
+node and reads back 1 + 2p doubles.
 
-Prints one JSON line.  Also reported: the plain per-edge loop (one launch per
-bucket step) on the same GPU, the roofline of the persistent kernel, and the
+Prints one JSON line.  Beside the headline it reports: the plain per-edge
+loop (one launch per bucket step) on the same GPU; the roofline of the
+persistent kernel; the p = 5, N = 1000 workload (throughput, HBM fraction of
+the whole sweep and of its buckets of width >= 20 timed one by one); and the
 CPU oracle timed on a bounded sample of edges.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +29,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_persistent_kernel_p3_n244.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "plan.cpp", "opdesc.hpp"):
+        with open(os.path.join(ROOT, "paper_2106_15740_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs, only while the kernel sources are the ones they were taken with."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(w, budget_s: float = 15.0):
@@ -31,6 +58,7 @@ def cpu_baseline(w, budget_s: float = 15.0):
     edge terms with the gradient by central differences (4p + 1 contractions
     per edge, the oracle as it stands), one process per host core."""
     import concurrent.futures as cf
+    import multiprocessing as mp
 
     import numpy as np
 
@@ -39,19 +67,13 @@ def cpu_baseline(w, budget_s: float = 15.0):
     order = rng.permutation(len(w.edges))
     p = w.p
     h = 1e-4
-
-    def job_args(e):
-        return (w.n, w.edges, w.gamma, w.beta, w.edges[e], h)
-
     t0 = time.perf_counter()
     done = 0
-    import multiprocessing as mp
-
     with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
-        futs = []
         i = 0
         while i < len(order) and (time.perf_counter() - t0) < budget_s:
-            batch = [ex.submit(_oracle_edge_grad, *job_args(int(e))) for e in order[i:i + cores]]
+            batch = [ex.submit(_oracle_edge_grad, w.n, w.edges, w.gamma, w.beta, w.edges[int(e)], h)
+                     for e in order[i:i + cores]]
             for f in batch:
                 f.result()
             done += len(batch)
@@ -82,21 +104,82 @@ def _oracle_edge_grad(n, edges, gamma, beta, edge, h):
     return z
 
 
+def time_sweeps(net, steps: int, warmup: int, mode: str = "batched"):
+    """Wall time of `steps` energy + gradient sweeps bracketed by device
+    synchronisation, the last energy, and the average device time of the graph
+    replay (HIP events on the launch stream)."""
+    import torch
+
+    for _ in range(warmup):
+        net.energy_grad(mode)
+    net.kernel_time(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e, _, _ = net.energy_grad(mode)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_cnt = net.kernel_time(reset=True)
+    return dt, e, k_ms / max(k_cnt, 1), k_cnt
+
+
+def wide_leg(repeats: int, steps: int):
+    """p = 5, N = 1000 (1500 edges), c64: the HBM-bound workload."""
+    import torch
+
+    from paper_2106_15740_amd import QaoaNet
+    from workloads import workload
+
+    w = workload("p5_n1000")
+    t0 = time.perf_counter()
+    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=0, repeats=repeats)
+    plan_s = time.perf_counter() - t0
+    net.set_tuning(seq_max_bits=14, tile_blocks=64)
+    net.set_params(w.gamma, w.beta)
+    info = net.info()
+    dt, e, k_ms, _ = time_sweeps(net, steps, 1)
+    alg = info["fwd_bytes"] + info["bwd_bytes"]
+    wb, wms, wn = net.time_wide_ops(min_width=20, with_grad=True, reps=2)
+    out = {
+        "workload": f"QAOA-MaxCut p=5, random 3-regular N=1000 (1500 edges), c64, min-fill randomized greedy "
+                    f"({repeats} repeats), batched energy + gradient",
+        "edge_light_cones_per_s": len(w.edges) * steps / dt,
+        "ms_per_step": 1e3 * dt / steps,
+        "max_width": info["max_width"],
+        "alg_bytes_per_sweep": alg,
+        "achieved_GBps": alg / (k_ms * 1e-3) / 1e9,
+        "frac_of_peak": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "width_ge_20": {"ops": wn, "alg_bytes": wb, "ms": wms,
+                        "achieved_GBps": (wb / (wms * 1e-3) / 1e9) if wms else None,
+                        "frac_of_peak": (wb / (wms * 1e-3) / 1e9 / HBM_PEAK_GBS) if wms else None,
+                        "method": "each contraction op of a bucket with output rank >= 20 launched alone, "
+                                  "2 replays between HIP events"},
+        "energy": e,
+        "plan_s": plan_s,
+    }
+    del net
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="p3_n244")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--repeats", type=int, default=10,
                     help="randomized greedy order: runs per cone on top of the deterministic one (0: deterministic)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--no-wide", action="store_true", help="skip the p=5 N=1000 leg")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the light-cone sweep is not sharded across GPUs in this "
-              "build (see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+              "build (DESIGN.md describes how it would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from workloads import workload
@@ -113,37 +196,25 @@ def main():
     net = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=w.order, device=0, repeats=args.repeats)
     plan_s = time.perf_counter() - t0
     net.set_params(w.gamma, w.beta)
+    tuned = net.tuning() if args.no_autotune else net.autotune(with_grad=True)
     info = net.info()
-    tuned = net.autotune(with_grad=True) if args.autotune else net.tuning()
-    stream = torch.cuda.current_stream()
 
-    # warm-up (also captures the hipGraph)
-    for _ in range(args.warmup):
-        net.energy_grad("batched")
-    net.kernel_time(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e, dg, db = net.energy_grad("batched")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    k_ms, k_cnt = net.kernel_time(reset=True)
+    dt, e, k_avg_ms, k_cnt = time_sweeps(net, args.steps, args.warmup)
     ms_step = 1e3 * dt / args.steps
     cones_per_s = len(w.edges) * args.steps / dt
 
-    # plain per-edge loop (one launch per bucket step), same GPU
     plain_ms = None
     if args.plain_steps > 0:
-        net.energy_grad("plain")
+        pdt, _, _, _ = time_sweeps(net, args.plain_steps, 1, mode="plain")
+        plain_ms = 1e3 * pdt / args.plain_steps
+
+    if args.copy_mb > 0:
+        x = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            net.energy_grad("plain")
-        torch.cuda.synchronize()
-        plain_ms = 1e3 * (time.perf_counter() - t0) / args.plain_steps
 
     alg_bytes = info["fwd_bytes"] + info["bwd_bytes"]
-    k_avg_ms = k_ms / max(k_cnt, 1)
     achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9 if k_cnt else None
     out = {
         "metric": "edge light-cones/sec (energy+grad) & HBM GB/s vs plain loop, 3-regular p=3",
@@ -159,15 +230,17 @@ def main():
         "dtype": "c64 (fp32 accumulate)" if w.dtype == "c64" else "c128",
         "data": "synthetic: seeded random 3-regular graph, angles ~ U(0, pi)",
         "config": {"workload": f"QAOA-MaxCut p={w.p}, random 3-regular N={w.n} ({len(w.edges)} edges), "
-                               f"{w.dtype}, {w.order.replace('_', '-')} order, batched persistent sweep "
-                               f"(energy + gradient)",
+                               f"{w.dtype}, {w.order.replace('_', '-')} randomized greedy order "
+                               f"({args.repeats} repeats), batched persistent sweep (energy + gradient)",
                    "n_vertices": w.n, "n_edges": len(w.edges), "p": w.p, "order": w.order,
                    "repeats": args.repeats, "max_width": info["max_width"], "buckets": info["n_buckets"],
                    "lds_resident_cones": info["n_lds_cones"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(),
                      "kernel": "persistent_kernel", "kernel_ms": k_avg_ms,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "note": "p=3 sweeps are cache- and LDS-resident: latency-bound, not HBM-bound"},
         "plain_loop": None if plain_ms is None else {
             "ms_per_step": plain_ms, "edge_light_cones_per_s": len(w.edges) / (plain_ms * 1e-3),
             "speedup_batched_vs_plain": plain_ms / ms_step},
@@ -175,6 +248,10 @@ def main():
         "plan_s": plan_s,
         "tuning": tuned,
     }
+    if not args.no_wide:
+        del net
+        torch.cuda.empty_cache()
+        out["wide"] = wide_leg(args.repeats, steps=3)
     if cpu is not None:
         cpu["gpu_speedup"] = cones_per_s / cpu["value"]
         out["cpu_baseline"] = cpu

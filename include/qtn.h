@@ -168,6 +168,16 @@ qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t
  * stream around the replay; and the number of such sweeps. */
 qtn_status qtn_kernel_time(qtn_net* net, double* ms_sum, int64_t* count, int32_t reset);
 
+/* Times the contraction ops of buckets whose output rank is >= min_width
+ * (forward and, with with_grad, adjoint ops) one launch at a time on
+ * `stream`, each replayed `reps` times between HIP events, reading the tensors
+ * left in `workspace` by the last sweep of the same kind (atomic adjoint
+ * outputs accumulate, so run a sweep again before reading results).  Returns
+ * the algorithmic bytes of those ops (each input read once, output written
+ * once; per replay) and their summed average device time. */
+qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width, void* workspace, size_t ws_bytes,
+                             void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out);
+
 void qtn_net_free(qtn_net* net);
 
 #ifdef __cplusplus

@@ -661,6 +661,51 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
   return s;
 }
 
+qtn_status qtn_time_wide_ops(qtn_net* n, int32_t with_grad, int32_t min_width, void* ws, size_t ws_bytes,
+                             void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out) {
+  qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
+  if (s != QTN_OK) return s;
+  if (reps < 1) reps = 1;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  const WsLayout L = ws_layout(n, with_grad != 0);
+  Env env = make_env(n, static_cast<char*>(ws), L);
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  double bytes = 0, ms_tot = 0;
+  int64_t cnt = 0;
+  (void)hipGetLastError();
+  for (size_t c = 0; c < n->P.cones.size() && s == QTN_OK; ++c) {
+    std::vector<std::pair<int32_t, int32_t>> ranges = {{n->P.cone_fwd_lo[c], n->P.cone_fwd_hi[c]}};
+    if (with_grad) ranges.push_back({n->P.cone_adj_lo[c], n->P.cone_adj_hi[c]});
+    for (auto& r : ranges)
+      for (int32_t o = r.first; o < r.second; ++o) {
+        const OpDesc& d = n->P.ops[o];
+        if (d.kind != OP_CONTRACT || d.nbits - 1 < min_width) continue;
+        double b = std::ldexp(1.0, __builtin_popcount(d.out_mask));
+        for (int i = 0; i < d.n_in; ++i) b += std::ldexp(1.0, __builtin_popcount(d.in_mask[i]));
+        b *= n->elem;
+        HIPCHECK(launch_op(n->c128, n->d_ops, d, o, env, n->P.tune.threads, 4096, st));  // warm
+        HIPCHECK(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) HIPCHECK(launch_op(n->c128, n->d_ops, d, o, env, n->P.tune.threads, 4096, st));
+        HIPCHECK(hipEventRecord(e1, st));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        bytes += b;
+        ms_tot += ms / reps;
+        ++cnt;
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (bytes_out) *bytes_out = bytes;
+  if (ms_out) *ms_out = ms_tot;
+  if (n_ops_out) *n_ops_out = cnt;
+  return QTN_OK;
+}
+
 qtn_status qtn_kernel_time(qtn_net* n, double* ms_sum, int64_t* count, int32_t reset) {
   if (!n) return fail(QTN_EINVAL, "net is NULL");
   if (ms_sum) *ms_sum = n->kernel_ms_sum;

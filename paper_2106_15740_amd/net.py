@@ -189,6 +189,16 @@ class QaoaNet:
                                        self._stream(), int(reps), C.byref(t)))
         return t.as_dict()
 
+    def time_wide_ops(self, min_width: int = 20, with_grad: bool = True, reps: int = 2) -> Tuple[float, float, int]:
+        """(algorithmic bytes, device ms, op count) of the contraction ops whose
+        output rank is >= min_width, each launched alone (after a sweep)."""
+        ws = self._workspace(with_grad)
+        b, ms, n = C.c_double(), C.c_double(), C.c_int64()
+        L.check(self._lib.qtn_time_wide_ops(self.handle, int(bool(with_grad)), int(min_width),
+                                            C.c_void_p(ws.data_ptr()), ws.numel(), self._stream(), int(reps),
+                                            C.byref(b), C.byref(ms), C.byref(n)))
+        return b.value, ms.value, n.value
+
     def kernel_time(self, reset: bool = False) -> Tuple[float, int]:
         ms = C.c_double()
         cnt = C.c_int64()
