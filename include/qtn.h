@@ -79,6 +79,9 @@ typedef struct {
   size_t ws_fwd, ws_grad;   /* workspace bytes: forward only / forward + gradient */
   int32_t n_lds_cones;      /* light cones that run LDS-resident in the batched sweep */
   int32_t lds_window;       /* bytes of LDS window each persistent workgroup reserves for them */
+  int64_t n_recomputed;     /* bucket outputs dropped after the forward sweep and recomputed in the adjoint */
+  double rec_bytes;         /* extra bytes of those recomputations per gradient sweep (not algorithmic) */
+  size_t arena_keep_all;    /* arena bytes the gradient sweep would need keeping every output */
 } qtn_info;
 
 /* Context bound to HIP device `device` (hipSetDevice is called on it).  Owns a
@@ -114,7 +117,8 @@ qtn_status qtn_order_rgreedy(qtn_net* net, qtn_order_kind kind, int32_t n_repeat
                              uint64_t seed, int32_t* max_width_out);
 
 /* Bytes of device workspace that qtn_contract (with_grad = 0) or
- * qtn_energy_grad (with_grad = 1) need. */
+ * qtn_energy_grad (with_grad = 1) need.  Buffers share memory by lifetime, so
+ * both sweeps use the same arena. */
 qtn_status qtn_workspace_size(const qtn_net* net, int32_t with_grad, size_t* bytes_out);
 
 /* gamma[p], beta[p] (host, float64, finite).  Leaf tensor values are computed
@@ -151,6 +155,15 @@ qtn_status qtn_cone_stats(const qtn_net* net, int32_t* width, int32_t* n_qubits,
  * consistent with the union sets, widths, arena ranges disjoint and in bounds).
  * QTN_OK or QTN_EINVAL with the first violation in qtn_last_error(). */
 qtn_status qtn_validate_plan(const qtn_net* net);
+
+/* Checkpointed adjoint: limit the workspace to about `bytes` (0: no limit).
+ * While the arena does not fit, the largest bucket output of the largest light
+ * cone whose producer reads only kept outputs is dropped after the forward
+ * sweep and recomputed by the adjoint sweep right before it is needed
+ * (results are unchanged; qtn_info reports the extra traffic).  QTN_ENOMEM
+ * (and no limit) when even full recomputation cannot meet it.  Rebuilds and
+ * re-uploads the device program. */
+qtn_status qtn_set_memory_budget(qtn_net* net, size_t bytes);
 
 /* Tile parameters; changing them rebuilds and re-uploads the device program. */
 qtn_status qtn_get_tuning(const qtn_net* net, qtn_tuning* out);

@@ -21,7 +21,7 @@ EXPORTS = [
     "qtn_workspace_size",
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
-    "qtn_kernel_time", "qtn_time_wide_ops", "qtn_net_free",
+    "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_net_free",
 ]
 
 
@@ -45,7 +45,8 @@ class Info(C.Structure):
                 ("n_buckets", C.c_int64), ("n_ops_fwd", C.c_int64), ("n_ops_grad", C.c_int64),
                 ("n_items_fwd", C.c_int64), ("n_items_grad", C.c_int64), ("fwd_bytes", C.c_double),
                 ("bwd_bytes", C.c_double), ("fwd_flops", C.c_double), ("ws_fwd", C.c_size_t),
-                ("ws_grad", C.c_size_t), ("n_lds_cones", C.c_int32), ("lds_window", C.c_int32)]
+                ("ws_grad", C.c_size_t), ("n_lds_cones", C.c_int32), ("lds_window", C.c_int32),
+                ("n_recomputed", C.c_int64), ("rec_bytes", C.c_double), ("arena_keep_all", C.c_size_t)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -83,6 +84,7 @@ def lib() -> C.CDLL:
         "qtn_set_tuning": (I32, [P, C.POINTER(Tuning)]),
         "qtn_autotune": (I32, [P, I32, P, SZ, P, I32, C.POINTER(Tuning)]),
         "qtn_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64), I32]),
+        "qtn_set_memory_budget": (I32, [P, SZ]),
         "qtn_time_wide_ops": (I32, [P, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)]),
         "qtn_net_free": (None, [P]),
     }

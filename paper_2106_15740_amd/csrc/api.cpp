@@ -381,7 +381,6 @@ qtn_status qtn_order_rgreedy(qtn_net* n, qtn_order_kind kind, int32_t n_repeats,
     O.temperature = temperature;
     O.seed = seed;
     order_cones(n->P, O, (int)std::max(1u, std::min(hw, 16u)));
-    layout_cones(n->P);
     if (n->P.max_width > MAXBITS - 1)
       return fail(QTN_EUNSUPPORTED, "contraction width " + std::to_string(n->P.max_width) + " exceeds 30");
     qtn_status s = rebuild_programs(n);
@@ -554,6 +553,11 @@ qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
   out->ws_grad = ws_layout(n, true).total;
   for (char l : n->P.cone_lds) out->n_lds_cones += l ? 1 : 0;
   out->lds_window = (int32_t)(n->P.lds_elems * n->elem);
+  for (const Cone& C : n->P.cones) {
+    for (char r : C.recompute) out->n_recomputed += r ? 1 : 0;
+    out->rec_bytes += C.rec_bytes;
+    out->arena_keep_all += (size_t)C.keep_all_elems * n->elem;
+  }
   return QTN_OK;
 }
 
@@ -715,6 +719,19 @@ qtn_status qtn_kernel_time(qtn_net* n, double* ms_sum, int64_t* count, int32_t r
     n->kernel_count = 0;
   }
   return QTN_OK;
+}
+
+qtn_status qtn_set_memory_budget(qtn_net* n, size_t bytes) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  n->P.mem_budget = (int64_t)(bytes / (size_t)n->elem);
+  if (!n->P.ordered) return QTN_OK;
+  qtn_status s = rebuild_programs(n);
+  if (s == QTN_EUNSUPPORTED) {  // the builder reports an unreachable budget this way
+    n->P.mem_budget = 0;
+    (void)rebuild_programs(n);
+    return fail(QTN_ENOMEM, "memory budget of " + std::to_string(bytes) + " bytes cannot be met");
+  }
+  return s;
 }
 
 qtn_status qtn_validate_plan(const qtn_net* n) {

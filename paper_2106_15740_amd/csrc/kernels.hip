@@ -599,15 +599,66 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
   }
 }
 
-// Independent small ops of every cone in one launch: the leaf-product tables
-// before a sweep, the leaf gradients after the adjoint sweep.  One workgroup
-// per op.
+// Leaf-product tables (OP_LEAF) and leaf gradients (OP_LEAFGRAD) of every
+// cone, one wavefront per op: the tables have a few to a few hundred entries,
+// so a whole workgroup per op would idle.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
 template <typename R>
-__global__ void __launch_bounds__(512) batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env) {
-  __shared__ RedBuf<typename CT<R>::E> red;
-  for (int op = lo + blockIdx.x; op < hi; op += gridDim.x) {
-    exec_op<R, 1>(ops[op], env, 0, 1, 0, 1, &red);
-    __syncthreads();
+__global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env) {
+  using E = typename CT<R>::E;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+  const E* vals = reinterpret_cast<const E*>(env.leafvals);
+  const E* dvals = reinterpret_cast<const E*>(env.dleafvals);
+  E* arena = reinterpret_cast<E*>(env.arena);
+  for (int op = lo + wave; op < hi; op += nwaves) {
+    const OpDesc& d = ops[op];
+    const int64_t n = int64_t(1) << d.nbits;
+    const LeafRef* refs = env.leafrefs + d.aux0;
+    if (d.kind == OP_LEAF) {
+      E* out = arena + d.out_off;
+      for (int64_t e = lane; e < n; e += 64) {
+        E pr = {1, 0};
+        for (int r = 0; r < d.aux1; ++r) {
+          const LeafRef L = refs[r];
+          int idx = (e >> L.pa) & 1;
+          if (L.pb >= 0) idx |= ((e >> L.pb) & 1) << 1;
+          pr = cmul(pr, vals[L.kind * 4 + idx]);
+        }
+        out[e] = pr;
+      }
+    } else if (d.kind == OP_LEAFGRAD) {
+      // dR/dtheta += sum_e Lbar[e] * (derivative of one leaf) * (the other leaves)
+      const E* lbar = arena + d.in_off[0];
+      double* res = env.res + (int64_t)d.cone * env.res_stride;
+      for (int r = 0; r < d.aux1; ++r) {
+        const int slot = theta_slot(refs[r].kind, env.p);
+        if (slot < 0) continue;  // uniform across the wavefront
+        double ax = 0, ay = 0;
+        for (int64_t e = lane; e < n; e += 64) {
+          E t = lbar[e];
+          for (int q = 0; q < d.aux1; ++q) {
+            const LeafRef Ls = refs[q];
+            int idx = (e >> Ls.pa) & 1;
+            if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
+            t = cmul(t, q == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
+          }
+          ax += (double)t.x;
+          ay += (double)t.y;
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if (lane == 0) {
+          atomicAdd(res + slot, ax);
+          atomicAdd(res + slot + 1, ay);
+        }
+      }
+    }
   }
 }
 
@@ -688,12 +739,13 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
 }
 
 hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st) {
+  (void)threads;
   if (hi <= lo) return hipSuccess;
-  const int grid = std::min(hi - lo, 8192);
+  const int grid = std::min((hi - lo + 3) / 4, 4096);  // 4 wavefronts per workgroup, one op each
   if (c128)
-    hipLaunchKernelGGL(batch_kernel<double>, dim3(grid), dim3(threads), 0, st, d_ops, lo, hi, env);
+    hipLaunchKernelGGL(leaf_batch_kernel<double>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env);
   else
-    hipLaunchKernelGGL(batch_kernel<float>, dim3(grid), dim3(threads), 0, st, d_ops, lo, hi, env);
+    hipLaunchKernelGGL(leaf_batch_kernel<float>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env);
   return hipGetLastError();
 }
 

@@ -367,57 +367,6 @@ static int64_t align_elems(int64_t off, int64_t size) {
   return (off + a - 1) / a * a;
 }
 
-void layout_cones(Plan& P) {
-  // forward region of every cone first, then every cone's adjoint region, so a
-  // forward-only sweep needs only the first part of the arena.
-  int64_t off = 0;
-  P.cone_base.assign(P.cones.size(), 0);
-  for (size_t c = 0; c < P.cones.size(); ++c) {
-    Cone& C = P.cones[c];
-    const size_t nb = C.buckets.size();
-    C.out_off.assign(nb, -1);
-    C.lam_off.assign(nb, -1);
-    C.adj_off.assign(nb, -1);
-    C.lamadj_off.assign(nb, -1);
-    // the cone's leaf-product tables form one contiguous block (copied into
-    // LDS as a whole when the cone runs LDS-resident)
-    off = align_elems(off, 64);
-    C.lam_base = off;
-    for (size_t b = 0; b < nb; ++b)
-      if (C.buckets[b].lam_mask) {
-        int64_t sl = int64_t(1) << C.buckets[b].lam_rank();
-        off = align_elems(off, sl);
-        C.lam_off[b] = off;
-        off += sl;
-      }
-    C.lam_size = off - C.lam_base;
-    for (size_t b = 0; b < nb; ++b) {
-      int64_t sz = int64_t(1) << C.buckets[b].out_rank();
-      off = align_elems(off, sz);
-      C.out_off[b] = off;
-      off += std::max<int64_t>(sz, 2);
-    }
-  }
-  P.arena_fwd = align_elems(off, 64);
-  off = P.arena_fwd;
-  for (size_t c = 0; c < P.cones.size(); ++c) {
-    Cone& C = P.cones[c];
-    for (size_t b = 0; b < C.buckets.size(); ++b) {
-      int64_t sz = int64_t(1) << C.buckets[b].out_rank();
-      off = align_elems(off, sz);
-      C.adj_off[b] = off;
-      off += std::max<int64_t>(sz, 2);
-      if (C.buckets[b].lam_mask) {
-        int64_t sl = int64_t(1) << C.buckets[b].lam_rank();
-        off = align_elems(off, sl);
-        C.lamadj_off[b] = off;
-        off += sl;
-      }
-    }
-  }
-  P.arena_grad = align_elems(off, 64);
-}
-
 // ---------------------------------------------------------------- op programs
 namespace {
 
@@ -517,14 +466,15 @@ OpDesc blank(int kind, int cone) {
 }  // namespace
 
 // LDS-resident cones: when every op of a cone's program fits one workgroup,
-// its tensors can live in LDS for the whole persistent sweep.  Lifetimes are
-// taken over the gradient program (forward ops, result, adjoint ops), which
-// covers the forward-only program too; buffers are placed first-fit by
-// definition time.  The leaf-product block sits at LDS offset 0 for the whole
-// program.  The adjoints of the leaf tables stay in global memory (the leaf
-// gradients are batched after the sweep).  Ops keep their global offsets for
-// the plain per-op path; lds_off/lds_mask are used only by the persistent
-// kernel in items flagged as LDS-resident.
+// its tensors can live in LDS for the whole persistent sweep.  Works on the
+// programs while their operands still hold buffer codes: lifetimes are taken
+// over the gradient program (which covers the forward-only program too) and
+// buffers are placed first-fit by definition time.  The leaf-product block
+// sits at LDS offset 0, laid out as in the arena.  The adjoints of the leaf
+// tables stay in global memory (the leaf gradients are batched after the
+// sweep).  Ops keep their global offsets for the plain per-op path;
+// lds_off/lds_mask are used only by the persistent kernel in items flagged as
+// LDS-resident.
 static void lds_layout(Plan& P) {
   const TuneParams& T = P.tune;
   const int64_t budget = (int64_t)T.lds_kb * 1024 / std::max(1, T.elem_bytes);
@@ -536,63 +486,56 @@ static void lds_layout(Plan& P) {
     std::vector<int32_t> prog;
     for (int32_t o = P.cone_fwd_lo[c]; o <= P.cone_fwd_hi[c]; ++o) prog.push_back(o);  // includes forward result
     for (int32_t o = P.cone_adj_lo[c]; o < P.cone_adj_hi[c]; ++o) prog.push_back(o);
-    bool ok = true;
+    bool ok = C.lam_size <= budget;
     for (int32_t o : prog) {
       const OpDesc& d = P.ops[o];
       if (d.kind == OP_ZERO || (d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits)) ok = false;
     }
-    if (!ok || C.lam_size > budget) continue;
-    // buffers by global offset: forward outputs and adjoint buffers
-    struct Buf {
-      int64_t goff, size;
+    if (!ok) continue;
+    std::unordered_map<int64_t, int64_t> lam_local;  // leaf tables: offset inside the block
+    std::unordered_map<int64_t, size_t> idx;
+    struct L {
+      int64_t code, size;
       int def = -1, last = -1;
       int64_t loff = -1;
     };
-    std::vector<Buf> bufs;
-    std::unordered_map<int64_t, int> id;
-    auto add = [&](int64_t g, int64_t sz) {
-      if (id.count(g)) return;
-      id[g] = (int)bufs.size();
-      bufs.push_back({g, std::max<int64_t>(sz, 2)});
-    };
-    for (size_t b = 0; b < C.buckets.size(); ++b) {
-      const int64_t sz = int64_t(1) << C.buckets[b].out_rank();
-      add(C.out_off[b], sz);
-      add(C.adj_off[b], sz);
+    std::vector<L> bufs;
+    for (const BufLife& B : C.bufs) {
+      if (code_kind(B.code) == BK_LAM) lam_local[B.code] = B.off;
+      if (code_kind(B.code) == BK_LAM || code_kind(B.code) == BK_LAMADJ) continue;
+      idx[B.code] = bufs.size();
+      bufs.push_back({B.code, B.size});
     }
-    auto in_lam = [&](int64_t g) { return g >= C.lam_base && g < C.lam_base + C.lam_size; };
-    auto touch = [&](int64_t g, int t, bool write) {
-      auto it = id.find(g);
-      if (it == id.end()) return;
-      Buf& B = bufs[it->second];
-      if (write && B.def < 0) B.def = t;
+    auto touch = [&](int64_t code, int t) {
+      auto it = idx.find(code);
+      if (it == idx.end()) return;
+      L& B = bufs[it->second];
       if (B.def < 0) B.def = t;
       B.last = std::max(B.last, t);
     };
     for (size_t t = 0; t < prog.size(); ++t) {
       const OpDesc& d = P.ops[prog[t]];
       if (d.kind == OP_CONTRACT) {
-        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t, false);
-        touch(d.out_off, (int)t, true);
+        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t);
+        touch(d.out_off, (int)t);
       } else if (d.kind == OP_RESULT) {
-        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t, false);
+        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t);
         if (d.flags & F_GRAD)
-          for (int i = 0; i < d.n_in; ++i) touch(d.in_off[d.n_in + i], (int)t, true);
+          for (int i = 0; i < d.n_in; ++i) touch(d.in_off[d.n_in + i], (int)t);
       }
     }
-    // first fit, lifetimes [def, last]
-    std::vector<int> order;
+    std::vector<size_t> order;
     for (size_t i = 0; i < bufs.size(); ++i)
-      if (bufs[i].def >= 0) order.push_back((int)i);
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return bufs[a].def < bufs[b].def; });
+      if (bufs[i].def >= 0) order.push_back(i);
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bufs[a].def < bufs[b].def; });
     const int64_t base0 = (C.lam_size + 63) / 64 * 64;
     int64_t peak = base0;
-    std::vector<int> live;
-    for (int bi : order) {
-      Buf& B = bufs[bi];
-      live.erase(std::remove_if(live.begin(), live.end(), [&](int x) { return bufs[x].last < B.def; }), live.end());
+    std::vector<size_t> live;
+    for (size_t bi : order) {
+      L& B = bufs[bi];
+      live.erase(std::remove_if(live.begin(), live.end(), [&](size_t x) { return bufs[x].last < B.def; }), live.end());
       std::vector<std::pair<int64_t, int64_t>> used;
-      for (int x : live) used.push_back({bufs[x].loff, bufs[x].loff + bufs[x].size});
+      for (size_t x : live) used.push_back({bufs[x].loff, bufs[x].loff + bufs[x].size});
       std::sort(used.begin(), used.end());
       const int64_t al = B.size >= 64 ? 64 : 2;
       int64_t cand = base0;
@@ -605,16 +548,17 @@ static void lds_layout(Plan& P) {
       live.push_back(bi);
     }
     if (peak > budget) continue;
-    // commit: LDS offsets into the ops
     P.cone_lds[c] = 1;
     P.lds_elems = std::max(P.lds_elems, peak);
-    auto lds_of = [&](int64_t g, int32_t& out) -> bool {
-      if (in_lam(g)) {
-        out = (int32_t)(g - C.lam_base);
+    auto lds_of = [&](int64_t code, int32_t& out) -> bool {
+      if (!is_code(code)) return false;
+      auto lt = lam_local.find(code);
+      if (lt != lam_local.end()) {
+        out = (int32_t)lt->second;
         return true;
       }
-      auto it = id.find(g);
-      if (it == id.end() || bufs[it->second].loff < 0) return false;
+      auto it = idx.find(code);
+      if (it == idx.end() || bufs[it->second].loff < 0) return false;
       out = (int32_t)bufs[it->second].loff;
       return true;
     };
@@ -626,8 +570,7 @@ static void lds_layout(Plan& P) {
           if (lds_of(d.in_off[i], d.lds_off[i])) d.lds_mask |= 1u << i;
         if (lds_of(d.out_off, d.lds_off[MAXIN])) d.lds_mask |= 1u << MAXIN;
       } else if (d.kind == OP_RESULT) {
-        const int ns = d.n_in;
-        for (int i = 0; i < 2 * ns; ++i)
+        for (int i = 0; i < 2 * d.n_in; ++i)
           if (lds_of(d.in_off[i], d.lds_off[i])) d.lds_mask |= 1u << i;
       }
     }
@@ -694,9 +637,296 @@ static void mark_barriers(Plan& P) {
   }
 }
 
+namespace {
+
+// One cone's programs with buffer codes as operands.
+struct ConeProg {
+  std::vector<OpDesc> fwd, adj, leaf, lgrad;
+  OpDesc result;
+};
+
+int64_t buf_size(const Cone& C, int64_t code) {
+  const Bucket& B = C.buckets[code_bucket(code)];
+  switch (code_kind(code)) {
+    case BK_LAM:
+    case BK_LAMADJ: return int64_t(1) << B.lam_rank();
+    default: return std::max<int64_t>(int64_t(1) << B.out_rank(), 2);
+  }
+}
+
+// Forward program (leaf tables, buckets in elimination order, result) and
+// adjoint program (result with seeds, buckets in reverse order: the adjoint of
+// every intermediate input and of the leaf-product table; recomputation of
+// dropped outputs right before they are needed; zeroing right before ops
+// that accumulate).  The paper defines the forward contraction (Section
+// III.B); the adjoint is the reverse sweep of the same buckets.
+std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
+  Cone& C = P.cones[c];
+  const TuneParams& T = P.tune;
+  const int eb = T.elem_bytes;
+  G = ConeProg();
+  if (C.width > MAXBITS - 1) return "contraction width " + std::to_string(C.width) + " exceeds 30";
+  if (C.scalars.size() > MAXIN / 2) return "more than 4 disconnected components in one light cone";
+  const size_t nb = C.buckets.size();
+  if (C.recompute.size() != nb) C.recompute.assign(nb, 0);
+  C.fwd_bytes_alg = C.bwd_bytes_alg = C.fwd_flops = C.rec_bytes = 0;
+  std::vector<int32_t> ref_lo(nb, -1), ref_n(nb, 0);
+  for (size_t b = 0; b < nb; ++b) {
+    const Bucket& Bk = C.buckets[b];
+    if (!Bk.lam_mask) continue;
+    OpDesc d = blank(OP_LEAF, (int)c);
+    d.nbits = Bk.lam_rank();
+    d.out_off = buf_code(BK_LAM, (int)b);
+    d.aux0 = (int32_t)P.leafrefs.size();
+    for (int li : Bk.leaves) {
+      const Leaf& l = C.leaves[li];
+      auto lbit = [&](int idx) {
+        int u = 0;
+        while (Bk.uni[u] != idx) ++u;
+        return __builtin_popcount(Bk.lam_mask & ((1u << u) - 1));
+      };
+      LeafRef r;
+      r.kind = (int16_t)l.kind;
+      r.pa = (int8_t)lbit(l.a);
+      r.pb = (int8_t)(l.b >= 0 ? lbit(l.b) : -1);
+      P.leafrefs.push_back(r);
+    }
+    d.aux1 = (int32_t)P.leafrefs.size() - d.aux0;
+    ref_lo[b] = d.aux0;
+    ref_n[b] = d.aux1;
+    G.leaf.push_back(d);
+  }
+  // forward contraction of bucket b, writing `out` (its output or a recomputation)
+  auto fwd_op = [&](size_t b, int64_t out, double* bytes, double* flops) -> OpDesc {
+    const Bucket& Bk = C.buckets[b];
+    const int nbits = Bk.nbits();
+    OpDesc d = blank(OP_CONTRACT, (int)c);
+    d.nbits = nbits;
+    int ni = 0;
+    double in_elems = 0;
+    for (size_t t = 0; t < Bk.in_bkt.size(); ++t) {
+      d.in_off[ni] = buf_code(BK_OUT, Bk.in_bkt[t]);
+      d.in_mask[ni] = Bk.in_mask[t];
+      in_elems += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
+      ++ni;
+    }
+    if (Bk.lam_mask) {
+      d.in_off[ni] = buf_code(BK_LAM, (int)b);
+      d.in_mask[ni] = Bk.lam_mask;
+      ++ni;
+    }
+    d.n_in = ni;
+    d.out_mask = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u) & ~1u;
+    d.out_off = out;
+    partition_bits(d, nbits, d.out_mask, nbits <= T.seq_max_bits, T);
+    const double outn = std::ldexp(1.0, nbits - 1);
+    if (bytes) *bytes += (in_elems + outn) * eb;
+    if (flops) *flops += 6.0 * std::max(0, ni - 1) * std::ldexp(1.0, nbits) + 2.0 * outn;
+    return d;
+  };
+  for (size_t b = 0; b < nb; ++b) {
+    const Bucket& Bk = C.buckets[b];
+    if (Bk.in_bkt.size() + (Bk.lam_mask ? 1 : 0) > (size_t)MAXIN) return "bucket with more than 8 inputs";
+    G.fwd.push_back(fwd_op(b, buf_code(BK_OUT, (int)b), &C.fwd_bytes_alg, &C.fwd_flops));
+  }
+  G.result = blank(OP_RESULT, (int)c);
+  G.result.n_in = (int)C.scalars.size();
+  for (size_t s = 0; s < C.scalars.size(); ++s) {
+    G.result.in_off[s] = buf_code(BK_OUT, C.scalars[s]);
+    G.result.in_off[C.scalars.size() + s] = buf_code(BK_ADJ, C.scalars[s]);
+  }
+  OpDesc rg = G.result;
+  rg.flags = F_GRAD;
+  G.adj.push_back(rg);
+  for (size_t bb = nb; bb-- > 0;) {
+    const Bucket& Bk = C.buckets[bb];
+    const int nbits = Bk.nbits();
+    const bool seq = nbits <= T.seq_max_bits;
+    const uint32_t all = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u);
+    const int nin = (int)Bk.in_bkt.size();
+    // inputs dropped after the forward sweep are recomputed before their use
+    for (int t = 0; t < nin; ++t) {
+      const int pb = Bk.in_bkt[t];
+      if (C.recompute[pb]) G.adj.push_back(fwd_op(pb, buf_code(BK_REC, pb), &C.rec_bytes, nullptr));
+    }
+    auto in_code = [&](int t) {
+      const int pb = Bk.in_bkt[t];
+      return buf_code(C.recompute[pb] ? BK_REC : BK_OUT, pb);
+    };
+    double stored = 0;
+    for (int t = 0; t < nin; ++t) stored += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
+    C.bwd_bytes_alg += (std::ldexp(1.0, nbits - 1) + stored) * eb;
+    auto add_common = [&](OpDesc& d, int skip_t, bool with_lam) {
+      int ni = 0;
+      d.in_off[ni] = buf_code(BK_ADJ, (int)bb);
+      d.in_mask[ni] = all & ~1u;
+      ++ni;
+      if (with_lam && Bk.lam_mask) {
+        d.in_off[ni] = buf_code(BK_LAM, (int)bb);
+        d.in_mask[ni] = Bk.lam_mask;
+        ++ni;
+      }
+      for (int t = 0; t < nin; ++t) {
+        if (t == skip_t) continue;
+        d.in_off[ni] = in_code(t);
+        d.in_mask[ni] = Bk.in_mask[t];
+        ++ni;
+      }
+      d.n_in = ni;
+    };
+    auto push_adj = [&](OpDesc& d) {
+      if (d.flags & F_ATOMIC) {
+        OpDesc z = blank(OP_ZERO, (int)c);
+        z.out_off = d.out_off;
+        z.in_off[0] = int64_t(1) << __builtin_popcount(d.out_mask);
+        G.adj.push_back(z);
+      }
+      G.adj.push_back(d);
+    };
+    for (int t = 0; t < nin; ++t) {
+      OpDesc d = blank(OP_CONTRACT, (int)c);
+      d.nbits = nbits;
+      add_common(d, t, true);
+      if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
+      d.out_mask = Bk.in_mask[t];
+      d.out_off = buf_code(BK_ADJ, Bk.in_bkt[t]);
+      partition_bits(d, nbits, d.out_mask, seq, T);
+      push_adj(d);
+      C.bwd_bytes_alg += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t])) * eb;
+    }
+    if (Bk.lam_mask) {
+      OpDesc d = blank(OP_CONTRACT, (int)c);
+      d.nbits = nbits;
+      add_common(d, -1, false);
+      if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
+      d.out_mask = Bk.lam_mask;
+      d.out_off = buf_code(BK_LAMADJ, (int)bb);
+      partition_bits(d, nbits, d.out_mask, seq, T);
+      push_adj(d);
+      OpDesc g = blank(OP_LEAFGRAD, (int)c);
+      g.nbits = Bk.lam_rank();
+      g.in_off[0] = buf_code(BK_LAMADJ, (int)bb);
+      g.aux0 = ref_lo[bb];
+      g.aux1 = ref_n[bb];
+      G.lgrad.push_back(g);
+    }
+  }
+  return "";
+}
+
+// Lifetimes over the gradient program and first-fit placement.  Arena of a
+// cone: [leaf tables][their adjoints][everything else, reused by lifetime].
+int64_t alloc_cone(Cone& C, const ConeProg& G) {
+  std::unordered_map<int64_t, size_t> idx;
+  C.bufs.clear();
+  auto touch = [&](int64_t code, int t) {
+    if (!is_code(code)) return;
+    auto it = idx.find(code);
+    if (it == idx.end()) {
+      idx[code] = C.bufs.size();
+      BufLife B;
+      B.code = code;
+      B.size = buf_size(C, code);
+      B.def = B.last = t;
+      C.bufs.push_back(B);
+    } else {
+      C.bufs[it->second].last = std::max(C.bufs[it->second].last, t);
+    }
+  };
+  auto scan = [&](const OpDesc& d, int t) {
+    switch (d.kind) {
+      case OP_CONTRACT:
+        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], t);
+        touch(d.out_off, t);
+        break;
+      case OP_RESULT:
+        for (int i = 0; i < 2 * d.n_in; ++i) touch(d.in_off[i], t);
+        break;
+      case OP_ZERO: touch(d.out_off, t); break;
+      case OP_LEAF: touch(d.out_off, t); break;
+      case OP_LEAFGRAD: touch(d.in_off[0], t); break;
+      default: break;
+    }
+  };
+  int t = 0;
+  for (const OpDesc& d : G.leaf) scan(d, t);
+  for (const OpDesc& d : G.fwd) scan(d, ++t);
+  scan(G.result, ++t);  // forward-only result: same position as the seeding result
+  for (const OpDesc& d : G.adj) scan(d, t++);
+  for (const OpDesc& d : G.lgrad) scan(d, t);
+  // pinned blocks
+  int64_t off = 0;
+  for (BufLife& B : C.bufs)
+    if (code_kind(B.code) == BK_LAM) {
+      off = align_elems(off, B.size);
+      B.off = off;
+      off += B.size;
+    }
+  const int64_t lam_size = off;
+  off = align_elems(off, 64);
+  for (BufLife& B : C.bufs)
+    if (code_kind(B.code) == BK_LAMADJ) {
+      off = align_elems(off, B.size);
+      B.off = off;
+      off += B.size;
+    }
+  const int64_t base0 = align_elems(off, 64);
+  std::vector<size_t> order;
+  for (size_t i = 0; i < C.bufs.size(); ++i) {
+    const int k = code_kind(C.bufs[i].code);
+    if (k != BK_LAM && k != BK_LAMADJ) order.push_back(i);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return C.bufs[a].def < C.bufs[b].def; });
+  int64_t peak = base0;
+  std::vector<size_t> live;
+  for (size_t bi : order) {
+    BufLife& B = C.bufs[bi];
+    live.erase(std::remove_if(live.begin(), live.end(), [&](size_t x) { return C.bufs[x].last < B.def; }),
+               live.end());
+    std::vector<std::pair<int64_t, int64_t>> used;
+    for (size_t x : live) used.push_back({C.bufs[x].off, C.bufs[x].off + C.bufs[x].size});
+    std::sort(used.begin(), used.end());
+    const int64_t al = B.size >= 64 ? 64 : 2;
+    int64_t cand = base0;
+    for (auto& u : used) {
+      if (cand + B.size <= u.first) break;
+      cand = std::max(cand, align_elems(u.second, al >= 64 ? B.size : 2));
+    }
+    B.off = cand;
+    peak = std::max(peak, cand + B.size);
+    live.push_back(bi);
+  }
+  C.lam_size = lam_size;
+  C.arena_elems = align_elems(peak, 64);
+  return C.arena_elems;
+}
+
+// The largest kept bucket output whose producer reads only kept outputs, so
+// that its recomputation is one contraction deep; -1 if none.
+int recompute_candidate(const Cone& C) {
+  int best = -1;
+  for (size_t b = 0; b < C.buckets.size(); ++b) {
+    const Bucket& Bk = C.buckets[b];
+    if (C.recompute[b] || Bk.consumer < 0 || Bk.out_rank() < 4) continue;
+    bool ok = true;
+    for (int pb : Bk.in_bkt) ok &= !C.recompute[pb];
+    for (size_t x = 0; x < C.buckets.size() && ok; ++x)  // nothing recomputed may read it
+      if (C.recompute[x])
+        for (int pb : C.buckets[x].in_bkt) ok &= pb != (int)b;
+    if (ok && (best < 0 || Bk.out_rank() > C.buckets[best].out_rank())) best = (int)b;
+  }
+  return best;
+}
+
+int64_t resolve_off(const Cone& C, const std::unordered_map<int64_t, int64_t>& where, int64_t v) {
+  if (!is_code(v)) return v;
+  return C.base + where.at(v);
+}
+
+}  // namespace
+
 std::string build_programs(Plan& P, int elem_bytes) {
   P.tune.elem_bytes = elem_bytes;
-  const TuneParams& T = P.tune;
   P.ops.clear();
   P.leafrefs.clear();
   const size_t nc = P.cones.size();
@@ -704,187 +934,87 @@ std::string build_programs(Plan& P, int elem_bytes) {
   P.cone_fwd_hi.assign(nc, 0);
   P.cone_adj_lo.assign(nc, 0);
   P.cone_adj_hi.assign(nc, 0);
-  std::vector<std::vector<int32_t>> zero_ops(nc);
+  std::vector<ConeProg> progs(nc);
+  int64_t total = 0;
+  for (size_t c = 0; c < nc; ++c) {
+    P.cones[c].recompute.assign(P.cones[c].buckets.size(), 0);
+    std::string err = emit_cone(P, c, progs[c]);
+    if (!err.empty()) return err;
+    total += alloc_cone(P.cones[c], progs[c]);
+    P.cones[c].keep_all_elems = P.cones[c].arena_elems;
+  }
+  // memory budget: drop the largest recomputable outputs of the largest
+  // cones until the arena fits
+  while (P.mem_budget > 0 && total > P.mem_budget) {
+    size_t worst = nc;
+    int cand = -1;
+    for (size_t c = 0; c < nc; ++c) {
+      const int b = recompute_candidate(P.cones[c]);
+      if (b >= 0 && (worst == nc || P.cones[c].arena_elems > P.cones[worst].arena_elems)) {
+        worst = c;
+        cand = b;
+      }
+    }
+    if (worst == nc) return "the gradient sweep does not fit the memory budget even with recomputation";
+    Cone& C = P.cones[worst];
+    const int64_t before = C.arena_elems;
+    C.recompute[cand] = 1;
+    std::string err = emit_cone(P, worst, progs[worst]);
+    if (!err.empty()) return err;
+    total += alloc_cone(C, progs[worst]) - before;
+  }
+  // assemble the op list (operands still coded)
   std::vector<OpDesc> leaf_ops, lgrad_ops;
   for (size_t c = 0; c < nc; ++c) {
-    Cone& C = P.cones[c];
-    const int64_t base = 0;  // offsets are absolute arena offsets
-    (void)base;
-    if (C.width > MAXBITS - 1) return "contraction width " + std::to_string(C.width) + " exceeds 30";
-    if (C.scalars.size() > MAXIN / 2) return "more than 4 disconnected components in one light cone";
-    C.fwd_bytes_alg = C.bwd_bytes_alg = C.fwd_flops = 0;
+    ConeProg& G = progs[c];
     P.cone_fwd_lo[c] = (int32_t)P.ops.size();
-    // leaf-product tables (one batched launch for all cones, before the sweep)
-    std::vector<int32_t> ref_lo(C.buckets.size(), -1), ref_n(C.buckets.size(), 0);
-    for (size_t b = 0; b < C.buckets.size(); ++b) {
-      const Bucket& Bk = C.buckets[b];
-      if (!Bk.lam_mask) continue;
-      OpDesc d = blank(OP_LEAF, (int)c);
-      d.nbits = Bk.lam_rank();
-      d.out_off = C.lam_off[b];
-      d.aux0 = (int32_t)P.leafrefs.size();
-      for (int li : Bk.leaves) {
-        const Leaf& l = C.leaves[li];
-        auto lbit = [&](int idx) {
-          int u = 0;
-          while (Bk.uni[u] != idx) ++u;
-          return __builtin_popcount(Bk.lam_mask & ((1u << u) - 1));
-        };
-        LeafRef r;
-        r.kind = (int16_t)l.kind;
-        r.pa = (int8_t)lbit(l.a);
-        r.pb = (int8_t)(l.b >= 0 ? lbit(l.b) : -1);
-        P.leafrefs.push_back(r);
-      }
-      d.aux1 = (int32_t)P.leafrefs.size() - d.aux0;
-      ref_lo[b] = d.aux0;
-      ref_n[b] = d.aux1;
-      leaf_ops.push_back(d);
-    }
-    // forward buckets
-    for (size_t b = 0; b < C.buckets.size(); ++b) {
-      const Bucket& Bk = C.buckets[b];
-      const int nbits = Bk.nbits();
-      const bool seq = nbits <= T.seq_max_bits;
-      OpDesc d = blank(OP_CONTRACT, (int)c);
-      d.nbits = nbits;
-      int ni = 0;
-      double in_elems = 0;
-      for (size_t t = 0; t < Bk.in_bkt.size(); ++t) {
-        if (ni >= MAXIN) return "bucket with more than 8 inputs";
-        d.in_off[ni] = C.out_off[Bk.in_bkt[t]];
-        d.in_mask[ni] = Bk.in_mask[t];
-        in_elems += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
-        ++ni;
-      }
-      if (Bk.lam_mask) {
-        if (ni >= MAXIN) return "bucket with more than 8 inputs";
-        d.in_off[ni] = C.lam_off[b];
-        d.in_mask[ni] = Bk.lam_mask;
-        ++ni;
-      }
-      d.n_in = ni;
-      d.out_mask = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u) & ~1u;
-      d.out_off = C.out_off[b];
-      partition_bits(d, nbits, d.out_mask, seq, T);
-      P.ops.push_back(d);
-      const double outn = std::ldexp(1.0, nbits - 1);
-      C.fwd_bytes_alg += (in_elems + outn) * elem_bytes;
-      C.fwd_flops += 6.0 * std::max(0, ni - 1) * std::ldexp(1.0, nbits) + 2.0 * outn;
-    }
+    P.ops.insert(P.ops.end(), G.fwd.begin(), G.fwd.end());
     P.cone_fwd_hi[c] = (int32_t)P.ops.size();
-    // result (+ seeds when a gradient is requested; the same op record serves
-    // both programs, F_GRAD is set on the gradient copy)
-    {
-      OpDesc d = blank(OP_RESULT, (int)c);
-      d.n_in = (int)C.scalars.size();
-      for (size_t s = 0; s < C.scalars.size(); ++s) {
-        d.in_off[s] = C.out_off[C.scalars[s]];
-        d.in_off[C.scalars.size() + s] = C.adj_off[C.scalars[s]];
-      }
-      P.ops.push_back(d);
-    }
+    P.ops.push_back(G.result);
     P.cone_adj_lo[c] = (int32_t)P.ops.size();
-    {
-      OpDesc d = P.ops.back();
-      d.flags = F_GRAD;
-      P.ops.push_back(d);
-    }
-    // adjoint sweep, buckets in reverse elimination order
-    const size_t zero_slot = P.ops.size();
-    (void)zero_slot;
-    for (size_t bb = C.buckets.size(); bb-- > 0;) {
-      const Bucket& Bk = C.buckets[bb];
-      const int nbits = Bk.nbits();
-      const bool seq = nbits <= T.seq_max_bits;
-      const uint32_t all = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u);
-      const int nin = (int)Bk.in_bkt.size();
-      const double ob = std::ldexp(1.0, nbits - 1);
-      double stored = 0;
-      for (int t = 0; t < nin; ++t) stored += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
-      C.bwd_bytes_alg += (ob + stored) * elem_bytes;
-      auto add_common = [&](OpDesc& d, int skip_t, bool with_lam) {
-        int ni = 0;
-        d.in_off[ni] = C.adj_off[bb];
-        d.in_mask[ni] = all & ~1u;
-        ++ni;
-        if (with_lam && Bk.lam_mask) {
-          d.in_off[ni] = C.lam_off[bb];
-          d.in_mask[ni] = Bk.lam_mask;
-          ++ni;
-        }
-        for (int t = 0; t < nin; ++t) {
-          if (t == skip_t) continue;
-          d.in_off[ni] = C.out_off[Bk.in_bkt[t]];
-          d.in_mask[ni] = Bk.in_mask[t];
-          ++ni;
-        }
-        d.n_in = ni;
-      };
-      for (int t = 0; t < nin; ++t) {
-        OpDesc d = blank(OP_CONTRACT, (int)c);
-        d.nbits = nbits;
-        add_common(d, t, true);
-        if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
-        d.out_mask = Bk.in_mask[t];
-        d.out_off = C.adj_off[Bk.in_bkt[t]];
-        partition_bits(d, nbits, d.out_mask, seq, T);
-        if (d.flags & F_ATOMIC) zero_ops[c].push_back((int32_t)P.ops.size());
-        P.ops.push_back(d);
-        C.bwd_bytes_alg += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t])) * elem_bytes;
-      }
-      if (Bk.lam_mask) {
-        OpDesc d = blank(OP_CONTRACT, (int)c);
-        d.nbits = nbits;
-        add_common(d, -1, false);
-        if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
-        d.out_mask = Bk.lam_mask;
-        d.out_off = C.lamadj_off[bb];
-        partition_bits(d, nbits, d.out_mask, seq, T);
-        if (d.flags & F_ATOMIC) zero_ops[c].push_back((int32_t)P.ops.size());
-        P.ops.push_back(d);
-        // leaf gradient of this bucket: one batched launch after the sweep
-        OpDesc g = blank(OP_LEAFGRAD, (int)c);
-        g.nbits = Bk.lam_rank();
-        g.in_off[0] = C.lamadj_off[bb];
-        g.aux0 = ref_lo[bb];
-        g.aux1 = ref_n[bb];
-        lgrad_ops.push_back(g);
-      }
-    }
+    P.ops.insert(P.ops.end(), G.adj.begin(), G.adj.end());
     P.cone_adj_hi[c] = (int32_t)P.ops.size();
+    leaf_ops.insert(leaf_ops.end(), G.leaf.begin(), G.leaf.end());
+    lgrad_ops.insert(lgrad_ops.end(), G.lgrad.begin(), G.lgrad.end());
   }
-  // Zeroing of atomic adjoint outputs: insert right after each cone's result
-  // op.  Rebuild the op list with the zero ops spliced in.
-  bool any_zero = false;
-  for (auto& z : zero_ops) any_zero |= !z.empty();
-  if (any_zero) {
-    std::vector<OpDesc> ops;
-    ops.reserve(P.ops.size() + 64);
-    for (size_t c = 0; c < nc; ++c) {
-      int32_t flo = (int32_t)ops.size();
-      for (int32_t o = P.cone_fwd_lo[c]; o < P.cone_fwd_hi[c]; ++o) ops.push_back(P.ops[o]);
-      int32_t fhi = (int32_t)ops.size();
-      ops.push_back(P.ops[P.cone_fwd_hi[c]]);  // forward result op
-      int32_t alo = (int32_t)ops.size();
-      ops.push_back(P.ops[P.cone_adj_lo[c]]);  // gradient result op
-      for (int32_t zo : zero_ops[c]) {
-        const OpDesc& src = P.ops[zo];
-        OpDesc z = blank(OP_ZERO, (int)c);
-        z.out_off = src.out_off;
-        z.in_off[0] = int64_t(1) << __builtin_popcount(src.out_mask);
-        ops.push_back(z);
-      }
-      for (int32_t o = P.cone_adj_lo[c] + 1; o < P.cone_adj_hi[c]; ++o) ops.push_back(P.ops[o]);
-      int32_t ahi = (int32_t)ops.size();
-      P.cone_fwd_lo[c] = flo;
-      P.cone_fwd_hi[c] = fhi;
-      P.cone_adj_lo[c] = alo;
-      P.cone_adj_hi[c] = ahi;
-    }
-    P.ops.swap(ops);
+  P.leaf_lo = (int32_t)P.ops.size();
+  P.ops.insert(P.ops.end(), leaf_ops.begin(), leaf_ops.end());
+  P.leaf_hi = (int32_t)P.ops.size();
+  P.lgrad_lo = P.leaf_hi;
+  P.ops.insert(P.ops.end(), lgrad_ops.begin(), lgrad_ops.end());
+  P.lgrad_hi = (int32_t)P.ops.size();
+  // cone bases, LDS windows (on codes), then absolute offsets
+  int64_t off = 0;
+  for (size_t c = 0; c < nc; ++c) {
+    Cone& C = P.cones[c];
+    C.base = off;
+    C.lam_base = off;
+    off += C.arena_elems;
   }
+  P.arena_grad = P.arena_fwd = align_elems(off, 64);
   lds_layout(P);
+  {
+    std::vector<std::unordered_map<int64_t, int64_t>> where(nc);
+    for (size_t c = 0; c < nc; ++c)
+      for (const BufLife& B : P.cones[c].bufs) where[c][B.code] = B.off;
+    for (OpDesc& d : P.ops) {
+      const Cone& C = P.cones[d.cone];
+      const auto& W = where[d.cone];
+      switch (d.kind) {
+        case OP_CONTRACT:
+          for (int i = 0; i < d.n_in; ++i) d.in_off[i] = resolve_off(C, W, d.in_off[i]);
+          d.out_off = resolve_off(C, W, d.out_off);
+          break;
+        case OP_RESULT:
+          for (int i = 0; i < 2 * d.n_in; ++i) d.in_off[i] = resolve_off(C, W, d.in_off[i]);
+          break;
+        case OP_ZERO:
+        case OP_LEAF: d.out_off = resolve_off(C, W, d.out_off); break;
+        case OP_LEAFGRAD: d.in_off[0] = resolve_off(C, W, d.in_off[0]); break;
+        default: break;
+      }
+    }
+  }
   mark_barriers(P);
   // copy-in ops of the LDS-resident cones (leaf-product block -> LDS)
   P.cone_copyin.assign(nc, -1);
@@ -896,12 +1026,6 @@ std::string build_programs(Plan& P, int elem_bytes) {
       P.cone_copyin[c] = (int32_t)P.ops.size();
       P.ops.push_back(d);
     }
-  P.leaf_lo = (int32_t)P.ops.size();
-  P.ops.insert(P.ops.end(), leaf_ops.begin(), leaf_ops.end());
-  P.leaf_hi = (int32_t)P.ops.size();
-  P.lgrad_lo = P.leaf_hi;
-  P.ops.insert(P.ops.end(), lgrad_ops.begin(), lgrad_ops.end());
-  P.lgrad_hi = (int32_t)P.ops.size();
   return "";
 }
 
@@ -971,22 +1095,24 @@ std::string validate_plan(const Plan& P) {
     for (int b = 0; b < n; ++b)
       if ((C.buckets[b].consumer >= 0) != (consumed[b] == 1)) return "cone " + S(c, b) + "output not consumed once";
     if (width != C.width) return "cone " + S(c) + "width mismatch";
-    for (int b = 0; b < n; ++b) {
-      const Bucket& B = C.buckets[b];
-      const int64_t sz = std::max<int64_t>(int64_t(1) << B.out_rank(), 2);
-      iv.push_back({C.out_off[b], C.out_off[b] + sz});
-      iv.push_back({C.adj_off[b], C.adj_off[b] + sz});
-      if (B.lam_mask) {
-        iv.push_back({C.lam_off[b], C.lam_off[b] + (int64_t(1) << B.lam_rank())});
-        iv.push_back({C.lamadj_off[b], C.lamadj_off[b] + (int64_t(1) << B.lam_rank())});
-      }
+    // arena placement: in the cone's region, and buffers alive at the same
+    // time never overlap
+    std::vector<const BufLife*> bl;
+    for (const BufLife& B : C.bufs) {
+      if (B.off < 0 || B.off + B.size > C.arena_elems) return "cone " + S(c) + "buffer outside the cone's arena";
+      bl.push_back(&B);
     }
+    std::sort(bl.begin(), bl.end(), [](const BufLife* a, const BufLife* b) { return a->def < b->def; });
+    for (size_t i = 0; i < bl.size(); ++i)
+      for (size_t j = i + 1; j < bl.size() && bl[j]->def <= bl[i]->last; ++j) {
+        const BufLife& A = *bl[i];
+        const BufLife& B = *bl[j];
+        if (A.off < B.off + B.size && B.off < A.off + A.size)
+          return "cone " + S(c) + "buffers with overlapping lifetimes share memory";
+      }
+    if (C.base < 0 || C.base + C.arena_elems > P.arena_grad) return "cone " + S(c) + "arena out of bounds";
   }
-  std::sort(iv.begin(), iv.end(), [](const Iv& a, const Iv& b) { return a.lo < b.lo; });
-  for (size_t i = 0; i < iv.size(); ++i) {
-    if (iv[i].lo < 0 || iv[i].hi > P.arena_grad) return "arena range out of bounds";
-    if (i && iv[i].lo < iv[i - 1].hi) return "arena ranges overlap";
-  }
+  (void)iv;
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const OpDesc& d = P.ops[o];
     if (d.kind != OP_CONTRACT) continue;

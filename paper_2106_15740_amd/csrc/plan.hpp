@@ -40,6 +40,29 @@ struct Bucket {
   int lam_rank() const { return __builtin_popcount(lam_mask); }
 };
 
+// Logical buffers of a cone program.  While programs are built, an operand
+// offset holds buf_code(kind, bucket) (a negative number); the arena layout
+// replaces it by an absolute element offset.
+enum BufKind : int32_t {
+  BK_OUT = 0,     // forward output of a bucket
+  BK_ADJ = 1,     // adjoint of that output
+  BK_REC = 2,     // forward output recomputed during the adjoint sweep
+  BK_LAM = 3,     // leaf-product table
+  BK_LAMADJ = 4,  // adjoint of the leaf-product table
+};
+inline int64_t buf_code(int kind, int bucket) { return -((((int64_t)bucket) << 3 | kind) + 1); }
+inline bool is_code(int64_t off) { return off < 0; }
+inline int code_kind(int64_t code) { return (int)((-code - 1) & 7); }
+inline int code_bucket(int64_t code) { return (int)((-code - 1) >> 3); }
+
+// Lifetime and placement of one logical buffer in the cone's arena.
+struct BufLife {
+  int64_t code = 0;
+  int64_t size = 0;
+  int def = -1, last = -1;  // positions in the gradient program
+  int64_t off = -1;         // element offset relative to the cone's base
+};
+
 // One edge term <Z_j Z_k>: the light-cone network and its contraction plan.
 struct Cone {
   int32_t j = 0, k = 0;
@@ -50,12 +73,14 @@ struct Cone {
   int32_t width = 0;              // largest bucket output rank
   std::vector<Bucket> buckets;    // in elimination order
   std::vector<int32_t> scalars;   // buckets whose output has rank 0
-  // arena layout (element offsets relative to the cone's base)
-  std::vector<int64_t> out_off, lam_off, adj_off, lamadj_off;
-  int64_t lam_base = 0, lam_size = 0;  // contiguous block of the leaf-product tables
-  int64_t fwd_elems = 0;          // outputs + leaf tables
-  int64_t total_elems = 0;        // + adjoint buffers
-  double fwd_bytes_alg = 0, bwd_bytes_alg = 0, fwd_flops = 0;
+  // arena: [leaf tables][their adjoints][buffers placed by lifetime]
+  std::vector<char> recompute;    // bucket outputs not kept for the adjoint sweep (recomputed there)
+  std::vector<BufLife> bufs;      // placement of every logical buffer
+  int64_t base = 0;               // element offset of the cone in the arena
+  int64_t arena_elems = 0;        // elements the cone occupies
+  int64_t keep_all_elems = 0;     // elements without any recomputation
+  int64_t lam_base = 0, lam_size = 0;  // contiguous block of the leaf-product tables (absolute)
+  double fwd_bytes_alg = 0, bwd_bytes_alg = 0, fwd_flops = 0, rec_bytes = 0;
 };
 
 struct TuneParams {
@@ -86,8 +111,8 @@ struct Plan {
   std::vector<char> cone_lds;          // cone runs LDS-resident in the persistent sweep
   std::vector<int32_t> cone_copyin;    // its OP_COPYIN op (-1: none)
   int64_t lds_elems = 0;               // largest LDS window needed (elements)
-  std::vector<int64_t> cone_base;   // element offset of each cone in the arena
   int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
+  int64_t mem_budget = 0;           // arena budget in elements (0: unlimited)
   // persistent-queue items (forward-only and forward+gradient programs)
   std::vector<QItem> items_fwd, items_grad;
   std::vector<int32_t> node_init_fwd, node_init_grad;   // initial dependency counts
@@ -105,7 +130,9 @@ struct OrderOptions {
   uint64_t seed = 0;
 };
 void order_cones(Plan& P, const OrderOptions& O, int n_threads);
-void layout_cones(Plan& P);
+// Builds every cone's forward and adjoint programs, places the buffers by
+// lifetime (recomputing bucket outputs in the adjoint sweep where the memory
+// budget requires it) and resolves all operand offsets.
 std::string build_programs(Plan& P, int elem_bytes);
 // Persistent-queue items for the forward (grad = false) or forward + adjoint
 // program; items are in topological order.

@@ -103,6 +103,12 @@ class QaoaNet:
         L.check(self._lib.qtn_workspace_size(self.handle, int(bool(with_grad)), C.byref(s)))
         return s.value
 
+    def set_memory_budget(self, nbytes: int) -> None:
+        """Checkpointed adjoint: keep the workspace within about nbytes by
+        recomputing dropped bucket outputs in the adjoint sweep (0: no limit)."""
+        L.check(self._lib.qtn_set_memory_budget(self.handle, int(nbytes)))
+        self._ws.clear()
+
     def tuning(self) -> dict:
         t = L.Tuning()
         L.check(self._lib.qtn_get_tuning(self.handle, C.byref(t)))

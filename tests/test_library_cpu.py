@@ -72,7 +72,7 @@ def test_plan_invariants(name, order):
     assert info["n_cones"] == len(w.edges)
     assert info["max_width"] == st["width"].max()
     assert info["n_buckets"] == st["n_buckets"].sum()
-    assert info["ws_grad"] > info["ws_fwd"] > 0
+    assert info["ws_grad"] >= info["ws_fwd"] > 0
     assert info["n_items_fwd"] >= len(w.edges)
 
 
@@ -129,3 +129,29 @@ def test_empty_and_degenerate_graphs_plan():
     net.validate()
     st = net.cone_stats()
     assert st["n_qubits"][0] == 2
+
+
+def test_memory_budget_checkpointing_plan():
+    """A workspace budget below the keep-everything arena makes the planner
+    drop bucket outputs after the forward sweep and recompute them in the
+    adjoint sweep; the plan stays valid, fits, and the budget is released by 0.
+    An unreachable budget is refused and leaves no limit behind."""
+    w = workload("p3_n244")
+    net = QaoaNet(w.n, w.edges[:60], w.p, dtype="c64", order="min_fill", device=None)
+    full = net.info()
+    assert full["n_recomputed"] == 0 and full["rec_bytes"] == 0
+    keep = full["ws_grad"]
+    budget = int(0.95 * full["arena_keep_all"])
+    net.set_memory_budget(budget)
+    net.validate()
+    cut = net.info()
+    assert cut["n_recomputed"] > 0 and cut["rec_bytes"] > 0
+    assert cut["ws_grad"] - (keep - full["arena_keep_all"]) <= budget
+    assert cut["fwd_bytes"] == full["fwd_bytes"] and cut["bwd_bytes"] == full["bwd_bytes"]
+    net.set_memory_budget(0)
+    assert net.info()["n_recomputed"] == 0 and net.info()["ws_grad"] == keep
+    with pytest.raises(QtnError) as ei:
+        net.set_memory_budget(1024)
+    assert ei.value.status == L.QTN_ENOMEM
+    assert net.info()["n_recomputed"] == 0 and net.info()["ws_grad"] == keep
+    net.validate()
