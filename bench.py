@@ -53,10 +53,11 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(w, budget_s: float = 15.0):
-    """The oracle's tensor-network contraction (numpy, complex128) of sampled
-    edge terms with the gradient by central differences (4p + 1 contractions
-    per edge, the oracle as it stands), one process per host core."""
+def cpu_baseline(w, budget_s: float = 12.0):
+    """The oracle's tensor-network contraction (numpy, complex128) of the edge
+    terms with the gradient by central differences (4p + 1 contractions per
+    edge, the oracle as it stands), one process per host core, in passes over
+    the edges in a seeded order until budget_s has elapsed."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
@@ -71,18 +72,18 @@ def cpu_baseline(w, budget_s: float = 15.0):
     done = 0
     with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
         i = 0
-        while i < len(order) and (time.perf_counter() - t0) < budget_s:
-            batch = [ex.submit(_oracle_edge_grad, w.n, w.edges, w.gamma, w.beta, w.edges[int(e)], h)
-                     for e in order[i:i + cores]]
+        while (time.perf_counter() - t0) < budget_s:
+            idx = [int(order[(i + k) % len(order)]) for k in range(cores)]
+            batch = [ex.submit(_oracle_edge_grad, w.n, w.edges, w.gamma, w.beta, w.edges[e], h) for e in idx]
             for f in batch:
                 f.result()
             done += len(batch)
             i += cores
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "edge light-cones/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} of {len(w.edges)} edges (first in a seeded permutation), numpy einsum bucket "
-                      f"elimination in complex128, energy + gradient by central differences "
-                      f"({4 * p + 1} contractions per edge), {cores} worker processes, {dt:.1f} s"}
+            "sample": f"{done} edge light cones ({done / len(w.edges):.1f} passes over the {len(w.edges)} edges in a "
+                      f"seeded order), numpy einsum bucket elimination in complex128, energy + gradient by central "
+                      f"differences ({4 * p + 1} contractions per edge), {cores} worker processes, {dt:.1f} s"}
 
 
 def _oracle_edge_grad(n, edges, gamma, beta, edge, h):
@@ -123,8 +124,9 @@ def time_sweeps(net, steps: int, warmup: int, mode: str = "batched"):
     return dt, e, k_ms / max(k_cnt, 1), k_cnt
 
 
-def wide_leg(repeats: int, steps: int):
-    """p = 5, N = 1000 (1500 edges), c64: the HBM-bound workload."""
+def wide_leg(repeats: int, steps: int, copy_gbps):
+    """p = 5, N = 1000 (1500 edges), c64, min-degree randomized greedy order
+    (widths up to 26, 0.5 GB tensors): the HBM-bound workload."""
     import torch
 
     from paper_2106_15740_amd import QaoaNet
@@ -132,26 +134,32 @@ def wide_leg(repeats: int, steps: int):
 
     w = workload("p5_n1000")
     t0 = time.perf_counter()
-    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=0, repeats=repeats)
+    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_degree", device=0, repeats=repeats)
     plan_s = time.perf_counter() - t0
     net.set_tuning(seq_max_bits=14, tile_blocks=64)
     net.set_params(w.gamma, w.beta)
     info = net.info()
     dt, e, k_ms, _ = time_sweeps(net, steps, 1)
+    pk_ms = net.time_persistent(with_grad=True, reps=2)
     alg = info["fwd_bytes"] + info["bwd_bytes"]
     wb, wms, wn = net.time_wide_ops(min_width=20, with_grad=True, reps=2)
     out = {
-        "workload": f"QAOA-MaxCut p=5, random 3-regular N=1000 (1500 edges), c64, min-fill randomized greedy "
+        "workload": f"QAOA-MaxCut p=5, random 3-regular N=1000 (1500 edges), c64, min-degree randomized greedy "
                     f"({repeats} repeats), batched energy + gradient",
         "edge_light_cones_per_s": len(w.edges) * steps / dt,
         "ms_per_step": 1e3 * dt / steps,
         "max_width": info["max_width"],
         "alg_bytes_per_sweep": alg,
-        "achieved_GBps": alg / (k_ms * 1e-3) / 1e9,
-        "frac_of_peak": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "sweep_ms": k_ms,
+        "persistent_kernel_ms": pk_ms,
+        "achieved_GBps": alg / (pk_ms * 1e-3) / 1e9,
+        "frac_of_peak": alg / (pk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "frac_of_copy": alg / (pk_ms * 1e-3) / 1e9 / copy_gbps if copy_gbps else None,
+        "workspace_GB": info["ws_grad"] / 1e9,
         "width_ge_20": {"ops": wn, "alg_bytes": wb, "ms": wms,
                         "achieved_GBps": (wb / (wms * 1e-3) / 1e9) if wms else None,
                         "frac_of_peak": (wb / (wms * 1e-3) / 1e9 / HBM_PEAK_GBS) if wms else None,
+                        "frac_of_copy": (wb / (wms * 1e-3) / 1e9 / copy_gbps) if (wms and copy_gbps) else None,
                         "method": "each contraction op of a bucket with output rank >= 20 launched alone, "
                                   "2 replays between HIP events"},
         "energy": e,
@@ -166,42 +174,81 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="p3_n244")
     ap.add_argument("--repeats", type=int, default=10,
                     help="randomized greedy order: runs per cone on top of the deterministic one (0: deterministic)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--tuning", default="",
+                    help="fixed tile shapes instead of the autotuner, e.g. threads=128,lane_cap=7,seq_max_bits=14")
     ap.add_argument("--no-wide", action="store_true", help="skip the p=5 N=1000 leg")
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-other-order", dest="other_order", action="store_false",
+                    help="skip the headline workload under the other greedy order")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the light-cone sweep is not sharded across GPUs in this "
-              "build (DESIGN.md describes how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the light-cone sweep is not sharded across GPUs; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from workloads import workload
 
     w = workload(args.workload)
-    # the CPU leg forks worker processes, so it runs before the GPU is touched
-    cpu = None if args.no_cpu else cpu_baseline(w)
+    if args.cpu_only:
+        print(json.dumps(cpu_baseline(w)))
+        return
+    # the CPU leg runs in a child process (which forks its workers) and ends
+    # before this process touches the GPU
+    cpu = None
+    if not args.no_cpu:
+        import subprocess
+
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only", "--workload", args.workload],
+                           capture_output=True, text=True, check=True)
+        cpu = json.loads(r.stdout.strip().splitlines()[-1])
 
     import torch
 
-    from paper_2106_15740_amd import QaoaNet
+    from paper_2106_15740_amd import QaoaNet, copy_bandwidth
 
     t0 = time.perf_counter()
     net = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=w.order, device=0, repeats=args.repeats)
     plan_s = time.perf_counter() - t0
     net.set_params(w.gamma, w.beta)
-    tuned = net.tuning() if args.no_autotune else net.autotune(with_grad=True)
+    if args.tuning:
+        net.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+        tuned = net.tuning()
+    else:
+        tuned = net.tuning() if args.no_autotune else net.autotune(with_grad=True)
     info = net.info()
 
     dt, e, k_avg_ms, k_cnt = time_sweeps(net, args.steps, args.warmup)
     ms_step = 1e3 * dt / args.steps
     cones_per_s = len(w.edges) * args.steps / dt
+    # the dominant kernel alone: HIP events around the persistent kernel on
+    # the launch stream (sweeps enqueued without graph capture)
+    pk_ms = net.time_persistent(with_grad=True, reps=20)
+
+    other = None
+    if args.other_order:
+        # the same workload under the other greedy order (same tile shapes)
+        o2 = "min_degree" if w.order == "min_fill" else "min_fill"
+        net2 = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=o2, device=0, repeats=args.repeats)
+        net2.set_params(w.gamma, w.beta)
+        net2.set_tuning(**{k: v for k, v in tuned.items()})
+        i2 = net2.info()
+        dt2, _, k2, _ = time_sweeps(net2, args.steps, args.warmup)
+        other = {"order": o2, "max_width": i2["max_width"], "edge_light_cones_per_s": len(w.edges) * args.steps / dt2,
+                 "ms_per_step": 1e3 * dt2 / args.steps,
+                 "alg_GBps": (i2["fwd_bytes"] + i2["bwd_bytes"]) / (k2 * 1e-3) / 1e9}
+        del net2
+
+    # achievable-bandwidth reference, after the timed steps
+    copy_gbps = copy_bandwidth(1 << 30, reps=5)
 
     plain_ms = None
     if args.plain_steps > 0:
@@ -215,7 +262,7 @@ def main():
         torch.cuda.synchronize()
 
     alg_bytes = info["fwd_bytes"] + info["bwd_bytes"]
-    achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9 if k_cnt else None
+    achieved = alg_bytes / (pk_ms * 1e-3) / 1e9 if pk_ms > 0 else None
     out = {
         "metric": "edge light-cones/sec (energy+grad) & HBM GB/s vs plain loop, 3-regular p=3",
         "value": cones_per_s,
@@ -238,12 +285,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(),
-                     "kernel": "persistent_kernel", "kernel_ms": k_avg_ms,
+                     "kernel": "persistent_kernel", "kernel_ms": pk_ms, "sweep_ms": k_avg_ms,
                      "alg_bytes_per_launch": alg_bytes,
+                     "copy_kernel_GBps": copy_gbps,
+                     "frac_of_copy": (achieved / copy_gbps) if achieved else None,
                      "note": "p=3 sweeps are cache- and LDS-resident: latency-bound, not HBM-bound"},
         "plain_loop": None if plain_ms is None else {
             "ms_per_step": plain_ms, "edge_light_cones_per_s": len(w.edges) / (plain_ms * 1e-3),
             "speedup_batched_vs_plain": plain_ms / ms_step},
+        "other_order": other,
         "energy": e,
         "plan_s": plan_s,
         "tuning": tuned,
@@ -251,7 +301,7 @@ def main():
     if not args.no_wide:
         del net
         torch.cuda.empty_cache()
-        out["wide"] = wide_leg(args.repeats, steps=3)
+        out["wide"] = wide_leg(args.repeats, steps=3, copy_gbps=copy_gbps)
     if cpu is not None:
         cpu["gpu_speedup"] = cones_per_s / cpu["value"]
         out["cpu_baseline"] = cpu

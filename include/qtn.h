@@ -191,6 +191,22 @@ qtn_status qtn_kernel_time(qtn_net* net, double* ms_sum, int64_t* count, int32_t
 qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width, void* workspace, size_t ws_bytes,
                              void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out);
 
+/* Device time of the persistent kernel alone: `reps` batched sweeps (after
+ * one warm-up) are enqueued on `stream` without graph capture, each with HIP
+ * events right before and after the persistent kernel; *ms_out is their
+ * average.  Needs qtn_set_params and a workspace as for the sweep.  QTN_EDEVICE
+ * if a sweep's dependency wait gave up. */
+qtn_status qtn_time_persistent(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
+                               int32_t reps, double* ms_out);
+
+/* Achievable-bandwidth reference: the library's plain copy kernel copies the
+ * first half of the caller's device buffer `buf` (`bytes` long, 16-byte
+ * aligned) onto its second half, `reps` times on `stream` after one warm-up,
+ * between HIP events.  *gbps_out = (bytes read + bytes written) per copy /
+ * average device time.  The buffer's contents are overwritten.  QTN_EINVAL for
+ * a null buffer, fewer than 32 bytes or reps < 1. */
+qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* stream, int32_t reps, double* gbps_out);
+
 void qtn_net_free(qtn_net* net);
 
 #ifdef __cplusplus

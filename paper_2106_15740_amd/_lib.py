@@ -21,7 +21,8 @@ EXPORTS = [
     "qtn_workspace_size",
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
-    "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_net_free",
+    "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
+    "qtn_net_free",
 ]
 
 
@@ -86,6 +87,8 @@ def lib() -> C.CDLL:
         "qtn_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64), I32]),
         "qtn_set_memory_budget": (I32, [P, SZ]),
         "qtn_time_wide_ops": (I32, [P, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)]),
+        "qtn_copy_bandwidth": (I32, [P, P, SZ, P, I32, C.POINTER(D)]),
+        "qtn_time_persistent": (I32, [P, I32, P, SZ, P, I32, C.POINTER(D)]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

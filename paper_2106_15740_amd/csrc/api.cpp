@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdint>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -72,10 +73,13 @@ struct qtn_net {
   // host staging (pinned)
   void* h_leafvals = nullptr;
   double* h_fin = nullptr;
+  void* dh_leafvals = nullptr;  // device addresses of the two mapped pinned host buffers
+  void* dh_fin = nullptr;
   size_t leaf_bytes = 0;
   bool params_set = false;
   int grid = 0;
   int max_nin = 1;
+  bool has_wide = false;  // some op carries F_WIDE
   GraphCache graph[2];
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
   bool ev_pending = false;
@@ -102,6 +106,13 @@ WsLayout ws_layout(const qtn_net* n, bool grad) {
   L.arena_off = L.ctl_off + align256((2 + nn) * sizeof(int32_t));
   L.total = L.arena_off + align256((size_t)(grad ? n->P.arena_grad : n->P.arena_fwd) * n->elem);
   return L;
+}
+
+// Bytes copied back after every sweep: the fin block (E, dE/dgamma,
+// dE/dbeta) through the queue head and error flag of the ctl block.
+size_t fin_copy_bytes(const qtn_net* n) {
+  const WsLayout L = ws_layout(n, true);
+  return (L.ctl_off - L.fin_off) + 2 * sizeof(int32_t);
 }
 
 void free_device_plan(qtn_net* n) {
@@ -138,6 +149,8 @@ qtn_status rebuild_programs(qtn_net* n) {
   n->max_nin = 1;
   for (const OpDesc& d : n->P.ops)
     if (d.kind == OP_CONTRACT) n->max_nin = std::max(n->max_nin, (int)d.n_in);
+  n->has_wide = false;
+  for (const OpDesc& d : n->P.ops) n->has_wide |= d.kind == OP_CONTRACT && (d.flags & F_WIDE);
   if (n->ctx->device < 0) {  // host-only context: plan without upload
     for (int g = 0; g < 2; ++g)
       n->prog[g].n_nodes = (int32_t)(g ? n->P.node_init_grad.size() : n->P.node_init_fwd.size());
@@ -173,15 +186,17 @@ Env make_env(qtn_net* n, char* ws, const WsLayout& L) {
   return e;
 }
 
-// Enqueue one complete sweep on stream st (no host synchronisation).
-qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t st, void* zz_out) {
+// Enqueue one complete sweep on stream st (no host synchronisation).  With
+// pk0/pk1 (not under capture) the persistent kernel is bracketed by them.
+qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t st, void* zz_out,
+                         hipEvent_t pk0 = nullptr, hipEvent_t pk1 = nullptr) {
   const WsLayout L = ws_layout(n, grad);
   char* w = static_cast<char*>(ws);
   Env env = make_env(n, w, L);
   // kernel launches report through hipGetLastError: drop any error left
   // behind by unrelated earlier calls on this thread
   (void)hipGetLastError();
-  HIPCHECK(hipMemcpyAsync(n->d_leafvals, n->h_leafvals, n->leaf_bytes, hipMemcpyHostToDevice, st));
+  HIPCHECK(launch_small_copy(n->dh_leafvals, n->d_leafvals, n->leaf_bytes, st));
   const TuneParams& T = n->P.tune;
   HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, n->P.leaf_hi, env, T.threads, st));
   if (mode == QTN_PLAIN) {
@@ -207,13 +222,17 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
     HIPCHECK(launch_reset(ctl, pg.init, pg.n_nodes, st));
     const int grid = std::max(1, std::min<int>(n->grid, std::max(1, pg.n_items)));
     const size_t lds_bytes = (size_t)n->P.lds_elems * n->elem;
-    HIPCHECK(launch_persistent(n->c128, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env, T.threads, grid,
-                               lds_bytes, kSpinLimit, st));
+    if (pk0) HIPCHECK(hipEventRecord(pk0, st));
+    HIPCHECK(launch_persistent(n->c128, n->has_wide, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env,
+                               T.threads, grid, lds_bytes, kSpinLimit, st));
+    if (pk1) HIPCHECK(hipEventRecord(pk1, st));
   }
   if (grad) HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, n->P.lgrad_hi, env, T.threads, st));
   HIPCHECK(launch_final(n->c128, env.res, env.res_stride, (int)n->P.cones.size(), n->P.p, grad ? 1 : 0, zz_out,
                         reinterpret_cast<double*>(w + L.fin_off), st));
-  HIPCHECK(hipMemcpyAsync(n->h_fin, w + L.fin_off, (1 + 2 * n->P.p) * sizeof(double), hipMemcpyDeviceToHost, st));
+  // E, dE/dtheta and, right after them in the workspace, the queue head and
+  // the persistent kernel's error flag: one copy
+  HIPCHECK(launch_small_copy(w + L.fin_off, n->dh_fin, fin_copy_bytes(n), st));
   return QTN_OK;
 }
 
@@ -271,7 +290,11 @@ qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes,
   }
   HIPCHECK(hipEventRecord(n->ev_done, st));
   if (want_host) {
-    HIPCHECK(hipEventSynchronize(n->ev_done));
+    // poll rather than block: a blocking wait can add a scheduler wake-up
+    // (up to a millisecond) to every sweep
+    hipError_t q;
+    while ((q = hipEventQuery(n->ev_done)) == hipErrorNotReady) std::this_thread::yield();
+    if (q != hipSuccess) return fail(QTN_EDEVICE, std::string("sweep: ") + hipGetErrorString(q));
     if (mode == QTN_BATCHED && n->ev_pending) {
       float ms = 0;
       if (hipEventElapsedTime(&ms, n->ev_k0, n->ev_k1) == hipSuccess) {
@@ -286,7 +309,8 @@ qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes,
     if (mode == QTN_BATCHED) {
       const WsLayout L = ws_layout(n, grad);
       int32_t flag = 0;
-      HIPCHECK(hipMemcpy(&flag, (char*)ws + L.ctl_off + sizeof(int32_t), sizeof(int32_t), hipMemcpyDeviceToHost));
+      std::memcpy(&flag, reinterpret_cast<const char*>(n->h_fin) + (L.ctl_off - L.fin_off) + sizeof(int32_t),
+                  sizeof(int32_t));
       if (flag) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
     }
   }
@@ -396,8 +420,10 @@ qtn_status qtn_order_rgreedy(qtn_net* n, qtn_order_kind kind, int32_t n_repeats,
     if (!n->d_leafvals) {
       n->leaf_bytes = 2 * (size_t)n_leaf_kinds(n->P.p) * 4 * n->elem;
       HIPCHECK(hipMalloc(&n->d_leafvals, n->leaf_bytes));
-      HIPCHECK(hipHostMalloc(&n->h_leafvals, n->leaf_bytes, hipHostMallocDefault));
-      HIPCHECK(hipHostMalloc((void**)&n->h_fin, (1 + 2 * n->P.p) * sizeof(double), hipHostMallocDefault));
+      HIPCHECK(hipHostMalloc(&n->h_leafvals, n->leaf_bytes, hipHostMallocMapped));
+      HIPCHECK(hipHostMalloc((void**)&n->h_fin, fin_copy_bytes(n), hipHostMallocMapped));
+      HIPCHECK(hipHostGetDevicePointer(&n->dh_leafvals, n->h_leafvals, 0));
+      HIPCHECK(hipHostGetDevicePointer(&n->dh_fin, n->h_fin, 0));
       HIPCHECK(hipEventCreate(&n->ev_k0));
       HIPCHECK(hipEventCreate(&n->ev_k1));
       HIPCHECK(hipEventCreateWithFlags(&n->ev_done, hipEventDisableTiming));
@@ -707,6 +733,66 @@ qtn_status qtn_time_wide_ops(qtn_net* n, int32_t with_grad, int32_t min_width, v
   if (bytes_out) *bytes_out = bytes;
   if (ms_out) *ms_out = ms_tot;
   if (n_ops_out) *n_ops_out = cnt;
+  return QTN_OK;
+}
+
+qtn_status qtn_time_persistent(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes, void* stream,
+                               int32_t reps, double* ms_out) {
+  qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
+  if (s != QTN_OK) return s;
+  if (reps < 1) return fail(QTN_EINVAL, "reps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  double tot = 0;
+  for (int r = 0; r <= reps && s == QTN_OK; ++r) {  // the first sweep warms up
+    s = enqueue_sweep(n, QTN_BATCHED, with_grad != 0, ws, st, nullptr, e0, e1);
+    if (s != QTN_OK) break;
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) s = fail(QTN_EDEVICE, std::string("persistent kernel timing: ") + hipGetErrorString(e));
+    if (r > 0) tot += ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != QTN_OK) return s;
+  HIPCHECK(hipStreamSynchronize(st));
+  int32_t flag = 0;
+  const WsLayout L = ws_layout(n, with_grad != 0);
+  std::memcpy(&flag, reinterpret_cast<const char*>(n->h_fin) + (L.ctl_off - L.fin_off) + sizeof(int32_t),
+              sizeof(int32_t));
+  if (flag) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
+  if (ms_out) *ms_out = tot / reps;
+  return QTN_OK;
+}
+
+qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* stream, int32_t reps, double* gbps_out) {
+  if (!ctx) return fail(QTN_EINVAL, "context is NULL");
+  if (ctx->device < 0) return fail(QTN_ESTATE, "host-only context has no device");
+  if (!buf || bytes < 32 || reps < 1) return fail(QTN_EINVAL, "need a device buffer of >= 32 bytes and reps >= 1");
+  if (reinterpret_cast<uintptr_t>(buf) % 16) return fail(QTN_EINVAL, "buffer must be 16-byte aligned");
+  HIPCHECK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n16 = bytes / 32;  // 16-byte words per half
+  char* src = static_cast<char*>(buf);
+  char* dst = src + n16 * 16;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  hipError_t e = launch_copy(src, dst, n16, st);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, n16, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("copy kernel: ") + hipGetErrorString(e));
+  if (gbps_out) *gbps_out = 2.0 * (double)(n16 * 16) * reps / (ms * 1e-3) / 1e9;
   return QTN_OK;
 }
 

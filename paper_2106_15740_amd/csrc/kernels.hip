@@ -307,6 +307,244 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
   }
 }
 
+// ------------------------------------------------------------------ wide ops
+// Executor of the ops flagged F_WIDE (buckets too wide for one workgroup).
+// Everything that decides the instruction stream is a template parameter, so
+// the step body has no branches between its loads: NIN inputs, S0 = 1 when
+// input 0 lacks the eliminated index (the output adjoint of an adjoint op;
+// every other input holds it and is loaded as a 16-byte pair), UU = 2^nu
+// outputs per thread.  All loads of a step are issued before the first use.
+// When the op has more per-thread output bits than UU covers (nu > log2 UU,
+// at most one more), the step repeats for the extra bit.  The block range
+// [blk_begin, blk_end) is an aligned power of two of at least one block per
+// sub-block; offsets fit 32 bits (tensor rank <= 30).
+template <typename R, int NIN, int S0, int UU>
+__device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                          int64_t blk_end, int64_t wg_rank, int64_t wg_count,
+                                          RedBuf<typename CT<R>::E>* __restrict__ red) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk;
+  const int sbits = 31 - __clz(blockDim.x >> nl);
+  const int sub = tid >> nl;
+  const int lane = tid & ((1 << nl) - 1);
+  const uint32_t out_mask = d.out_mask;
+  const bool out_pair = out_mask & 1u;
+  const bool atomic = d.flags & F_ATOMIC;
+  const bool ldsred = d.flags & F_LDSRED;
+  const uint32_t lane_sum = d.lane_sum;
+  uint32_t mask[NIN], loff[NIN];
+  const E* inp[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    inp[i] = arena + d.in_off[i];
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl && sh != LSH_NONE) o |= ((uint32_t)(lane >> j) & 1u) << sh;
+    }
+    loff[i] = o;
+  }
+  uint32_t lout = 0;
+#pragma unroll
+  for (int j = 0; j < MAXLANE; ++j) {
+    const uint32_t sh = d.lsh[MAXIN][j];
+    if (j < nl && sh != LSH_NONE) lout |= ((uint32_t)(lane >> j) & 1u) << sh;
+  }
+  // offsets of the UU outputs of a thread (unroll bits zbit[nl], zbit[nl + 1])
+  uint32_t us[NIN][UU], uo[UU];
+#pragma unroll
+  for (int i = 0; i <= NIN; ++i) {
+    const uint32_t m = i < NIN ? mask[i] : out_mask;
+    const uint32_t s0 = UU > 1 ? bit_stride(m, d.zbit[nl]) : 0u;
+    const uint32_t s1 = UU > 2 ? bit_stride(m, d.zbit[nl + 1]) : 0u;
+#pragma unroll
+    for (int k = 0; k < UU; ++k) {
+      const uint32_t v = ((k & 1) ? s0 : 0u) + ((k & 2) ? s1 : 0u);
+      if (i < NIN)
+        us[i][k] = v;
+      else
+        uo[k] = v;
+    }
+  }
+  E* outp = arena + d.out_off;
+  constexpr int NU = UU == 4 ? 2 : (UU == 2 ? 1 : 0);
+  const int nrep = d.nu > NU ? 2 : 1;
+  uint32_t rs[NIN], rso = 0;  // strides of the repeated output bit
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) rs[i] = nrep > 1 ? bit_stride(mask[i], d.zbit[nl + NU]) : 0u;
+  if (nrep > 1) rso = bit_stride(out_mask, d.zbit[nl + NU]);
+  const int zk0 = nl + d.nu, zb0 = nl + d.nu + nk;
+  const int nloop = 1 << nk;
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_st = lg_nblk - sbits;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_st - lg_chunk);
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t q0 = (uint32_t)ch << lg_chunk;
+    const uint32_t blk = base_blk + (q0 << sbits) + (uint32_t)sub;
+    uint32_t boff[NIN], bout = lout;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    for (int j = 0; j < d.nb; ++j)
+      if ((blk >> j) & 1u) {
+        const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+        bout += bit_stride(out_mask, u);
+      }
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      if (c) {
+        // Gray step: block bit sbits + t flips
+        const int t = __ffs(c) - 1;
+        const bool up = ((c ^ (c >> 1)) >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
+        }
+        const uint32_t so = bit_stride(out_mask, u);
+        bout = up ? bout + so : bout - so;
+      }
+#pragma unroll 1
+      for (int rep = 0; rep < nrep; ++rep) {
+      E acc0[UU], acc1[UU];
+#pragma unroll
+      for (int k = 0; k < UU; ++k) {
+        acc0[k] = E{0, 0};
+        acc1[k] = E{0, 0};
+      }
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = boff[i] + (rep ? rs[i] : 0u);
+      const uint32_t rout = bout + (rep ? rso : 0u);
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;  // Gray code over the summed loop bits
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
+        }
+        E a0[UU][NIN], a1[UU][NIN];
+#pragma unroll
+        for (int k = 0; k < UU; ++k)
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t o = koff[i] + us[i][k];
+            if (i == 0 && S0 == 1)
+              a0[k][i] = inp[i][o];
+            else
+              load_pair(inp[i] + o, a0[k][i], a1[k][i]);
+          }
+#pragma unroll
+        for (int k = 0; k < UU; ++k) {
+          E p0 = a0[k][0];
+          E p1 = S0 == 1 ? a0[k][0] : a1[k][0];
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) {
+            p0 = cmul(p0, a0[k][i]);
+            p1 = cmul(p1, a1[k][i]);
+          }
+          acc0[k] = cadd(acc0[k], p0);
+          acc1[k] = cadd(acc1[k], p1);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < UU; ++k) {
+        E s0 = acc0[k], s1 = acc1[k];
+        if (!out_pair) s0 = cadd(s0, s1);
+        if (lane_sum & 63u) {
+          for (int j = 0; j < 6; ++j)
+            if ((lane_sum >> j) & 1) {
+              s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+              if (out_pair) s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+            }
+        }
+        if (ldsred) {
+          // lanes of the same sub-block in other wavefronts: combine in LDS
+          __syncthreads();
+          red->v[2 * tid] = s0;
+          red->v[2 * tid + 1] = s1;
+          __syncthreads();
+          const uint32_t hi = lane_sum & ~63u;
+          if ((lane & hi) == 0)
+            for (uint32_t m = hi; m; m = (m - 1) & hi) {
+              s0 = cadd(s0, red->v[2 * (tid ^ (int)m)]);
+              s1 = cadd(s1, red->v[2 * (tid ^ (int)m) + 1]);
+            }
+        }
+        if ((lane & lane_sum) == 0) {
+          const uint32_t o = rout + uo[k];
+          if (out_pair) {
+            if (atomic) {
+              atomic_add_c(outp + o, s0);
+              atomic_add_c(outp + o + 1, s1);
+            } else {
+              store_pair(outp + o, s0, s1);
+            }
+          } else {
+            if (atomic)
+              atomic_add_c(outp + o, s0);
+            else
+              outp[o] = s0;
+          }
+        }
+      }
+      }
+    }
+  }
+}
+
+// Largest per-thread output count of the wide executor for element type R:
+// its own launches, and inside the persistent kernel (whose other state
+// competes for registers; the rest of the op's output bits repeat the step).
+template <typename R>
+struct WideMaxU {
+  static constexpr int value = sizeof(R) == 4 ? 4 : 2;
+  static constexpr int in_persistent = sizeof(R) == 4 ? 2 : 1;
+};
+
+template <typename R, int NIN, int S0>
+__device__ __forceinline__ void exec_wide_u(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                            int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
+  constexpr int M = WideMaxU<R>::in_persistent;
+  if (d.nu == 0 || M == 1)
+    exec_wide<R, NIN, S0, 1>(d, arena, b0, b1, r, c, red);
+  else
+    exec_wide<R, NIN, S0, M>(d, arena, b0, b1, r, c, red);
+}
+
+template <typename R>
+__device__ __forceinline__ void exec_wide_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                              int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
+  const bool s0 = !(d.in_mask[0] & 1u);
+  switch (d.n_in * 2 + (s0 ? 1 : 0)) {
+    case 2: exec_wide_u<R, 1, 0>(d, arena, b0, b1, r, c, red); break;
+    case 3: exec_wide_u<R, 1, 1>(d, arena, b0, b1, r, c, red); break;
+    case 4: exec_wide_u<R, 2, 0>(d, arena, b0, b1, r, c, red); break;
+    case 5: exec_wide_u<R, 2, 1>(d, arena, b0, b1, r, c, red); break;
+    case 6: exec_wide_u<R, 3, 0>(d, arena, b0, b1, r, c, red); break;
+    case 7: exec_wide_u<R, 3, 1>(d, arena, b0, b1, r, c, red); break;
+    case 8: exec_wide_u<R, 4, 0>(d, arena, b0, b1, r, c, red); break;
+    default: exec_wide_u<R, 4, 1>(d, arena, b0, b1, r, c, red); break;
+  }
+}
+
 template <typename R, int MAXNIN, bool USE_LDS>
 __device__ __forceinline__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
                                                   int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red,
@@ -455,7 +693,7 @@ __device__ __forceinline__ void exec_zero(const OpDesc& d, typename CT<R>::E* ar
 
 // MAXNIN < 0: contraction ops have exactly -MAXNIN inputs (plain launches are
 // specialised per input count on the host); else up to MAXNIN inputs.
-template <typename R, int MAXNIN, bool USE_LDS = false>
+template <typename R, int MAXNIN, bool USE_LDS = false, bool WIDE = false>
 __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank,
                                         int64_t wg_count, RedBuf<typename CT<R>::E>* red,
                                         typename CT<R>::E* lds = nullptr) {
@@ -463,6 +701,12 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
   E* arena = reinterpret_cast<E*>(env.arena);
   switch (d.kind) {
     case OP_CONTRACT:
+      if constexpr (WIDE && !USE_LDS) {
+        if (d.flags & F_WIDE) {
+          exec_wide_any<R>(d, arena, b0, b1, wg_rank, wg_count, red);
+          break;
+        }
+      }
       if constexpr (MAXNIN < 0)
         exec_contract<R, -MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
       else
@@ -482,15 +726,41 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
 
 // ------------------------------------------------------------------ kernels
 // One op per launch (the plain per-edge loop).
+// The descriptor is staged in LDS: the executors read its bit tables inside
+// their loops, and an LDS read does not wait for the loads in flight.
+__device__ __forceinline__ void stage_desc(OpDesc& sd, const OpDesc* ops, int op) {
+  constexpr int W = sizeof(OpDesc) / sizeof(uint4);
+  if (threadIdx.x < W) reinterpret_cast<uint4*>(&sd)[threadIdx.x] = reinterpret_cast<const uint4*>(ops + op)[threadIdx.x];
+  __syncthreads();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs: give each XCD a
+// contiguous range of logical workgroups (and so of blocks), so blocks that
+// share input data meet in the same L2.
+__device__ __forceinline__ int64_t xcd_rank() {
+  const int64_t G = gridDim.x;
+  const int64_t w = blockIdx.x;
+  return G % 8 == 0 ? (w % 8) * (G / 8) + w / 8 : w;
+}
+
 template <typename R, int NIN>
 __global__ void __launch_bounds__(512) op_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
   __shared__ RedBuf<typename CT<R>::E> red;
-  const OpDesc& d = ops[op];
+  __shared__ OpDesc d;
+  stage_desc(d, ops, op);
   const int64_t nblocks = int64_t(1) << d.nb;
-  const int64_t G = gridDim.x;
-  int64_t w = blockIdx.x;
-  if (G % 8 == 0) w = (w % 8) * (G / 8) + w / 8;
-  exec_contract<R, NIN>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, w, G, &red);
+  exec_contract<R, NIN>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x, &red);
+}
+
+// One F_WIDE op per launch, specialised like the executor.
+template <typename R, int NIN, int S0, int UU>
+__global__ void __launch_bounds__(512) wide_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  __shared__ RedBuf<typename CT<R>::E> red;
+  __shared__ OpDesc d;
+  stage_desc(d, ops, op);
+  const int64_t nblocks = int64_t(1) << d.nb;
+  exec_wide<R, NIN, S0, UU>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x,
+                            &red);
 }
 
 // Leaf tables, results, zeroing and leaf gradients (one op per launch).
@@ -498,14 +768,7 @@ template <typename R>
 __global__ void __launch_bounds__(512) misc_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
   __shared__ RedBuf<typename CT<R>::E> red;
   const OpDesc& d = ops[op];
-  const int64_t nblocks = 1;
-  // workgroups are dispatched round-robin over the 8 XCDs: give each XCD a
-  // contiguous range of logical workgroups (and so of blocks), so blocks that
-  // share input data meet in the same L2
-  const int64_t G = gridDim.x;
-  int64_t w = blockIdx.x;
-  if (G % 8 == 0) w = (w % 8) * (G / 8) + w / 8;
-  exec_op<R, 1>(d, env, 0, nblocks, w, G, &red);
+  exec_op<R, 1>(d, env, 0, 1, xcd_rank(), gridDim.x, &red);
 }
 
 constexpr int DESC_CHUNK = 16;
@@ -514,7 +777,9 @@ constexpr int DESC_CHUNK = 16;
 // order; an item waits until its node counter is zero, runs, then releases
 // its successor nodes.  Every item waits only on items earlier in the queue,
 // which were already taken by running workgroups, so the sweep always drains.
-template <typename R, int MAXNIN>
+// WIDE: the plan has F_WIDE ops (a separate instantiation keeps the register
+// budget of narrow-only sweeps unchanged).
+template <typename R, int MAXNIN, bool WIDE>
 __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items,
                                                           int n_items, const int32_t* __restrict__ succ, int32_t* ctl,
                                                           Env env, long long spin_limit) {
@@ -584,7 +849,7 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
             if (lds)
               exec_op<R, MAXNIN, true>(d, env, b0, b1, 0, 1, &red, lds);
             else
-              exec_op<R, MAXNIN, false>(d, env, b0, b1, 0, 1, &red);
+              exec_op<R, MAXNIN, false, WIDE>(d, env, b0, b1, 0, 1, &red);
           }
           __syncthreads();
         }
@@ -662,6 +927,21 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
   }
 }
 
+// Copy of a few hundred bytes between device memory and mapped pinned host
+// memory (leaf values in, results out): a kernel node keeps the sweep's
+// graph free of copy-engine transfers and their start-up latency.
+__global__ void __launch_bounds__(256) small_copy_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                         int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Plain device copy (16-byte words, grid-stride): the achievable-bandwidth
+// reference the contraction kernels are compared against.
+__global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Resets the queue head, the error flag and the node counters (a kernel, not
 // a memset, so the sweep can be captured in a graph).
 __global__ void reset_ctl_kernel(int32_t* ctl, const int32_t* __restrict__ init, int n_nodes) {
@@ -718,6 +998,34 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
     hipLaunchKernelGGL((misc_kernel<R>), g, b, 0, st, d_ops, op, env);
     return hipGetLastError();
   }
+  if (h.flags & F_WIDE) {
+    const bool s0 = !(h.in_mask[0] & 1u);
+    const int uu = 1 << h.nu;
+#define QTN_WIDE(N, S, UU) hipLaunchKernelGGL((wide_kernel<R, N, S, UU>), g, b, 0, st, d_ops, op, env)
+#define QTN_WIDE_U(N, S)                              \
+  do {                                                \
+    if (uu == 1)                                      \
+      QTN_WIDE(N, S, 1);                              \
+    else if (uu == 2 || WideMaxU<R>::value < 4)       \
+      QTN_WIDE(N, S, 2);                              \
+    else                                              \
+      QTN_WIDE(N, S, WideMaxU<R>::value);             \
+  } while (0)
+    switch (h.n_in * 2 + (s0 ? 1 : 0)) {
+      case 2: QTN_WIDE_U(1, 0); break;
+      case 3: QTN_WIDE_U(1, 1); break;
+      case 4: QTN_WIDE_U(2, 0); break;
+      case 5: QTN_WIDE_U(2, 1); break;
+      case 6: QTN_WIDE_U(3, 0); break;
+      case 7: QTN_WIDE_U(3, 1); break;
+      case 8: QTN_WIDE_U(4, 0); break;
+      case 9: QTN_WIDE_U(4, 1); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef QTN_WIDE_U
+#undef QTN_WIDE
+    return hipGetLastError();
+  }
   switch (h.n_in) {
     case 1: hipLaunchKernelGGL((op_kernel<R, 1>), g, b, 0, st, d_ops, op, env); break;
     case 2: hipLaunchKernelGGL((op_kernel<R, 2>), g, b, 0, st, d_ops, op, env); break;
@@ -749,6 +1057,21 @@ hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const En
   return hipGetLastError();
 }
 
+hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 4 || bytes > (size_t(1) << 20)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(small_copy_kernel, dim3(1), dim3(256), 0, st, reinterpret_cast<const uint32_t*>(src),
+                     reinterpret_cast<uint32_t*>(dst), (int)(bytes / 4));
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t n16, hipStream_t st) {
+  if (n16 == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(8192), dim3(256), 0, st, reinterpret_cast<const uint4*>(src),
+                     reinterpret_cast<uint4*>(dst), n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st) {
   int grid = (n_nodes + 2 + 255) / 256;
   if (grid > 1024) grid = 1024;
@@ -756,38 +1079,43 @@ hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStrea
   return hipGetLastError();
 }
 
-template <typename R, int M>
+template <typename R, int M, bool W>
 static hipError_t launch_persistent_m(const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
                                       int32_t* ctl, const Env& env, int threads, int grid, size_t lds_bytes,
                                       long long spin_limit, hipStream_t st) {
   if (lds_bytes > 0) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&persistent_kernel<R, M>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&persistent_kernel<R, M, W>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((persistent_kernel<R, M>), dim3(grid), dim3(threads), lds_bytes, st, ops, items, n_items, succ,
-                     ctl, env, spin_limit);
+  hipLaunchKernelGGL((persistent_kernel<R, M, W>), dim3(grid), dim3(threads), lds_bytes, st, ops, items, n_items,
+                     succ, ctl, env, spin_limit);
   return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, bool W>
 static hipError_t launch_persistent_t(int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                                       const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
                                       size_t lds_bytes, long long spin_limit, hipStream_t st) {
   if (max_nin <= 3)
-    return launch_persistent_m<R, 3>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
+    return launch_persistent_m<R, 3, W>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
   if (max_nin <= 5)
-    return launch_persistent_m<R, 5>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
-  return launch_persistent_m<R, 8>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
+    return launch_persistent_m<R, 5, W>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
+  return launch_persistent_m<R, 8, W>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
 }
 
-hipError_t launch_persistent(bool c128, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
+hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
                              size_t lds_bytes, long long spin_limit, hipStream_t st) {
-  return c128 ? launch_persistent_t<double>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes,
-                                            spin_limit, st)
-              : launch_persistent_t<float>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes,
-                                           spin_limit, st);
+  if (c128)
+    return wide ? launch_persistent_t<double, true>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid,
+                                                    lds_bytes, spin_limit, st)
+                : launch_persistent_t<double, false>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid,
+                                                     lds_bytes, spin_limit, st);
+  return wide ? launch_persistent_t<float, true>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes,
+                                                 spin_limit, st)
+              : launch_persistent_t<float, false>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid,
+                                                  lds_bytes, spin_limit, st);
 }
 
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,

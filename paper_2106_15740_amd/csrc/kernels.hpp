@@ -22,10 +22,16 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
                      int max_grid, hipStream_t st);
 // ops [lo, hi) (OP_LEAF or OP_LEAFGRAD), one workgroup each
 hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st);
+// bytes (a multiple of 4, <= 1 MiB) from src to dst with one workgroup;
+// either side may be mapped pinned host memory
+hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+// n16 16-byte words from src to dst (non-overlapping)
+hipError_t launch_copy(const void* src, void* dst, size_t n16, hipStream_t st);
 hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st);
-// max_nin: the largest input count of any contraction op in the items.
-// lds_bytes: dynamic LDS window of LDS-resident items (0: none)
-hipError_t launch_persistent(bool c128, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
+// wide: some op carries F_WIDE; max_nin: the largest input count of any
+// contraction op in the items; lds_bytes: dynamic LDS window of LDS-resident
+// items (0: none)
+hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
                              size_t lds_bytes, long long spin_limit, hipStream_t st);
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,

@@ -24,6 +24,8 @@ enum OpFlags : int32_t {
   F_GRAD = 2,    // OP_RESULT also writes adjoint seeds
   F_LDSRED = 4,  // summed lane bits >= 6: partial sums are combined across wavefronts in LDS
   F_SYNC = 8,    // in a sequential program: barrier before this op (it depends on an op since the last one)
+  F_WIDE = 16,   // run by the wide-op executor: <= 4 inputs, inputs 1.. hold the eliminated index, every block
+                 // range it is given holds at least one block per sub-block
 };
 
 // A contraction op iterates the union index u of a bucket.  Bit 0 of u is the

@@ -378,7 +378,29 @@ struct Ctx {
 // Split the non-pair union bits of a contraction op into lanes, loop and
 // blocks (see OpDesc).  seq: the op runs inside one workgroup, so no summed
 // bit may become a block bit (no atomics).
+void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool wide, const TuneParams& T);
+
+// Splits the union bits of a contraction op into lanes, per-thread outputs,
+// the summation loop and blocks.  Ops outside sequential programs with at
+// most 4 inputs, all but input 0 holding the eliminated index, go to the wide
+// executor when every block range they are given (a tile of tile_blocks
+// blocks, or all blocks) holds at least one block per sub-block.
 void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T) {
+  bool wide = !seq && d.n_in <= 4;
+  for (int i = 1; i < d.n_in; ++i) wide = wide && (d.in_mask[i] & 1u) != 0;
+  if (wide) {
+    partition_bits_as(d, nbits, out_mask, seq, true, T);
+    const int64_t nsub = std::max(1, T.threads >> d.nl);
+    const int64_t nblk = int64_t(1) << d.nb;
+    if (std::min<int64_t>(std::max(1, T.tile_blocks), nblk) >= nsub) {
+      d.flags |= F_WIDE;
+      return;
+    }
+  }
+  partition_bits_as(d, nbits, out_mask, seq, false, T);
+}
+
+void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool wide, const TuneParams& T) {
   std::vector<int> freeb, sumb;
   for (int u = 1; u < nbits; ++u) ((out_mask >> u) & 1 ? freeb : sumb).push_back(u);
   const int max_lanes = std::min({T.lane_cap, MAXLANE, 31 - __builtin_clz((unsigned)std::max(T.threads, 1))});
@@ -398,8 +420,11 @@ void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const Tun
     // several outputs per thread: more loads in flight, block offsets amortised
     // (bounded by the register budget of the kernel variant for this input count)
     const int nin = d.n_in;
-    const int lim = (T.elem_bytes == 8 && nin <= 2) ? 1 : 0;
-    const int cap = std::min(T.unroll_cap, lim);
+    int cap;
+    if (wide)  // per-thread outputs only where nothing is summed beyond the lanes (and the pair)
+      cap = rsum.empty() ? (T.elem_bytes == 8 ? 2 : 1) : 0;
+    else
+      cap = std::min(T.unroll_cap, (T.elem_bytes == 8 && nin <= 2) ? 1 : 0);
     while ((int)unroll.size() < cap && rfree.size() > unroll.size() + 2) unroll.push_back(rfree[unroll.size()]);
     rfree.erase(rfree.begin(), rfree.begin() + unroll.size());
   }
@@ -1117,7 +1142,18 @@ std::string validate_plan(const Plan& P) {
     const OpDesc& d = P.ops[o];
     if (d.kind != OP_CONTRACT) continue;
     if (d.nl + d.nu + d.nk + d.nb != d.nbits - 1) return "op " + S(o) + "bit partition does not cover the union";
-    if (d.nu > ((P.tune.elem_bytes == 8 && d.n_in <= 2) ? 1 : 0)) return "op " + S(o) + "too many unroll bits";
+    if (d.flags & F_WIDE) {
+      if (d.nu > (P.tune.elem_bytes == 8 ? 2 : 1)) return "op " + S(o) + "too many unroll bits";
+      if (d.n_in > 4 || d.lds_mask) return "op " + S(o) + "wide op with more than 4 inputs or LDS operands";
+      for (int i = 1; i < d.n_in; ++i)
+        if (!(d.in_mask[i] & 1u)) return "op " + S(o) + "wide op input without the eliminated index";
+      const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
+      if (std::min<int64_t>(std::max(1, P.tune.tile_blocks), int64_t(1) << d.nb) < nsub)
+        return "op " + S(o) + "wide op block range smaller than a workgroup step";
+      if (d.nbits <= P.tune.seq_max_bits) return "op " + S(o) + "wide op inside a sequential program";
+    } else if (d.nu > ((P.tune.elem_bytes == 8 && d.n_in <= 2) ? 1 : 0)) {
+      return "op " + S(o) + "too many unroll bits";
+    }
     uint32_t seen = 0;
     bool summed_block = false;
     for (int z = 0; z < d.nbits - 1; ++z) {

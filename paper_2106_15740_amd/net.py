@@ -33,6 +33,21 @@ class Context:
             self.handle = None
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5, device: int = 0) -> float:
+    """GB/s (read + write) of the library's plain copy kernel over an nbytes
+    device buffer: the achievable-bandwidth reference."""
+    import torch
+
+    ctx = default_context(device)
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{device}")
+    g = C.c_double()
+    st = C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx._lib.qtn_copy_bandwidth(ctx.handle, C.c_void_p(buf.data_ptr()), buf.numel(), st, int(reps),
+                                        C.byref(g)))
+    del buf
+    return g.value
+
+
 _default_ctx = {}
 
 
@@ -204,6 +219,15 @@ class QaoaNet:
                                             C.c_void_p(ws.data_ptr()), ws.numel(), self._stream(), int(reps),
                                             C.byref(b), C.byref(ms), C.byref(n)))
         return b.value, ms.value, n.value
+
+    def time_persistent(self, with_grad: bool = True, reps: int = 10) -> float:
+        """Average device ms of the persistent kernel alone (sweeps enqueued
+        without graph capture, HIP events around that kernel)."""
+        ws = self._workspace(with_grad)
+        ms = C.c_double()
+        L.check(self._lib.qtn_time_persistent(self.handle, int(bool(with_grad)), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                              self._stream(), int(reps), C.byref(ms)))
+        return ms.value
 
     def kernel_time(self, reset: bool = False) -> Tuple[float, int]:
         ms = C.c_double()

@@ -270,3 +270,25 @@ def test_checkpointed_adjoint_under_memory_budget(mode):
         np.testing.assert_allclose(dg, dg_ref, atol=1e-9)
         np.testing.assert_allclose(db, db_ref, atol=1e-9)
     np.testing.assert_allclose(net.edge_results(), sv.zz_expectations(n, edges, g, b), atol=1e-10)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-10)])
+def test_wide_executor_plain_and_batched(dtype, tol):
+    """Buckets wider than seq_max_bits run in the wide-op executor (its own
+    launches in the plain loop; tiles inside the persistent sweep, with fewer
+    outputs per thread).  A low seq_max_bits sends most buckets of p = 4 light
+    cones there, with reductions over lanes, loops and blocks."""
+    w = workload("p4_n100")
+    net = make(w.n, w.edges, w.p, dtype, "min_fill", w.gamma, w.beta, seq_max_bits=9, lane_cap=6, tile_blocks=64)
+    ref = np.array([tn.zz_edge(w.n, w.edges, w.gamma, w.beta, j, k) for j, k in w.edges[:3]])
+    e_p, dg_p, db_p = net.energy_grad("plain")
+    zz_p = net.edge_results()
+    e_b, dg_b, db_b = net.energy_grad("batched")
+    zz_b = net.edge_results()
+    np.testing.assert_allclose(zz_p[:3], ref, atol=tol)
+    np.testing.assert_allclose(zz_b[:3], ref, atol=tol)
+    np.testing.assert_allclose(zz_b, zz_p, atol=tol)
+    assert abs(e_b - e_p) <= tol * abs(e_p)
+    gt = 1e-4 if dtype == "c64" else 1e-9
+    np.testing.assert_allclose(dg_b, dg_p, atol=gt * max(1, np.abs(dg_p).max()))
+    np.testing.assert_allclose(db_b, db_p, atol=gt * max(1, np.abs(db_p).max()))
