@@ -136,7 +136,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     t0 = time.perf_counter()
     net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_degree", device=0, repeats=repeats)
     plan_s = time.perf_counter() - t0
-    net.set_tuning(seq_max_bits=14, tile_blocks=64)
+    net.set_tuning(seq_max_bits=14, tile_blocks=64, par_bits=21)
     net.set_params(w.gamma, w.beta)
     info = net.info()
     dt, e, k_ms, _ = time_sweeps(net, steps, 1)

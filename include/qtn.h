@@ -62,6 +62,7 @@ typedef struct {
   int32_t loop_cap;     /* summed bits looped inside a thread before partial sums go to atomics */
   int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
   int32_t lds_kb;       /* LDS window (KiB) for light cones that run LDS-resident in the batched sweep (0: none) */
+  int32_t par_bits;     /* a split bucket aims at >= 2^par_bits threads before summing in per-thread loops (8..24) */
 } qtn_tuning;
 
 typedef struct {

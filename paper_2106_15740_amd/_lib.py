@@ -35,7 +35,7 @@ class QtnError(RuntimeError):
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("lane_cap", C.c_int32), ("seq_max_bits", C.c_int32),
                 ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32),
-                ("lds_kb", C.c_int32)]
+                ("lds_kb", C.c_int32), ("par_bits", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -612,6 +612,7 @@ qtn_status qtn_get_tuning(const qtn_net* n, qtn_tuning* out) {
   out->loop_cap = n->P.tune.loop_cap;
   out->grid = n->grid;
   out->lds_kb = n->P.tune.lds_kb;
+  out->par_bits = n->P.tune.par_bits;
   return QTN_OK;
 }
 
@@ -626,7 +627,9 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->loop_cap < 0 || t->loop_cap > 31) return fail(QTN_EINVAL, "loop_cap must be in 0..31");
   if (t->grid < 0) return fail(QTN_EINVAL, "grid must be >= 0");
   if (t->lds_kb < 0 || t->lds_kb > 128) return fail(QTN_EINVAL, "lds_kb must be in 0..128");
+  if (t->par_bits < 8 || t->par_bits > 24) return fail(QTN_EINVAL, "par_bits must be in 8..24");
   n->P.tune.threads = th;
+  n->P.tune.par_bits = t->par_bits;
   n->P.tune.lane_cap = t->lane_cap;
   n->P.tune.seq_max_bits = t->seq_max_bits;
   n->P.tune.tile_blocks = t->tile_blocks;

@@ -399,6 +399,13 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
         for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
         bout += bit_stride(out_mask, u);
       }
+    // partial sums carried across block steps that flip only summed bits
+    E acc0[UU], acc1[UU];
+#pragma unroll
+    for (int k = 0; k < UU; ++k) {
+      acc0[k] = E{0, 0};
+      acc1[k] = E{0, 0};
+    }
 #pragma unroll 1
     for (int c = 0; c < chunk; ++c) {
       if (c) {
@@ -414,14 +421,12 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
         const uint32_t so = bit_stride(out_mask, u);
         bout = up ? bout + so : bout - so;
       }
+      // keep accumulating when the next step of this chunk flips a summed
+      // bit (same outputs); nrep > 1 never has summed block bits
+      const bool carry = nrep == 1 && c + 1 < chunk &&
+                         bit_stride(out_mask, d.zbit[zb0 + sbits + __ffs(c + 1) - 1]) == 0u;
 #pragma unroll 1
       for (int rep = 0; rep < nrep; ++rep) {
-      E acc0[UU], acc1[UU];
-#pragma unroll
-      for (int k = 0; k < UU; ++k) {
-        acc0[k] = E{0, 0};
-        acc1[k] = E{0, 0};
-      }
       uint32_t koff[NIN];
 #pragma unroll
       for (int i = 0; i < NIN; ++i) koff[i] = boff[i] + (rep ? rs[i] : 0u);
@@ -464,9 +469,12 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
           acc1[k] = cadd(acc1[k], p1);
         }
       }
+      if (carry) continue;  // uniform
 #pragma unroll
       for (int k = 0; k < UU; ++k) {
         E s0 = acc0[k], s1 = acc1[k];
+        acc0[k] = E{0, 0};
+        acc1[k] = E{0, 0};
         if (!out_pair) s0 = cadd(s0, s1);
         if (lane_sum & 63u) {
           for (int j = 0; j < 6; ++j)

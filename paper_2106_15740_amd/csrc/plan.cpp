@@ -453,11 +453,22 @@ void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool w
     keyed.push_back({-w, u});
   }
   std::stable_sort(keyed.begin(), keyed.end());
-  for (auto& kv : keyed) blocks.push_back(kv.second);
   bool atomic = false;
-  for (size_t t = nk; t < rsum.size(); ++t) {
-    blocks.push_back(rsum[t]);
-    atomic = true;
+  if (wide) {
+    // wide ops: summed block bits vary fastest, so consecutive block steps of
+    // a workgroup add into the same outputs and the executor carries its
+    // partial sums across them (one atomic per output and run of steps)
+    for (size_t t = nk; t < rsum.size(); ++t) {
+      blocks.push_back(rsum[t]);
+      atomic = true;
+    }
+    for (auto& kv : keyed) blocks.push_back(kv.second);
+  } else {
+    for (auto& kv : keyed) blocks.push_back(kv.second);
+    for (size_t t = nk; t < rsum.size(); ++t) {
+      blocks.push_back(rsum[t]);
+      atomic = true;
+    }
   }
   d.nl = (int)lanes.size();
   d.nu = (int)unroll.size();

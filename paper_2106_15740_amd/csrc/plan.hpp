@@ -90,7 +90,7 @@ struct TuneParams {
   int tile_blocks = 8;      // blocks of a wide op handled by one queue item
   int loop_cap = 12;        // summed bits kept inside a thread before spilling to atomics
   int unroll_cap = 1;       // output bits handled inside one thread of a wide op (<= 1)
-  int par_bits = 19;        // a wide op aims at >= 2^par_bits threads
+  int par_bits = 21;        // a wide op aims at >= 2^par_bits threads
   int elem_bytes = 8;       // 8: complex64, 16: complex128 (set by build_programs)
   int lds_kb = 64;          // LDS window for LDS-resident cones (0: never)
 };
