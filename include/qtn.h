@@ -63,6 +63,9 @@ typedef struct {
   int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
   int32_t lds_kb;       /* LDS window (KiB) for light cones that run LDS-resident in the batched sweep (0: none) */
   int32_t par_bits;     /* a split bucket aims at >= 2^par_bits threads before summing in per-thread loops (8..24) */
+  int32_t merge_bits;   /* a bucket is merged into its consumer while the merged step's union has <= merge_bits
+                           bits (0: one step per bucket; at most 16) */
+  int32_t merge_lam_bits; /* ... and its leaf-product table carries <= merge_lam_bits indices (0..16) */
 } qtn_tuning;
 
 typedef struct {
@@ -70,7 +73,7 @@ typedef struct {
   int32_t p;
   int32_t max_width;        /* largest bucket output rank over all cones */
   int32_t dtype;            /* qtn_dtype */
-  int64_t n_buckets;        /* total buckets over all cones */
+  int64_t n_buckets;        /* total buckets over all cones (one per index) */
   int64_t n_ops_fwd;        /* device ops of the forward program */
   int64_t n_ops_grad;       /* device ops of the forward + adjoint program */
   int64_t n_items_fwd, n_items_grad;  /* persistent-queue items */
@@ -83,6 +86,7 @@ typedef struct {
   int64_t n_recomputed;     /* bucket outputs dropped after the forward sweep and recomputed in the adjoint */
   double rec_bytes;         /* extra bytes of those recomputations per gradient sweep (not algorithmic) */
   size_t arena_keep_all;    /* arena bytes the gradient sweep would need keeping every output */
+  int64_t n_steps;          /* contraction steps over all cones (buckets after merging small ones) */
 } qtn_info;
 
 /* Context bound to HIP device `device` (hipSetDevice is called on it).  Owns a
@@ -170,9 +174,12 @@ qtn_status qtn_set_memory_budget(qtn_net* net, size_t bytes);
 qtn_status qtn_get_tuning(const qtn_net* net, qtn_tuning* out);
 qtn_status qtn_set_tuning(qtn_net* net, const qtn_tuning* t);
 
-/* Project-written autotuner: times the batched sweep (with_grad as given) for
- * each candidate tile shape on `stream`, keeps the fastest and returns it in
- * *best (nullable).  Needs qtn_set_params first and a workspace as for the sweep. */
+/* Project-written autotuner: times the batched sweep (with_grad as given) on
+ * `stream` by coordinate descent over three groups (workgroup size and lane
+ * cap; split thresholds seq_max_bits and tile_blocks; merge_bits and
+ * merge_lam_bits), keeps the fastest setting and returns it in *best
+ * (nullable).  Needs qtn_set_params first and a workspace as for the sweep;
+ * settings whose workspace would not fit in ws_bytes are skipped. */
 qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
                         int32_t reps, qtn_tuning* best);
 

@@ -35,7 +35,8 @@ class QtnError(RuntimeError):
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("lane_cap", C.c_int32), ("seq_max_bits", C.c_int32),
                 ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32),
-                ("lds_kb", C.c_int32), ("par_bits", C.c_int32)]
+                ("lds_kb", C.c_int32), ("par_bits", C.c_int32), ("merge_bits", C.c_int32),
+                ("merge_lam_bits", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -47,7 +48,8 @@ class Info(C.Structure):
                 ("n_items_fwd", C.c_int64), ("n_items_grad", C.c_int64), ("fwd_bytes", C.c_double),
                 ("bwd_bytes", C.c_double), ("fwd_flops", C.c_double), ("ws_fwd", C.c_size_t),
                 ("ws_grad", C.c_size_t), ("n_lds_cones", C.c_int32), ("lds_window", C.c_int32),
-                ("n_recomputed", C.c_int64), ("rec_bytes", C.c_double), ("arena_keep_all", C.c_size_t)]
+                ("n_recomputed", C.c_int64), ("rec_bytes", C.c_double), ("arena_keep_all", C.c_size_t),
+                ("n_steps", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -566,7 +566,8 @@ qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
   out->max_width = n->P.max_width;
   for (size_t c = 0; c < n->P.cones.size(); ++c) {
     const Cone& C = n->P.cones[c];
-    out->n_buckets += (int64_t)C.buckets.size();
+    out->n_buckets += (int64_t)C.plain.size();
+    out->n_steps += (int64_t)C.buckets.size();
     out->fwd_bytes += C.fwd_bytes_alg;
     out->bwd_bytes += C.bwd_bytes_alg;
     out->fwd_flops += C.fwd_flops;
@@ -596,7 +597,7 @@ qtn_status qtn_cone_stats(const qtn_net* n, int32_t* width, int32_t* n_qubits, i
     if (n_qubits) n_qubits[c] = C.n_qubits;
     if (n_indices) n_indices[c] = C.n_idx;
     if (n_tensors) n_tensors[c] = (int32_t)C.leaves.size();
-    if (n_buckets) n_buckets[c] = (int32_t)C.buckets.size();
+    if (n_buckets) n_buckets[c] = (int32_t)C.plain.size();
     if (fwd_bytes) fwd_bytes[c] = C.fwd_bytes_alg;
     if (bwd_bytes) bwd_bytes[c] = C.bwd_bytes_alg;
   }
@@ -613,6 +614,8 @@ qtn_status qtn_get_tuning(const qtn_net* n, qtn_tuning* out) {
   out->grid = n->grid;
   out->lds_kb = n->P.tune.lds_kb;
   out->par_bits = n->P.tune.par_bits;
+  out->merge_bits = n->P.tune.merge_bits;
+  out->merge_lam_bits = n->P.tune.merge_lam_bits;
   return QTN_OK;
 }
 
@@ -628,8 +631,12 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->grid < 0) return fail(QTN_EINVAL, "grid must be >= 0");
   if (t->lds_kb < 0 || t->lds_kb > 128) return fail(QTN_EINVAL, "lds_kb must be in 0..128");
   if (t->par_bits < 8 || t->par_bits > 24) return fail(QTN_EINVAL, "par_bits must be in 8..24");
+  if (t->merge_bits < 0 || t->merge_bits > 16) return fail(QTN_EINVAL, "merge_bits must be in 0..16");
+  if (t->merge_lam_bits < 0 || t->merge_lam_bits > 16) return fail(QTN_EINVAL, "merge_lam_bits must be in 0..16");
   n->P.tune.threads = th;
   n->P.tune.par_bits = t->par_bits;
+  n->P.tune.merge_bits = t->merge_bits;
+  n->P.tune.merge_lam_bits = t->merge_lam_bits;
   n->P.tune.lane_cap = t->lane_cap;
   n->P.tune.seq_max_bits = t->seq_max_bits;
   n->P.tune.tile_blocks = t->tile_blocks;
@@ -648,40 +655,69 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
   hipStream_t st = (hipStream_t)stream;
   qtn_tuning base;
   qtn_get_tuning(n, &base);
-  std::vector<qtn_tuning> cand;
-  for (int th : {64, 128, 256, 512})
-    for (int lc : {6, 7, 8})
-      for (int sq : {12, 14, 16})
-        for (int tb : {16, 64}) {
-          if ((1 << lc) > th) continue;
-          qtn_tuning t = base;
-          t.threads = th;
-          t.lane_cap = lc;
-          t.seq_max_bits = sq;
-          t.tile_blocks = tb;
-          t.grid = 0;
-          cand.push_back(t);
-        }
-  double best_ms = 1e300;
-  qtn_tuning best = base;
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
-  for (const qtn_tuning& t : cand) {
-    if ((s = qtn_set_tuning(n, &t)) != QTN_OK) break;
-    if ((s = check_ready(n, ws, ws_bytes, with_grad != 0)) != QTN_OK) break;
-    if ((s = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, true)) != QTN_OK) break;
+  // time one candidate: a warm sweep (re-captures the graph) then `reps`
+  auto timed = [&](const qtn_tuning& t, double* ms_out) -> qtn_status {
+    qtn_status r;
+    if ((r = qtn_set_tuning(n, &t)) != QTN_OK) return r;
+    if (ws_layout(n, with_grad != 0).total > ws_bytes) {  // needs a larger workspace: not a candidate here
+      *ms_out = 1e300;
+      return QTN_OK;
+    }
+    if ((r = check_ready(n, ws, ws_bytes, with_grad != 0)) != QTN_OK) return r;
+    if ((r = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, true)) != QTN_OK) return r;
     HIPCHECK(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r)
-      if ((s = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, false)) != QTN_OK) break;
-    if (s != QTN_OK) break;
+    for (int k = 0; k < reps; ++k)
+      if ((r = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, false)) != QTN_OK) return r;
     HIPCHECK(hipEventRecord(e1, st));
     HIPCHECK(hipEventSynchronize(e1));
     float ms = 0;
     HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = t;
+    *ms_out = ms;
+    return QTN_OK;
+  };
+  // coordinate descent over three groups of parameters: workgroup shape,
+  // split thresholds of wide buckets, merging of small buckets
+  double best_ms = 1e300;
+  qtn_tuning best = base;
+  for (int stage = 0; stage < 3 && s == QTN_OK; ++stage) {
+    std::vector<qtn_tuning> cand;
+    const qtn_tuning b0 = best;
+    if (stage == 0) {
+      for (int th : {64, 128, 256, 512})
+        for (int lc : {6, 7, 8}) {
+          if ((1 << lc) > th) continue;
+          qtn_tuning t = b0;
+          t.threads = th;
+          t.lane_cap = lc;
+          t.grid = 0;
+          cand.push_back(t);
+        }
+    } else if (stage == 1) {
+      for (int sq : {12, 14, 16})
+        for (int tb : {16, 64}) {
+          qtn_tuning t = b0;
+          t.seq_max_bits = sq;
+          t.tile_blocks = tb;
+          cand.push_back(t);
+        }
+    } else {
+      for (auto mm : {std::pair<int, int>{0, 0}, {8, 6}, {10, 7}, {12, 7}, {12, 8}}) {
+        qtn_tuning t = b0;
+        t.merge_bits = mm.first;
+        t.merge_lam_bits = mm.second;
+        cand.push_back(t);
+      }
+    }
+    for (const qtn_tuning& t : cand) {
+      double ms = 0;
+      if ((s = timed(t, &ms)) != QTN_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
     }
   }
   (void)hipEventDestroy(e0);

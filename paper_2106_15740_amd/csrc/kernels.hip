@@ -109,8 +109,7 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
   const int tid = threadIdx.x;
   const int nl = d.nl, nu = d.nu, nk = d.nk;
   const int lanes = 1 << nl;
-  const int sbits = 31 - __clz(blockDim.x >> nl);  // log2(nsub)
-  const int nsub = 1 << sbits;
+  const int sbits = 31 - __clz(blockDim.x >> nl);  // log2(sub-blocks per workgroup)
   const int sub = tid >> nl;
   const int lane = tid & (lanes - 1);
   const uint32_t out_mask = d.out_mask;
@@ -880,6 +879,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+constexpr int LG_MAXL = 16;  // leaves per table handled by the linear-time leaf gradient
+
 template <typename R>
 __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env) {
   using E = typename CT<R>::E;
@@ -906,29 +907,92 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
         out[e] = pr;
       }
     } else if (d.kind == OP_LEAFGRAD) {
-      // dR/dtheta += sum_e Lbar[e] * (derivative of one leaf) * (the other leaves)
+      // dR/dtheta += sum_e Lbar[e] * (derivative of one leaf) * (the other
+      // leaves).  Up to LG_MAXL leaves: per entry, suffix products of the
+      // leaves, then one forward pass with the running prefix (3L complex
+      // multiplies instead of L^2); leaves come sorted by angle, so one
+      // atomic per angle.
       const E* lbar = arena + d.in_off[0];
       double* res = env.res + (int64_t)d.cone * env.res_stride;
-      for (int r = 0; r < d.aux1; ++r) {
-        const int slot = theta_slot(refs[r].kind, env.p);
-        if (slot < 0) continue;  // uniform across the wavefront
-        double ax = 0, ay = 0;
+      const int L = d.aux1;
+      if (L <= LG_MAXL) {
+        double ax[LG_MAXL], ay[LG_MAXL];
+#pragma unroll
+        for (int q = 0; q < LG_MAXL; ++q) ax[q] = ay[q] = 0.0;
         for (int64_t e = lane; e < n; e += 64) {
-          E t = lbar[e];
-          for (int q = 0; q < d.aux1; ++q) {
-            const LeafRef Ls = refs[q];
-            int idx = (e >> Ls.pa) & 1;
-            if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
-            t = cmul(t, q == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
+          E suf[LG_MAXL + 1];
+          suf[LG_MAXL] = E{1, 0};
+#pragma unroll
+          for (int q = LG_MAXL - 1; q >= 0; --q) {
+            if (q < L) {
+              const LeafRef Lq = refs[q];
+              int idx = (e >> Lq.pa) & 1;
+              if (Lq.pb >= 0) idx |= ((e >> Lq.pb) & 1) << 1;
+              suf[q] = cmul(vals[Lq.kind * 4 + idx], suf[q + 1]);
+            } else {
+              suf[q] = E{1, 0};
+            }
           }
-          ax += (double)t.x;
-          ay += (double)t.y;
+          E pre = lbar[e];
+#pragma unroll
+          for (int q = 0; q < LG_MAXL; ++q) {
+            if (q < L) {
+              const LeafRef Lq = refs[q];
+              int idx = (e >> Lq.pa) & 1;
+              if (Lq.pb >= 0) idx |= ((e >> Lq.pb) & 1) << 1;
+              const E t = cmul(cmul(pre, dvals[Lq.kind * 4 + idx]), suf[q + 1]);
+              ax[q] += (double)t.x;
+              ay[q] += (double)t.y;
+              pre = cmul(pre, vals[Lq.kind * 4 + idx]);
+            }
+          }
         }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0) {
-          atomicAdd(res + slot, ax);
-          atomicAdd(res + slot + 1, ay);
+        int cur = -1;
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int q = 0; q < LG_MAXL; ++q) {
+          if (q < L) {
+            const int slot = theta_slot(refs[q].kind, env.p);
+            if (slot < 0) continue;  // uniform across the wavefront
+            const double wx = wave_sum(ax[q]), wy = wave_sum(ay[q]);
+            if (slot != cur && cur >= 0 && lane == 0) {
+              atomicAdd(res + cur, sx);
+              atomicAdd(res + cur + 1, sy);
+            }
+            if (slot != cur) {
+              cur = slot;
+              sx = sy = 0;
+            }
+            sx += wx;
+            sy += wy;
+          }
+        }
+        if (cur >= 0 && lane == 0) {
+          atomicAdd(res + cur, sx);
+          atomicAdd(res + cur + 1, sy);
+        }
+      } else {
+        for (int r = 0; r < L; ++r) {
+          const int slot = theta_slot(refs[r].kind, env.p);
+          if (slot < 0) continue;  // uniform across the wavefront
+          double ax = 0, ay = 0;
+          for (int64_t e = lane; e < n; e += 64) {
+            E t = lbar[e];
+            for (int q = 0; q < L; ++q) {
+              const LeafRef Ls = refs[q];
+              int idx = (e >> Ls.pa) & 1;
+              if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
+              t = cmul(t, q == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
+            }
+            ax += (double)t.x;
+            ay += (double)t.y;
+          }
+          ax = wave_sum(ax);
+          ay = wave_sum(ay);
+          if (lane == 0) {
+            atomicAdd(res + slot, ax);
+            atomicAdd(res + slot + 1, ay);
+          }
         }
       }
     }

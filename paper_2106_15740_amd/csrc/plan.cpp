@@ -8,6 +8,8 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <functional>
+#include <iterator>
 #include <cstring>
 #include <cmath>
 #include <climits>
@@ -290,18 +292,17 @@ static void buckets_one(Cone& C) {
   const int n = C.n_idx;
   std::vector<int> pos(n);
   for (int s = 0; s < n; ++s) pos[C.order[s]] = s;
-  C.buckets.assign(n, Bucket());
+  C.plain.assign(n, Bucket());
   std::vector<std::vector<int>> out_idx(n);
   for (size_t li = 0; li < C.leaves.size(); ++li) {
     const Leaf& l = C.leaves[li];
     int first = l.b < 0 ? l.a : (pos[l.a] < pos[l.b] ? l.a : l.b);
-    C.buckets[pos[first]].leaves.push_back((int)li);
+    C.plain[pos[first]].leaves.push_back((int)li);
   }
-  C.scalars.clear();
   std::vector<std::vector<int>> pending(n);  // producer buckets waiting at each bucket
   int width = 0;
   for (int s = 0; s < n; ++s) {
-    Bucket& Bk = C.buckets[s];
+    Bucket& Bk = C.plain[s];
     Bk.v = C.order[s];
     Bk.in_bkt = pending[s];
     std::vector<int> uni = {Bk.v};
@@ -333,7 +334,6 @@ static void buckets_one(Cone& C) {
     out_idx[s].assign(uni.begin() + 1, uni.end());
     width = std::max(width, (int)uni.size() - 1);
     if (uni.size() == 1) {
-      C.scalars.push_back(s);
       Bk.consumer = -1;
     } else {
       Bk.consumer = pos[uni[1]];
@@ -341,6 +341,100 @@ static void buckets_one(Cone& C) {
     }
   }
   C.width = width;
+}
+
+
+// Contraction steps of a cone from its plain buckets.  In elimination order,
+// a bucket (with the buckets already merged into it) joins its consumer while
+// the merged union stays within merge_bits bits and the merged step has at
+// most MAXIN inputs: for buckets this small every step costs about the same
+// fixed time, so fewer steps are faster.  A merged step is the union of its
+// members' tensors summed over all of their eliminated indices (the same
+// contraction, Section III.B, taken several indices at a time).
+static void group_buckets(Cone& C, int merge_bits, int merge_lam_bits) {
+  const std::vector<Bucket>& Pl = C.plain;
+  const int n = (int)Pl.size();
+  std::vector<int> pos(C.n_idx);
+  for (int s = 0; s < n; ++s) pos[C.order[s]] = s;
+  std::vector<int> root(n), gsize(n), gelim(n, 1), gnin(n), glam(n);
+  std::vector<std::vector<int>> gleafidx(n);  // indices carried by the group's leaves
+  for (int b = 0; b < n; ++b) {
+    root[b] = b;
+    gsize[b] = Pl[b].nbits();
+    gnin[b] = (int)Pl[b].in_bkt.size();
+    glam[b] = Pl[b].lam_mask ? 1 : 0;
+    for (int li : Pl[b].leaves) {
+      gleafidx[b].push_back(C.leaves[li].a);
+      if (C.leaves[li].b >= 0) gleafidx[b].push_back(C.leaves[li].b);
+    }
+    std::sort(gleafidx[b].begin(), gleafidx[b].end());
+    gleafidx[b].erase(std::unique(gleafidx[b].begin(), gleafidx[b].end()), gleafidx[b].end());
+  }
+  std::function<int(int)> find = [&](int x) { return root[x] == x ? x : (root[x] = find(root[x])); };
+  if (merge_bits > 0)
+    for (int b = 0; b < n; ++b) {
+      const int t = Pl[b].consumer;  // b is still its group's root; t has not been merged anywhere yet
+      if (t < 0) continue;
+      const int size = gsize[t] + gelim[b];
+      const int nin = gnin[t] - 1 + gnin[b];
+      const int lam = glam[t] | glam[b];
+      if (size > merge_bits || nin + lam > MAXIN) continue;
+      // the merged leaf-product table (built and differentiated per entry)
+      // stays small
+      std::vector<int> li;
+      std::set_union(gleafidx[t].begin(), gleafidx[t].end(), gleafidx[b].begin(), gleafidx[b].end(),
+                     std::back_inserter(li));
+      if ((int)li.size() > merge_lam_bits) continue;
+      gleafidx[t] = li;
+      root[b] = t;
+      gsize[t] = size;
+      gelim[t] += gelim[b];
+      gnin[t] = nin;
+      glam[t] = lam;
+    }
+  std::vector<int> idx(n, -1);
+  int ng = 0;
+  for (int b = 0; b < n; ++b)
+    if (find(b) == b) idx[b] = ng++;
+  C.buckets.assign(ng, Bucket());
+  C.scalars.clear();
+  std::vector<std::vector<int>> members(ng);
+  for (int b = 0; b < n; ++b) members[idx[find(b)]].push_back(b);
+  for (int r = 0; r < n; ++r) {
+    if (idx[r] < 0) continue;
+    Bucket& G = C.buckets[idx[r]];
+    const std::vector<int>& mem = members[idx[r]];
+    G.v = Pl[mem[0]].v;
+    G.n_elim = (int)mem.size();
+    std::vector<int> uni;
+    for (int m : mem) uni.push_back(Pl[m].v);
+    uni.insert(uni.end(), Pl[r].uni.begin() + 1, Pl[r].uni.end());
+    std::sort(uni.begin(), uni.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+    G.uni = uni;
+    auto bit_of = [&](int x) {
+      for (size_t t = 0; t < uni.size(); ++t)
+        if (uni[t] == x) return (int)t;
+      return -1;
+    };
+    for (int m : mem) {
+      G.leaves.insert(G.leaves.end(), Pl[m].leaves.begin(), Pl[m].leaves.end());
+      for (int pb : Pl[m].in_bkt) {
+        const int g = find(pb);
+        if (g == r) continue;
+        G.in_bkt.push_back(idx[g]);
+        uint32_t mk = 0;
+        for (size_t q = 1; q < Pl[g].uni.size(); ++q) mk |= 1u << bit_of(Pl[g].uni[q]);
+        G.in_mask.push_back(mk);
+      }
+    }
+    G.lam_mask = 0;
+    for (int li : G.leaves) {
+      G.lam_mask |= 1u << bit_of(C.leaves[li].a);
+      if (C.leaves[li].b >= 0) G.lam_mask |= 1u << bit_of(C.leaves[li].b);
+    }
+    G.consumer = Pl[r].consumer < 0 ? -1 : idx[find(Pl[r].consumer)];
+    if (G.consumer < 0) C.scalars.push_back(idx[r]);
+  }
 }
 
 void order_cones(Plan& P, const OrderOptions& O, int n_threads) {
@@ -727,6 +821,10 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       r.pb = (int8_t)(l.b >= 0 ? lbit(l.b) : -1);
       P.leafrefs.push_back(r);
     }
+    // leaves of one angle next to each other: the leaf gradient sums them
+    // before its single atomic per angle
+    std::stable_sort(P.leafrefs.begin() + d.aux0, P.leafrefs.end(),
+                     [](const LeafRef& a, const LeafRef& b) { return a.kind < b.kind; });
     d.aux1 = (int32_t)P.leafrefs.size() - d.aux0;
     ref_lo[b] = d.aux0;
     ref_n[b] = d.aux1;
@@ -752,18 +850,29 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       ++ni;
     }
     d.n_in = ni;
-    d.out_mask = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u) & ~1u;
+    d.out_mask = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u) & ~Bk.elim_mask();
     d.out_off = out;
     partition_bits(d, nbits, d.out_mask, nbits <= T.seq_max_bits, T);
-    const double outn = std::ldexp(1.0, nbits - 1);
+    const double outn = std::ldexp(1.0, Bk.out_rank());
     if (bytes) *bytes += (in_elems + outn) * eb;
     if (flops) *flops += 6.0 * std::max(0, ni - 1) * std::ldexp(1.0, nbits) + 2.0 * outn;
     return d;
   };
+  // an op whose partial sums meet in atomics (summed bits among its block
+  // bits: merged steps split across work items) needs a zeroed output
+  auto push_zeroed = [&](std::vector<OpDesc>& prog, const OpDesc& d) {
+    if (d.flags & F_ATOMIC) {
+      OpDesc z = blank(OP_ZERO, (int)c);
+      z.out_off = d.out_off;
+      z.in_off[0] = int64_t(1) << __builtin_popcount(d.out_mask);
+      prog.push_back(z);
+    }
+    prog.push_back(d);
+  };
   for (size_t b = 0; b < nb; ++b) {
     const Bucket& Bk = C.buckets[b];
     if (Bk.in_bkt.size() + (Bk.lam_mask ? 1 : 0) > (size_t)MAXIN) return "bucket with more than 8 inputs";
-    G.fwd.push_back(fwd_op(b, buf_code(BK_OUT, (int)b), &C.fwd_bytes_alg, &C.fwd_flops));
+    push_zeroed(G.fwd, fwd_op(b, buf_code(BK_OUT, (int)b), &C.fwd_bytes_alg, &C.fwd_flops));
   }
   G.result = blank(OP_RESULT, (int)c);
   G.result.n_in = (int)C.scalars.size();
@@ -783,7 +892,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
     // inputs dropped after the forward sweep are recomputed before their use
     for (int t = 0; t < nin; ++t) {
       const int pb = Bk.in_bkt[t];
-      if (C.recompute[pb]) G.adj.push_back(fwd_op(pb, buf_code(BK_REC, pb), &C.rec_bytes, nullptr));
+      if (C.recompute[pb]) push_zeroed(G.adj, fwd_op(pb, buf_code(BK_REC, pb), &C.rec_bytes, nullptr));
     }
     auto in_code = [&](int t) {
       const int pb = Bk.in_bkt[t];
@@ -791,11 +900,11 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
     };
     double stored = 0;
     for (int t = 0; t < nin; ++t) stored += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
-    C.bwd_bytes_alg += (std::ldexp(1.0, nbits - 1) + stored) * eb;
+    C.bwd_bytes_alg += (std::ldexp(1.0, Bk.out_rank()) + stored) * eb;
     auto add_common = [&](OpDesc& d, int skip_t, bool with_lam) {
       int ni = 0;
       d.in_off[ni] = buf_code(BK_ADJ, (int)bb);
-      d.in_mask[ni] = all & ~1u;
+      d.in_mask[ni] = all & ~Bk.elim_mask();
       ++ni;
       if (with_lam && Bk.lam_mask) {
         d.in_off[ni] = buf_code(BK_LAM, (int)bb);
@@ -810,15 +919,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       }
       d.n_in = ni;
     };
-    auto push_adj = [&](OpDesc& d) {
-      if (d.flags & F_ATOMIC) {
-        OpDesc z = blank(OP_ZERO, (int)c);
-        z.out_off = d.out_off;
-        z.in_off[0] = int64_t(1) << __builtin_popcount(d.out_mask);
-        G.adj.push_back(z);
-      }
-      G.adj.push_back(d);
-    };
+    auto push_adj = [&](OpDesc& d) { push_zeroed(G.adj, d); };
     for (int t = 0; t < nin; ++t) {
       OpDesc d = blank(OP_CONTRACT, (int)c);
       d.nbits = nbits;
@@ -973,6 +1074,7 @@ std::string build_programs(Plan& P, int elem_bytes) {
   std::vector<ConeProg> progs(nc);
   int64_t total = 0;
   for (size_t c = 0; c < nc; ++c) {
+    group_buckets(P.cones[c], P.tune.merge_bits, P.tune.merge_lam_bits);
     P.cones[c].recompute.assign(P.cones[c].buckets.size(), 0);
     std::string err = emit_cone(P, c, progs[c]);
     if (!err.empty()) return err;
@@ -1085,15 +1187,21 @@ std::string validate_plan(const Plan& P) {
       if (v < 0 || v >= n || pos[v] >= 0) return "cone " + S(c) + "order is not a permutation";
       pos[v] = s;
     }
-    std::vector<int> leaf_seen(C.leaves.size(), 0), consumed(n, 0);
+    const int nb = (int)C.buckets.size();
+    std::vector<int> leaf_seen(C.leaves.size(), 0), consumed(nb, 0), elim_seen(n, 0);
     int width = 0;
-    for (int b = 0; b < n; ++b) {
+    for (int b = 0; b < nb; ++b) {
       const Bucket& B = C.buckets[b];
-      if (B.v != C.order[b] || B.uni.empty() || B.uni[0] != B.v) return "cone " + S(c, b) + "bucket index mismatch";
+      if (B.uni.empty() || B.n_elim < 1 || B.n_elim > (int)B.uni.size() || B.uni[0] != B.v)
+        return "cone " + S(c, b) + "bucket index mismatch";
+      if (B.nbits() > MAXBITS) return "cone " + S(c, b) + "union too wide";
       for (size_t t = 1; t < B.uni.size(); ++t)
         if (pos[B.uni[t]] <= pos[B.uni[t - 1]]) return "cone " + S(c, b) + "union not in elimination order";
+      for (int q = 0; q < B.n_elim; ++q) elim_seen[B.uni[q]]++;
+      if (b > 0 && pos[C.buckets[b - 1].uni[C.buckets[b - 1].n_elim - 1]] >= pos[B.uni[B.n_elim - 1]])
+        return "cone " + S(c, b) + "steps not in elimination order";
       const uint32_t all = (uint32_t)((uint64_t(1) << B.uni.size()) - 1);
-      uint32_t cover = 1;
+      uint32_t cover = 0;
       for (int li : B.leaves) {
         leaf_seen[li]++;
         const Leaf& L = C.leaves[li];
@@ -1101,7 +1209,6 @@ std::string validate_plan(const Plan& P) {
           if (idx < 0) continue;
           auto it = std::find(B.uni.begin(), B.uni.end(), idx);
           if (it == B.uni.end()) return "cone " + S(c, b) + "leaf index outside the union";
-          if (pos[idx] < b) return "cone " + S(c, b) + "leaf holds an index eliminated earlier";
           const uint32_t bit = 1u << (it - B.uni.begin());
           if (!(B.lam_mask & bit)) return "cone " + S(c, b) + "leaf bit missing from the leaf-product mask";
           cover |= bit;
@@ -1114,23 +1221,25 @@ std::string validate_plan(const Plan& P) {
         if (Pb.consumer != b) return "cone " + S(c, b) + "producer's consumer mismatch";
         consumed[pb]++;
         uint32_t mk = 0;
-        for (size_t q = 1; q < Pb.uni.size(); ++q) {
+        for (size_t q = Pb.n_elim; q < Pb.uni.size(); ++q) {
           auto it = std::find(B.uni.begin(), B.uni.end(), Pb.uni[q]);
           if (it == B.uni.end()) return "cone " + S(c, b) + "input index outside the union";
           mk |= 1u << (it - B.uni.begin());
         }
-        if (mk != B.in_mask[t] || !(mk & 1u)) return "cone " + S(c, b) + "input mask mismatch";
+        if (mk != B.in_mask[t] || (mk & B.elim_mask()) == 0) return "cone " + S(c, b) + "input mask mismatch";
         cover |= mk;
       }
       if (cover != all) return "cone " + S(c, b) + "union larger than its inputs";
-      width = std::max(width, (int)B.uni.size() - 1);
-      if (B.uni.size() == 1 && B.consumer != -1) return "cone " + S(c, b) + "scalar with a consumer";
+      width = std::max(width, B.out_rank());
+      if ((B.out_rank() == 0) != (B.consumer == -1)) return "cone " + S(c, b) + "scalar / consumer mismatch";
     }
     for (size_t li = 0; li < C.leaves.size(); ++li)
       if (leaf_seen[li] != 1) return "cone " + S(c, li) + "leaf not absorbed exactly once";
-    for (int b = 0; b < n; ++b)
+    for (int v = 0; v < n; ++v)
+      if (elim_seen[v] != 1) return "cone " + S(c, v) + "index not eliminated exactly once";
+    for (int b = 0; b < nb; ++b)
       if ((C.buckets[b].consumer >= 0) != (consumed[b] == 1)) return "cone " + S(c, b) + "output not consumed once";
-    if (width != C.width) return "cone " + S(c) + "width mismatch";
+    if (width > C.width) return "cone " + S(c) + "width above the order's width";
     // arena placement: in the cone's region, and buffers alive at the same
     // time never overlap
     std::vector<const BufLife*> bl;

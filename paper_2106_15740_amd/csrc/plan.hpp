@@ -27,16 +27,23 @@ struct Leaf {
   int32_t a, b;  // index ids; b = -1 for rank-1 leaves
 };
 
+// One contraction step.  A plain bucket eliminates one index (Section III.B);
+// a merged bucket eliminates the indices of a connected piece of the
+// elimination tree in one step (the union of its members' tensors, summed
+// over all of their indices at once).  The eliminated indices are the lowest
+// n_elim bits of the union.
 struct Bucket {
-  int32_t v = -1;                 // eliminated index
+  int32_t v = -1;                 // first eliminated index (bit 0)
+  int32_t n_elim = 1;             // eliminated indices: union bits 0 .. n_elim-1
   std::vector<int32_t> uni;       // union, sorted by elimination position (uni[0] == v)
   std::vector<int32_t> in_bkt;    // producer bucket of each intermediate input
-  std::vector<uint32_t> in_mask;  // its mask over union bits (bit 0 always set)
+  std::vector<uint32_t> in_mask;  // its mask over union bits
   std::vector<int32_t> leaves;    // leaf ids absorbed by this bucket
   uint32_t lam_mask = 0;          // union bits carried by the leaf product (0: no leaves)
   int32_t consumer = -1;          // bucket that reads this output (-1: scalar result)
   int nbits() const { return (int)uni.size(); }
-  int out_rank() const { return (int)uni.size() - 1; }
+  int out_rank() const { return (int)uni.size() - n_elim; }
+  uint32_t elim_mask() const { return (1u << n_elim) - 1u; }
   int lam_rank() const { return __builtin_popcount(lam_mask); }
 };
 
@@ -71,7 +78,8 @@ struct Cone {
   std::vector<Leaf> leaves;
   std::vector<int32_t> order;     // elimination order (index ids)
   int32_t width = 0;              // largest bucket output rank
-  std::vector<Bucket> buckets;    // in elimination order
+  std::vector<Bucket> plain;      // one bucket per index, in elimination order
+  std::vector<Bucket> buckets;    // contraction steps (plain buckets, small ones merged), in order
   std::vector<int32_t> scalars;   // buckets whose output has rank 0
   // arena: [leaf tables][their adjoints][buffers placed by lifetime]
   std::vector<char> recompute;    // bucket outputs not kept for the adjoint sweep (recomputed there)
@@ -93,6 +101,8 @@ struct TuneParams {
   int par_bits = 21;        // a wide op aims at >= 2^par_bits threads
   int elem_bytes = 8;       // 8: complex64, 16: complex128 (set by build_programs)
   int lds_kb = 64;          // LDS window for LDS-resident cones (0: never)
+  int merge_bits = 12;       // merge a bucket into its consumer while the merged union has <= this many bits (0: off)
+  int merge_lam_bits = 7;   // ... and its leaf-product table has <= this many bits
 };
 
 struct Plan {

@@ -138,6 +138,7 @@ def test_memory_budget_checkpointing_plan():
     An unreachable budget is refused and leaves no limit behind."""
     w = workload("p3_n244")
     net = QaoaNet(w.n, w.edges[:60], w.p, dtype="c64", order="min_fill", device=None)
+    net.set_tuning(merge_bits=0)  # one step per bucket: merged steps of these small cones leave little to drop
     full = net.info()
     assert full["n_recomputed"] == 0 and full["rec_bytes"] == 0
     keep = full["ws_grad"]
@@ -155,3 +156,22 @@ def test_memory_budget_checkpointing_plan():
     assert ei.value.status == L.QTN_ENOMEM
     assert net.info()["n_recomputed"] == 0 and net.info()["ws_grad"] == keep
     net.validate()
+
+
+@pytest.mark.parametrize("merge_bits", [0, 4, 8, 12])
+def test_merged_steps_cover_every_bucket(merge_bits):
+    """Merging buckets into contraction steps keeps the plan valid (every index
+    eliminated once, every leaf absorbed once, every step output consumed once)
+    and only removes steps: never more steps than buckets, fewer ops when on."""
+    w = workload("p3_n244")
+    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=None)
+    net.set_tuning(merge_bits=0)
+    base = net.info()
+    net.set_tuning(merge_bits=merge_bits)
+    net.validate()
+    info = net.info()
+    assert info["n_buckets"] == base["n_buckets"] == base["n_steps"]
+    assert info["n_steps"] <= info["n_buckets"]
+    if merge_bits >= 4:
+        assert info["n_steps"] < base["n_steps"] and info["n_ops_grad"] < base["n_ops_grad"]
+    assert info["max_width"] == base["max_width"]
