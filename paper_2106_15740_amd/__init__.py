@@ -16,4 +16,8 @@ def __getattr__(name):
         from . import autograd
 
         return getattr(autograd, name)
+    if name in ("maximize_cut", "OptResult"):
+        from . import optimize
+
+        return getattr(optimize, name)
     raise AttributeError(name)

@@ -292,3 +292,22 @@ def test_wide_executor_plain_and_batched(dtype, tol):
     gt = 1e-4 if dtype == "c64" else 1e-9
     np.testing.assert_allclose(dg_b, dg_p, atol=gt * max(1, np.abs(dg_p).max()))
     np.testing.assert_allclose(db_b, db_p, atol=gt * max(1, np.abs(db_p).max()))
+
+
+def test_optimisation_driver_reaches_the_p1_optimum():
+    """Adam over the library's energy and adjoint gradient on config 1 (p = 1)
+    climbs to the maximum of the oracle's energy landscape (dense grid over
+    gamma, beta of the state vector), and the final point's energy matches the
+    state vector there."""
+    from paper_2106_15740_amd import maximize_cut
+
+    w = workload("p1_n10")
+    net = make(w.n, w.edges, 1, "c128", "min_degree", [0.1], [0.1])
+    res = maximize_cut(net, [0.1], [0.1], steps=150, lr=0.05)
+    assert res.history[-1] > res.history[0] + 1.0
+    e_ref = sv.energy(w.n, w.edges, res.gamma, res.beta)
+    assert abs(res.energy - e_ref) <= 1e-10 * abs(e_ref)
+    # the landscape's maximum on a grid (one period in beta, half a period in gamma)
+    gs, bs = np.linspace(0, np.pi, 61), np.linspace(0, np.pi / 2, 31)
+    best = max(sv.energy(w.n, w.edges, [g], [b]) for g in gs for b in bs)
+    assert res.energy >= best - 1e-3
