@@ -198,7 +198,11 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
   (void)hipGetLastError();
   HIPCHECK(launch_small_copy(n->dh_leafvals, n->d_leafvals, n->leaf_bytes, st));
   const TuneParams& T = n->P.tune;
-  HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, n->P.leaf_hi, env, T.threads, st));
+  DevProg& pg = n->prog[grad ? 1 : 0];
+  int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
+  // leaf-product tables; in the batched form the same launch resets the queue
+  HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, n->P.leaf_hi, env, st, mode == QTN_BATCHED ? ctl : nullptr,
+                        pg.init, pg.n_nodes));
   if (mode == QTN_PLAIN) {
     for (size_t c = 0; c < n->P.cones.size(); ++c) {
       auto run = [&](int32_t lo, int32_t hi) -> qtn_status {
@@ -217,9 +221,6 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
       }
     }
   } else {
-    DevProg& pg = n->prog[grad ? 1 : 0];
-    int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
-    HIPCHECK(launch_reset(ctl, pg.init, pg.n_nodes, st));
     const int grid = std::max(1, std::min<int>(n->grid, std::max(1, pg.n_items)));
     const size_t lds_bytes = (size_t)n->P.lds_elems * n->elem;
     if (pk0) HIPCHECK(hipEventRecord(pk0, st));
@@ -227,12 +228,14 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
                                T.threads, grid, lds_bytes, kSpinLimit, st));
     if (pk1) HIPCHECK(hipEventRecord(pk1, st));
   }
-  if (grad) HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, n->P.lgrad_hi, env, T.threads, st));
+  if (grad) HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, n->P.lgrad_hi, env, st));
+  // E, dE/dtheta straight into the mapped host buffer, followed (at the
+  // workspace's ctl offset) by the queue head and the persistent kernel's
+  // error flag
   HIPCHECK(launch_final(n->c128, env.res, env.res_stride, (int)n->P.cones.size(), n->P.p, grad ? 1 : 0, zz_out,
-                        reinterpret_cast<double*>(w + L.fin_off), st));
-  // E, dE/dtheta and, right after them in the workspace, the queue head and
-  // the persistent kernel's error flag: one copy
-  HIPCHECK(launch_small_copy(w + L.fin_off, n->dh_fin, fin_copy_bytes(n), st));
+                        reinterpret_cast<double*>(w + L.fin_off), static_cast<double*>(n->dh_fin),
+                        mode == QTN_BATCHED ? ctl : nullptr,
+                        reinterpret_cast<int32_t*>(static_cast<char*>(n->dh_fin) + (L.ctl_off - L.fin_off)), st));
   return QTN_OK;
 }
 

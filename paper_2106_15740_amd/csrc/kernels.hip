@@ -882,7 +882,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int LG_MAXL = 16;  // leaves per table handled by the linear-time leaf gradient
 
 template <typename R>
-__global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env) {
+__global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env,
+                                                         int32_t* ctl, const int32_t* __restrict__ ctl_init,
+                                                         int n_nodes) {
+  // with ctl: also reset the queue head, the error flag and the node
+  // counters of the persistent sweep that follows
+  if (ctl)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes + 2; i += gridDim.x * blockDim.x)
+      ctl[i] = i < 2 ? 0 : ctl_init[i - 2];
   using E = typename CT<R>::E;
   const int lane = threadIdx.x & 63;
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -947,29 +954,29 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
             }
           }
         }
+        // per angle: sum the leaves in the lane, then across the wavefront
         int cur = -1;
         double sx = 0, sy = 0;
 #pragma unroll
-        for (int q = 0; q < LG_MAXL; ++q) {
-          if (q < L) {
-            const int slot = theta_slot(refs[q].kind, env.p);
-            if (slot < 0) continue;  // uniform across the wavefront
-            const double wx = wave_sum(ax[q]), wy = wave_sum(ay[q]);
-            if (slot != cur && cur >= 0 && lane == 0) {
-              atomicAdd(res + cur, sx);
-              atomicAdd(res + cur + 1, sy);
+        for (int q = 0; q <= LG_MAXL; ++q) {
+          const int slot = q < L ? theta_slot(refs[q].kind, env.p) : -2;  // uniform across the wavefront
+          if (slot == -1) continue;
+          if (slot != cur && cur >= 0) {
+            const double wx = wave_sum(sx), wy = wave_sum(sy);
+            if (lane == 0) {
+              atomicAdd(res + cur, wx);
+              atomicAdd(res + cur + 1, wy);
             }
-            if (slot != cur) {
-              cur = slot;
-              sx = sy = 0;
-            }
-            sx += wx;
-            sy += wy;
           }
-        }
-        if (cur >= 0 && lane == 0) {
-          atomicAdd(res + cur, sx);
-          atomicAdd(res + cur + 1, sy);
+          if (slot == -2) break;
+          if (slot != cur) {
+            cur = slot;
+            sx = sy = 0;
+          }
+          if (q < LG_MAXL) {
+            sx += ax[q];
+            sy += ay[q];
+          }
         }
       } else {
         for (int r = 0; r < L; ++r) {
@@ -1025,7 +1032,8 @@ __global__ void reset_ctl_kernel(int32_t* ctl, const int32_t* __restrict__ init,
 // per-edge <Z_j Z_k> = R_c in the caller's dtype.
 template <typename R>
 __global__ void final_kernel(const double* __restrict__ res, int res_stride, int n_cones, int p, int with_grad,
-                             typename CT<R>::E* zz_out, double* fin) {
+                             typename CT<R>::E* zz_out, double* fin, double* host_fin, const int32_t* ctl,
+                             int32_t* host_ctl) {
   using E = typename CT<R>::E;
   const int nv = 1 + (with_grad ? 2 * p : 0);
   for (int c = threadIdx.x; c < n_cones; c += blockDim.x)
@@ -1042,9 +1050,14 @@ __global__ void final_kernel(const double* __restrict__ res, int res_stride, int
       acc += v == 0 ? 0.5 * (1.0 - r[0]) : -0.5 * r[2 + 2 * (v - 1)];
     }
     const double2 s = block_sum<R>(make_double2(acc, 0));
-    if (threadIdx.x == 0) fin[v] = s.x;
+    if (threadIdx.x == 0) {
+      fin[v] = s.x;
+      if (host_fin) host_fin[v] = s.x;
+    }
     __syncthreads();
   }
+  // the queue head and the persistent kernel's error flag, next to the results
+  if (host_ctl && threadIdx.x < 2) host_ctl[threadIdx.x] = ctl ? ctl[threadIdx.x] : 0;
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -1118,14 +1131,17 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
               : launch_op_t<float>(d_ops, h, op, env, threads, max_grid, st);
 }
 
-hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st) {
-  (void)threads;
-  if (hi <= lo) return hipSuccess;
-  const int grid = std::min((hi - lo + 3) / 4, 4096);  // 4 wavefronts per workgroup, one op each
+hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, hipStream_t st, int32_t* ctl,
+                        const int32_t* ctl_init, int n_nodes) {
+  if (hi <= lo && !ctl) return hipSuccess;
+  // 4 wavefronts per workgroup, one op each
+  const int grid = std::max(1, std::min(std::max(hi - lo, 0) / 4 + 1, 4096));
   if (c128)
-    hipLaunchKernelGGL(leaf_batch_kernel<double>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env);
+    hipLaunchKernelGGL(leaf_batch_kernel<double>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env, ctl, ctl_init,
+                       n_nodes);
   else
-    hipLaunchKernelGGL(leaf_batch_kernel<float>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env);
+    hipLaunchKernelGGL(leaf_batch_kernel<float>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env, ctl, ctl_init,
+                       n_nodes);
   return hipGetLastError();
 }
 
@@ -1191,13 +1207,13 @@ hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* op
 }
 
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
-                        double* fin, hipStream_t st) {
+                        double* fin, double* host_fin, const int32_t* ctl, int32_t* host_ctl, hipStream_t st) {
   if (c128)
     hipLaunchKernelGGL(final_kernel<double>, dim3(1), dim3(256), 0, st, res, res_stride, n_cones, p, with_grad,
-                       reinterpret_cast<double2*>(zz_out), fin);
+                       reinterpret_cast<double2*>(zz_out), fin, host_fin, ctl, host_ctl);
   else
     hipLaunchKernelGGL(final_kernel<float>, dim3(1), dim3(256), 0, st, res, res_stride, n_cones, p, with_grad,
-                       reinterpret_cast<float2*>(zz_out), fin);
+                       reinterpret_cast<float2*>(zz_out), fin, host_fin, ctl, host_ctl);
   return hipGetLastError();
 }
 

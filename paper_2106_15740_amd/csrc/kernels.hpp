@@ -20,8 +20,11 @@ struct Env {
 
 hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads,
                      int max_grid, hipStream_t st);
-// ops [lo, hi) (OP_LEAF or OP_LEAFGRAD), one workgroup each
-hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, int threads, hipStream_t st);
+// ops [lo, hi) (OP_LEAF or OP_LEAFGRAD), one wavefront each; with ctl, the
+// same launch resets the persistent sweep's queue head, error flag and node
+// counters (n_nodes of them, from ctl_init)
+hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, hipStream_t st,
+                        int32_t* ctl = nullptr, const int32_t* ctl_init = nullptr, int n_nodes = 0);
 // bytes (a multiple of 4, <= 1 MiB) from src to dst with one workgroup;
 // either side may be mapped pinned host memory
 hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
@@ -34,7 +37,9 @@ hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStrea
 hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
                              size_t lds_bytes, long long spin_limit, hipStream_t st);
+// E, dE/dgamma, dE/dbeta into fin and, when host_fin is given, into mapped
+// pinned host memory, with ctl[0..1] (or zeros without ctl) into host_ctl
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
-                        double* fin, hipStream_t st);
+                        double* fin, double* host_fin, const int32_t* ctl, int32_t* host_ctl, hipStream_t st);
 
 }  // namespace qtn

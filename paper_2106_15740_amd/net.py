@@ -135,15 +135,19 @@ class QaoaNet:
         for k, v in kw.items():
             setattr(t, k, int(v))
         L.check(self._lib.qtn_set_tuning(self.handle, C.byref(t)))
+        self._ws = {k: v for k, v in self._ws.items() if k == "buf"}
 
     # ------------------------------------------------------------------ device work
     def _workspace(self, with_grad: bool):
         import torch
 
-        need = self.workspace_size(with_grad)
+        key = ("need", bool(with_grad))
+        need = self._ws.get(key)
+        if need is None:
+            need = self._ws[key] = self.workspace_size(with_grad)
         buf = self._ws.get("buf")
         if buf is None or buf.numel() < need:
-            self._ws.clear()
+            self._ws.pop("buf", None)
             buf = torch.empty(max(need, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
             self._ws["buf"] = buf
         return buf
@@ -208,6 +212,7 @@ class QaoaNet:
         t = L.Tuning()
         L.check(self._lib.qtn_autotune(self.handle, int(bool(with_grad)), C.c_void_p(ws.data_ptr()), ws.numel(),
                                        self._stream(), int(reps), C.byref(t)))
+        self._ws = {k: v for k, v in self._ws.items() if k == "buf"}
         return t.as_dict()
 
     def time_wide_ops(self, min_width: int = 20, with_grad: bool = True, reps: int = 2) -> Tuple[float, float, int]:
