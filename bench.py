@@ -13,8 +13,9 @@ node and reads back 1 + 2p doubles.
 Prints one JSON line.  Beside the headline it reports: the plain per-edge
 loop (one launch per bucket step) on the same GPU; the roofline of the
 persistent kernel; the p = 5, N = 1000 workload (throughput, HBM fraction of
-the whole sweep and of its buckets of width >= 20 timed one by one); and the
-CPU oracle timed on a bounded sample of edges.
+the whole sweep and of its buckets of width >= 20 timed one by one); one
+single amplitude of a 40-vertex graph at p = 4; and the CPU oracle timed on a
+bounded sample of edges.
 """
 from __future__ import annotations
 
@@ -170,6 +171,41 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     return out
 
 
+def amplitude_leg(steps: int = 3):
+    """The paper's own benchmark object: one amplitude <0...0|gamma beta> of a
+    whole 40-vertex random 3-regular graph at p = 4 (the depth the paper
+    estimates for supercomputers only), c64, min-fill randomized greedy order
+    (50 repeats), forward contraction."""
+    import torch
+
+    from paper_2106_15740_amd import QaoaAmplitude
+    from workloads import random_angles, random_regular_graph
+
+    n, p = 40, 4
+    edges = random_regular_graph(n, 3, 0)
+    g, b = random_angles(p, 1 + 1000 * p)
+    t0 = time.perf_counter()
+    net = QaoaAmplitude(n, edges, p, dtype="c64", order="min_fill", device=0, repeats=50)
+    plan_s = time.perf_counter() - t0
+    net.set_tuning(seq_max_bits=14, tile_blocks=64, par_bits=21)
+    net.set_params(g, b)
+    info = net.info()
+    a = net.amplitude()  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = net.amplitude()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "single amplitude <0...0|gamma beta>, random 3-regular N=40 (60 edges), p=4, c64, "
+                       "min-fill randomized greedy (50 repeats), batched forward contraction",
+           "ms_per_amplitude": 1e3 * dt, "max_width": info["max_width"], "workspace_GB": info["ws_fwd"] / 1e9,
+           "alg_bytes": info["fwd_bytes"], "alg_GBps": info["fwd_bytes"] / dt / 1e9,
+           "amplitude": [a.real, a.imag], "plan_s": plan_s}
+    del net
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +220,7 @@ def main():
     ap.add_argument("--tuning", default="",
                     help="fixed tile shapes instead of the autotuner, e.g. threads=128,lane_cap=7,seq_max_bits=14")
     ap.add_argument("--no-wide", action="store_true", help="skip the p=5 N=1000 leg")
+    ap.add_argument("--no-amplitude", action="store_true", help="skip the single-amplitude leg (N=40, p=4)")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-other-order", dest="other_order", action="store_false",
                     help="skip the headline workload under the other greedy order")
@@ -302,6 +339,8 @@ def main():
         del net
         torch.cuda.empty_cache()
         out["wide"] = wide_leg(args.repeats, steps=3, copy_gbps=copy_gbps)
+    if not args.no_amplitude:
+        out["amplitude"] = amplitude_leg()
     if cpu is not None:
         cpu["gpu_speedup"] = cones_per_s / cpu["value"]
         out["cpu_baseline"] = cpu

@@ -207,6 +207,26 @@ qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width,
 qtn_status qtn_time_persistent(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
                                int32_t reps, double* ms_out);
 
+/* Single-amplitude network (the paper's benchmark object, Section V):
+ * <0...0|gamma beta> of the whole graph, ket only, with the same diagonal-gate
+ * network rules (Sections III.A, IV.B) and a <0| leaf on the last index of
+ * every qubit.  The net has one light cone (the whole graph); qtn_order /
+ * qtn_order_rgreedy, qtn_set_params, qtn_set_tuning, qtn_workspace_size and
+ * qtn_get_info apply as for qtn_build; read results with qtn_amplitude.
+ * Arguments and errors as qtn_build (a graph with more than 4 connected
+ * components is refused by the planner with QTN_EUNSUPPORTED). */
+qtn_status qtn_build_amplitude(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                               qtn_dtype dtype, qtn_net** out);
+
+/* Contracts an amplitude network: amp_out[0..1] = (re, im) of
+ * <0...0|gamma beta> (host, float64).  With damp_out (host, [4p] doubles,
+ * nullable) the adjoint sweep also runs and damp_out holds d amp / d gamma_l
+ * (re, im) at 2l and d amp / d beta_l at 2p + 2l; the workspace must then be
+ * sized with_grad = 1.  Synchronises `stream`.  QTN_ESTATE for a net made by
+ * qtn_build. */
+qtn_status qtn_amplitude(qtn_net* net, qtn_mode mode, void* workspace, size_t ws_bytes, void* stream,
+                         double* amp_out, double* damp_out);
+
 /* Achievable-bandwidth reference: the library's plain copy kernel copies the
  * first half of the caller's device buffer `buf` (`bytes` long, 16-byte
  * aligned) onto its second half, `reps` times on `stream` after one warm-up,

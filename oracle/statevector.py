@@ -87,6 +87,13 @@ def qaoa_state(n: int, edges: Sequence[Edge], gamma: Sequence[float], beta: Sequ
     return psi
 
 
+def amplitude(n: int, edges: Sequence[Edge], gamma, beta, x: int = 0) -> complex:
+    """<x|gamma beta>, by default <0...0|gamma beta>: the single amplitude the
+    paper simulates with its tensor networks (Section V), read off the state
+    vector."""
+    return complex(qaoa_state(n, edges, gamma, beta)[x])
+
+
 def zz_expectations(n: int, edges: Sequence[Edge], gamma, beta) -> np.ndarray:
     """<gamma beta| Z_j Z_k |gamma beta> for every edge, complex128 (imaginary
     part kept so callers can check that it vanishes)."""

@@ -8,7 +8,7 @@ adjoint and the reductions run in hand-written HIP kernels behind the C ABI of
 include/qtn.h; this package is the Python binding of that library.
 """
 from ._lib import QtnError, lib  # noqa: F401
-from .net import Context, QaoaNet, copy_bandwidth  # noqa: F401
+from .net import Context, QaoaAmplitude, QaoaNet, copy_bandwidth  # noqa: F401
 
 
 def __getattr__(name):

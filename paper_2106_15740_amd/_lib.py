@@ -22,6 +22,7 @@ EXPORTS = [
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
+    "qtn_build_amplitude", "qtn_amplitude",
     "qtn_net_free",
 ]
 
@@ -91,6 +92,8 @@ def lib() -> C.CDLL:
         "qtn_time_wide_ops": (I32, [P, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)]),
         "qtn_copy_bandwidth": (I32, [P, P, SZ, P, I32, C.POINTER(D)]),
         "qtn_time_persistent": (I32, [P, I32, P, SZ, P, I32, C.POINTER(D)]),
+        "qtn_build_amplitude": (I32, [P, I32, I32, P, I32, I32, C.POINTER(P)]),
+        "qtn_amplitude": (I32, [P, I32, P, SZ, P, P, P]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

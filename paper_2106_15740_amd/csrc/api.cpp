@@ -80,6 +80,7 @@ struct qtn_net {
   int grid = 0;
   int max_nin = 1;
   bool has_wide = false;  // some op carries F_WIDE
+  bool amplitude = false; // single-amplitude network (one cone, result = <0...0|gamma beta>)
   GraphCache graph[2];
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
   bool ev_pending = false;
@@ -364,8 +365,8 @@ void qtn_destroy(qtn_ctx* c) {
   delete c;
 }
 
-qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
-                     qtn_dtype dtype, qtn_net** out) {
+static qtn_status build_net(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                            qtn_dtype dtype, bool amplitude, qtn_net** out) {
   if (!ctx || !out) return fail(QTN_EINVAL, "ctx or out is NULL");
   *out = nullptr;
   if (dtype != QTN_C64 && dtype != QTN_C128) return fail(QTN_EINVAL, "unknown dtype");
@@ -379,7 +380,11 @@ qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const in
     n->P.n = n_vertices;
     n->P.p = p;
     for (int e = 0; e < n_edges; ++e) n->P.edges.push_back({edges[2 * e], edges[2 * e + 1]});
-    build_cones(n->P);
+    n->amplitude = amplitude;
+    if (amplitude)
+      build_amplitude(n->P);
+    else
+      build_cones(n->P);
     n->grid = 8 * ctx->n_cu;
     *out = n;
     return QTN_OK;
@@ -388,6 +393,37 @@ qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const in
   } catch (const std::exception& ex) {
     return fail(QTN_EINVAL, ex.what());
   }
+}
+
+qtn_status qtn_build(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                     qtn_dtype dtype, qtn_net** out) {
+  return build_net(ctx, n_vertices, n_edges, edges, p, dtype, false, out);
+}
+
+qtn_status qtn_build_amplitude(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                               qtn_dtype dtype, qtn_net** out) {
+  if (n_vertices < 1) return fail(QTN_EINVAL, "the amplitude network needs at least one vertex");
+  return build_net(ctx, n_vertices, n_edges, edges, p, dtype, true, out);
+}
+
+qtn_status qtn_amplitude(qtn_net* n, qtn_mode mode, void* ws, size_t ws_bytes, void* stream, double* amp_out,
+                         double* damp_out) {
+  if (mode != QTN_PLAIN && mode != QTN_BATCHED) return fail(QTN_EINVAL, "unknown mode");
+  if (!n || !amp_out) return fail(QTN_EINVAL, "net or amp_out is NULL");
+  if (!n->amplitude) return fail(QTN_ESTATE, "not an amplitude network (use qtn_build_amplitude)");
+  const bool grad = damp_out != nullptr;
+  qtn_status s = check_ready(n, ws, ws_bytes, grad);
+  if (s != QTN_OK) return s;
+  s = run_sweep(n, mode, grad, ws, ws_bytes, (hipStream_t)stream, nullptr, true);
+  if (s != QTN_OK) return s;
+  const int rs = 2 + 4 * n->P.p;
+  std::vector<double> r(rs);
+  HIPCHECK(hipMemcpy(r.data(), ws, rs * sizeof(double), hipMemcpyDeviceToHost));  // the one cone's record
+  amp_out[0] = r[0];
+  amp_out[1] = r[1];
+  if (grad)
+    for (int i = 0; i < 4 * n->P.p; ++i) damp_out[i] = r[2 + i];
+  return QTN_OK;
 }
 
 qtn_status qtn_order(qtn_net* n, qtn_order_kind kind, int32_t* max_width_out) {
@@ -467,6 +503,7 @@ qtn_status qtn_set_params(qtn_net* n, const double* gamma, const double* beta) {
   put(v, LK_PLUS, 1, h, 0);
   put(v, LK_ZOBS, 0, 1, 0);
   put(v, LK_ZOBS, 1, -1, 0);
+  put(v, lk_proj0(p), 0, 1, 0);  // <0|: entry 1 stays 0
   for (int l = 0; l < p; ++l) {
     // ZZ phase of exp(-i gamma C) on one edge: 1 if the bits agree, exp(-i gamma) if not
     const double cg = std::cos(gamma[l]), sg = std::sin(gamma[l]);

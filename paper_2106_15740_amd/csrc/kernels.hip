@@ -591,9 +591,9 @@ __device__ __forceinline__ void exec_leaf(const OpDesc& d, typename CT<R>::E* ar
 }
 
 // Parameter slot of a leaf kind inside a cone's result record: gamma_l at
-// 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+> and Z.
+// 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+>, Z and <0|.
 __device__ __forceinline__ int theta_slot(int kind, int p) {
-  if (kind < 2) return -1;
+  if (kind < 2 || kind >= 2 + 4 * p) return -1;
   const int l = (kind - 2) >> 2, t = (kind - 2) & 3;
   return t < 2 ? 2 + 2 * l : 2 + 2 * p + 2 * l;
 }

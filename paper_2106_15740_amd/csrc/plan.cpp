@@ -117,6 +117,25 @@ void build_cones(Plan& P) {
   }
 }
 
+void build_amplitude(Plan& P) {
+  const int n = P.n, p = P.p;
+  P.cones.assign(1, Cone());
+  Cone& C = P.cones[0];
+  C.j = C.k = -1;
+  C.n_qubits = n;
+  // index a(q, s), s = 0..p: the wire of qubit q after s mixer layers
+  auto A = [&](int q, int s) { return q * (p + 1) + s; };
+  C.n_idx = n * (p + 1);
+  auto& L = C.leaves;
+  for (int q = 0; q < n; ++q) {
+    L.push_back({LK_PLUS, A(q, 0), -1});
+    for (int l = 1; l <= p; ++l) L.push_back({lk_mx(l - 1), A(q, l - 1), A(q, l)});
+    L.push_back({lk_proj0(p), A(q, p), -1});
+  }
+  for (auto& e : P.edges)
+    for (int l = 1; l <= p; ++l) L.push_back({lk_zz(l - 1), A(e.first, l - 1), A(e.second, l - 1)});
+}
+
 // ---------------------------------------------------------------- ordering
 // Greedy elimination on the interaction graph (indices adjacent iff they share
 // a leaf).  min-degree: fewest neighbours; min-fill: fewest new edges among

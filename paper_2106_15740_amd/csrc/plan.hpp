@@ -20,7 +20,8 @@ inline int32_t lk_zz(int l) { return 2 + 4 * l + 0; }     // l is 0-based layer
 inline int32_t lk_zzb(int l) { return 2 + 4 * l + 1; }
 inline int32_t lk_mx(int l) { return 2 + 4 * l + 2; }
 inline int32_t lk_mxb(int l) { return 2 + 4 * l + 3; }
-inline int32_t n_leaf_kinds(int p) { return 2 + 4 * p; }
+inline int32_t lk_proj0(int p) { return 2 + 4 * p; }      // <0| on the last index of a qubit (amplitude networks)
+inline int32_t n_leaf_kinds(int p) { return 3 + 4 * p; }
 
 struct Leaf {
   int32_t kind;
@@ -133,6 +134,9 @@ struct Plan {
 // Returns "" on success, else an error message.
 std::string validate_graph(int32_t n, int32_t m, const int32_t* edges, int32_t p);
 void build_cones(Plan& P);
+// Single-amplitude network <0...0|gamma beta> of the whole graph (ket only):
+// one "cone" whose result is the amplitude.
+void build_amplitude(Plan& P);
 struct OrderOptions {
   int kind = 0;              // 0 = min-degree, 1 = min-fill
   int repeats = 0;           // randomized runs on top of the deterministic one

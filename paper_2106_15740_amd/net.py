@@ -58,6 +58,8 @@ def default_context(device: int = 0) -> Context:
 
 
 class QaoaNet:
+    _BUILD = "qtn_build"
+
     """Light-cone tensor networks of every edge term of <gamma beta|C|gamma beta>.
 
     n, edges: the graph (vertices 0..n-1); p: QAOA depth; dtype "c64" or
@@ -78,8 +80,8 @@ class QaoaNet:
         e = np.ascontiguousarray(np.array(self.edges, dtype=np.int32).reshape(-1, 2))
         self._edges_buf = e
         h = C.c_void_p()
-        L.check(self._lib.qtn_build(self.ctx.handle, self.n, len(self.edges), e.ctypes.data_as(C.c_void_p),
-                                    self.p, _DTYPES[dtype], C.byref(h)))
+        L.check(getattr(self._lib, self._BUILD)(self.ctx.handle, self.n, len(self.edges),
+                                                e.ctypes.data_as(C.c_void_p), self.p, _DTYPES[dtype], C.byref(h)))
         self.handle = h
         w = C.c_int32()
         if repeats > 0:
@@ -140,6 +142,9 @@ class QaoaNet:
     # ------------------------------------------------------------------ device work
     def _workspace(self, with_grad: bool):
         import torch
+
+        if self.device is None:
+            raise L.QtnError(L.QTN_ESTATE, "a host-only network cannot run contractions")
 
         key = ("need", bool(with_grad))
         need = self._ws.get(key)
@@ -239,3 +244,28 @@ class QaoaNet:
         cnt = C.c_int64()
         L.check(self._lib.qtn_kernel_time(self.handle, C.byref(ms), C.byref(cnt), int(bool(reset))))
         return ms.value, cnt.value
+
+
+class QaoaAmplitude(QaoaNet):
+    """Single-amplitude network <0...0|gamma beta> of the whole graph (ket
+    only; the paper's benchmark object).  Ordering, tuning and parameters work
+    as for QaoaNet; read the value with amplitude() / amplitude_grad()."""
+
+    _BUILD = "qtn_build_amplitude"
+
+    def amplitude(self, mode: str = "batched") -> complex:
+        ws = self._workspace(False)
+        a = np.zeros(2)
+        L.check(self._lib.qtn_amplitude(self.handle, _MODES[mode], C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        self._stream(), a.ctypes.data_as(C.c_void_p), None))
+        return complex(a[0], a[1])
+
+    def amplitude_grad(self, mode: str = "batched"):
+        """(amplitude, d amplitude / d gamma [p], d amplitude / d beta [p]), complex."""
+        ws = self._workspace(True)
+        a = np.zeros(2)
+        d = np.zeros(4 * self.p)
+        L.check(self._lib.qtn_amplitude(self.handle, _MODES[mode], C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        self._stream(), a.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p)))
+        z = d[0::2] + 1j * d[1::2]
+        return complex(a[0], a[1]), z[: self.p], z[self.p:]

@@ -311,3 +311,35 @@ def test_optimisation_driver_reaches_the_p1_optimum():
     gs, bs = np.linspace(0, np.pi, 61), np.linspace(0, np.pi / 2, 31)
     best = max(sv.energy(w.n, w.edges, [g], [b]) for g in gs for b in bs)
     assert res.energy >= best - 1e-3
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_single_amplitude_vs_statevector(mode, dtype):
+    """<0...0|gamma beta> of whole graphs (the paper's benchmark network)
+    against the state vector, p = 1..3, and its derivative from the adjoint
+    sweep against central differences of the state-vector amplitude."""
+    from paper_2106_15740_amd import QaoaAmplitude
+
+    tol = 1e-12 if dtype == "c128" else 1e-6  # |amplitude| ~ 2^(-N/2)
+    for n, seed, p in ((10, 0, 1), (12, 1, 2), (14, 2, 3)):
+        edges = random_regular_graph(n, 3, seed)
+        rng = np.random.default_rng(seed + 40)
+        g, b = rng.uniform(0, np.pi, p), rng.uniform(0, np.pi, p)
+        print(f"[case] amplitude n={n} p={p} {dtype} {mode}", flush=True)
+        net = QaoaAmplitude(n, edges, p, dtype=dtype, order="min_fill", device=0)
+        net.set_params(g, b)
+        ref = sv.amplitude(n, edges, g, b)
+        assert abs(net.amplitude(mode) - ref) <= tol
+        a, dg, db = net.amplitude_grad(mode)
+        assert abs(a - ref) <= tol
+        h = 1e-5
+        for l in range(p):
+            for arr, d in ((g, dg), (b, db)):
+                arr[l] += h
+                up = sv.amplitude(n, edges, g, b)
+                arr[l] -= 2 * h
+                dn = sv.amplitude(n, edges, g, b)
+                arr[l] += h
+                fd = (up - dn) / (2 * h)
+                assert abs(d[l] - fd) <= (1e-8 if dtype == "c128" else 1e-5), (l, d[l], fd)

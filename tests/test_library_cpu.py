@@ -175,3 +175,23 @@ def test_merged_steps_cover_every_bucket(merge_bits):
     if merge_bits >= 4:
         assert info["n_steps"] < base["n_steps"] and info["n_ops_grad"] < base["n_ops_grad"]
     assert info["max_width"] == base["max_width"]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_amplitude_network_plan(p):
+    """The single-amplitude network has p+1 indices per qubit (one bucket
+    each), N(p+2) + p|E| leaves, and plans validly under both orders; the
+    host-only context refuses to contract it."""
+    from paper_2106_15740_amd import QaoaAmplitude
+
+    n, edges = 12, random_regular_graph(12, 3, 1)
+    for order in ("min_fill", "min_degree"):
+        a = QaoaAmplitude(n, edges, p, dtype="c64", order=order, device=None)
+        a.validate()
+        info = a.info()
+        assert info["n_cones"] == 1 and info["n_buckets"] == n * (p + 1)
+        st = a.cone_stats()
+        assert st["n_indices"][0] == n * (p + 1) and st["n_qubits"][0] == n
+        assert st["n_tensors"][0] == n * (p + 2) + p * len(edges)
+    with pytest.raises(QtnError):
+        a.amplitude()

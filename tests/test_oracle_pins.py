@@ -331,3 +331,19 @@ def test_subgraph_helper():
     assert m == 16
     assert all(0 <= u < v < 16 for u, v in sub)
     assert len(set(sub)) == len(sub)
+
+
+def test_amplitude_closed_forms():
+    """<0...0|gamma beta> from the state vector: at gamma = 0 every cost layer
+    is the identity and exp(-i beta X)|+> = exp(-i beta)|+>, so the amplitude
+    is 2^(-N/2) exp(-i N sum beta); at beta = 0 the mixers vanish and the
+    all-zero string cuts nothing, so it is 2^(-N/2); and the amplitudes of all
+    basis states have unit total weight."""
+    n, edges = 8, random_regular_graph(8, 3, 2)
+    b = [0.3, -0.7]
+    a = sv.amplitude(n, edges, [0.0, 0.0], b)
+    assert abs(a - 2 ** (-n / 2) * np.exp(-1j * n * sum(b))) < 1e-14
+    assert abs(sv.amplitude(n, edges, [0.9, 0.4], [0.0, 0.0]) - 2 ** (-n / 2)) < 1e-14
+    g = [0.9, 0.4]
+    tot = sum(abs(sv.amplitude(n, edges, g, b, x)) ** 2 for x in range(1 << n))
+    assert abs(tot - 1) < 1e-12
