@@ -227,6 +227,30 @@ qtn_status qtn_build_amplitude(qtn_ctx* ctx, int32_t n_vertices, int32_t n_edges
 qtn_status qtn_amplitude(qtn_net* net, qtn_mode mode, void* workspace, size_t ws_bytes, void* stream,
                          double* amp_out, double* damp_out);
 
+/* Cost model of the paper's comparison (Section IV; Figures diag_costs,
+ * diag_costs_vs_n; Tables I and II), host only: the single-amplitude network
+ * <0...0|gamma beta> of the graph built from the circuit in one of four ways
+ * (default: CNOT / Z-rotation / H decomposition, every gate a full tensor with
+ * fresh output indices; diagonal: gates keep the indices of the qubits they act
+ * on diagonally, i.e. Z rotations and CNOT controls; ZZ: one two-qubit ZZ gate
+ * per edge and one X rotation per qubit as full tensors; diagonal + ZZ: the ZZ
+ * phase as a rank-2 tensor on the current indices), ordered by the library's
+ * greedy or randomized greedy orderer (n_repeats, temperature, seed as in
+ * qtn_order_rgreedy) and eliminated bucket by bucket.  Fills *out: index and
+ * tensor counts, contraction width (largest intermediate rank), log2 of the
+ * sum over buckets of 2^|union| (the FLOP estimate up to a constant) and the
+ * ordering time.  QTN_EINVAL for bad arguments or graphs. */
+typedef enum { QTN_NET_DEFAULT = 0, QTN_NET_DIAGONAL = 1, QTN_NET_ZZ = 2, QTN_NET_DIAGONAL_ZZ = 3 } qtn_net_variant;
+typedef struct {
+  int32_t n_indices, n_tensors;
+  int32_t width;
+  double log2_ops;
+  double order_seconds;
+} qtn_cost;
+qtn_status qtn_cost_model(int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                          qtn_net_variant variant, qtn_order_kind kind, int32_t n_repeats, double temperature,
+                          uint64_t seed, qtn_cost* out);
+
 /* Achievable-bandwidth reference: the library's plain copy kernel copies the
  * first half of the caller's device buffer `buf` (`bytes` long, 16-byte
  * aligned) onto its second half, `reps` times on `stream` after one warm-up,

@@ -22,7 +22,7 @@ EXPORTS = [
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
-    "qtn_build_amplitude", "qtn_amplitude",
+    "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model",
     "qtn_net_free",
 ]
 
@@ -38,6 +38,14 @@ class Tuning(C.Structure):
                 ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32),
                 ("lds_kb", C.c_int32), ("par_bits", C.c_int32), ("merge_bits", C.c_int32),
                 ("merge_lam_bits", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Cost(C.Structure):
+    _fields_ = [("n_indices", C.c_int32), ("n_tensors", C.c_int32), ("width", C.c_int32),
+                ("log2_ops", C.c_double), ("order_seconds", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -94,6 +102,7 @@ def lib() -> C.CDLL:
         "qtn_time_persistent": (I32, [P, I32, P, SZ, P, I32, C.POINTER(D)]),
         "qtn_build_amplitude": (I32, [P, I32, I32, P, I32, I32, C.POINTER(P)]),
         "qtn_amplitude": (I32, [P, I32, P, SZ, P, P, P]),
+        "qtn_cost_model": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost)]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

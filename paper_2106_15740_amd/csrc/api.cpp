@@ -848,6 +848,37 @@ qtn_status qtn_time_persistent(qtn_net* n, int32_t with_grad, void* ws, size_t w
   return QTN_OK;
 }
 
+qtn_status qtn_cost_model(int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                          qtn_net_variant variant, qtn_order_kind kind, int32_t n_repeats, double temperature,
+                          uint64_t seed, qtn_cost* out) {
+  if (!out) return fail(QTN_EINVAL, "out is NULL");
+  if (variant < QTN_NET_DEFAULT || variant > QTN_NET_DIAGONAL_ZZ) return fail(QTN_EINVAL, "unknown network variant");
+  if (kind != QTN_ORDER_MIN_DEGREE && kind != QTN_ORDER_MIN_FILL) return fail(QTN_EINVAL, "unknown order kind");
+  if (n_repeats < 0 || !(temperature >= 0.0) || !std::isfinite(temperature))
+    return fail(QTN_EINVAL, "n_repeats must be >= 0 and temperature finite and >= 0");
+  std::string err = validate_graph(n_vertices, n_edges, edges, p);
+  if (!err.empty()) return fail(QTN_EINVAL, err);
+  try {
+    std::vector<std::pair<int32_t, int32_t>> E;
+    for (int e = 0; e < n_edges; ++e) E.push_back({edges[2 * e], edges[2 * e + 1]});
+    OrderOptions O;
+    O.kind = (int)kind;
+    O.repeats = n_repeats;
+    O.temperature = temperature;
+    O.seed = seed;
+    const auto t0 = std::chrono::steady_clock::now();
+    const CostEstimate c = cost_model(n_vertices, E, p, (int)variant, O);
+    out->order_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out->n_indices = c.n_indices;
+    out->n_tensors = c.n_tensors;
+    out->width = c.width;
+    out->log2_ops = c.log2_ops;
+    return QTN_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
 qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* stream, int32_t reps, double* gbps_out) {
   if (!ctx) return fail(QTN_EINVAL, "context is NULL");
   if (ctx->device < 0) return fail(QTN_ESTATE, "host-only context has no device");

@@ -302,7 +302,133 @@ void order_one(Cone& C, const OrderOptions& O, uint64_t cone_seed) {
   C.width = best.width;
 }
 
+
+// ---------------------------------------------------------------- cost model
+// Index structure of the single-amplitude network <0...0|gamma beta> under the
+// four constructions the paper compares (Section IV, Figures diag_costs and
+// diag_costs_vs_n, Tables I and II).  Circuit: |0> and H on every qubit, then
+// per layer the cost gates of every edge and the mixer of every qubit, then
+// <0| on every qubit.  "ZZ" circuits use one two-qubit ZZ(gamma) gate per edge
+// and one X rotation per qubit; the others decompose them as CNOT, Z rotation
+// on the target, CNOT and H, Z rotation, H.  Without the diagonal
+// simplification every gate gives each qubit it acts on a fresh index (a
+// 2-index tensor per one-qubit gate, 4 indices per two-qubit gate); with it,
+// a gate keeps the index of every qubit it acts on diagonally (Z rotations and
+// ZZ on both of their qubits, CNOT on its control), so the ZZ phase becomes a
+// rank-2 tensor on the two current indices.
+struct IndexNet {
+  int n_idx = 0;
+  std::vector<std::vector<int>> tensors;
+};
+
+IndexNet variant_network(int n, const std::vector<std::pair<int32_t, int32_t>>& edges, int p, int variant) {
+  const bool diag = variant == 1 || variant == 3;
+  const bool zz = variant == 2 || variant == 3;
+  IndexNet T;
+  std::vector<int> cur(n);
+  for (int q = 0; q < n; ++q) {
+    cur[q] = T.n_idx++;
+    T.tensors.push_back({cur[q]});  // |0>
+  }
+  auto one_qubit = [&](int q, bool keeps) {  // a one-qubit gate
+    if (keeps) {
+      T.tensors.push_back({cur[q]});
+    } else {
+      const int nw = T.n_idx++;
+      T.tensors.push_back({cur[q], nw});
+      cur[q] = nw;
+    }
+  };
+  for (int q = 0; q < n; ++q) one_qubit(q, false);  // H
+  for (int l = 0; l < p; ++l) {
+    for (auto& e : edges) {
+      const int u = e.first, w = e.second;
+      if (zz) {
+        if (diag) {
+          T.tensors.push_back({cur[u], cur[w]});
+        } else {
+          const int nu = T.n_idx++, nw = T.n_idx++;
+          T.tensors.push_back({cur[u], cur[w], nu, nw});
+          cur[u] = nu;
+          cur[w] = nw;
+        }
+      } else {
+        for (int g = 0; g < 3; ++g) {
+          if (g == 1) {
+            one_qubit(w, diag);  // Z rotation on the target
+            continue;
+          }
+          // CNOT(u -> w): the control keeps its index under the diagonal simplification
+          const int nw = T.n_idx++;
+          if (diag) {
+            T.tensors.push_back({cur[u], cur[w], nw});
+          } else {
+            const int nu = T.n_idx++;
+            T.tensors.push_back({cur[u], cur[w], nu, nw});
+            cur[u] = nu;
+          }
+          cur[w] = nw;
+        }
+      }
+    }
+    for (int q = 0; q < n; ++q) {
+      if (zz) {
+        one_qubit(q, false);  // X rotation
+      } else {
+        one_qubit(q, false);  // H
+        one_qubit(q, diag);   // Z rotation
+        one_qubit(q, false);  // H
+      }
+    }
+  }
+  for (int q = 0; q < n; ++q) T.tensors.push_back({cur[q]});  // <0|
+  return T;
+}
+
 }  // namespace
+
+CostEstimate cost_model(int n, const std::vector<std::pair<int32_t, int32_t>>& edges, int p, int variant,
+                        const OrderOptions& O) {
+  const IndexNet T = variant_network(n, edges, p, variant);
+  // the orderer works on the interaction graph: a tensor links every pair of
+  // its indices
+  Cone C;
+  C.n_idx = T.n_idx;
+  for (const auto& t : T.tensors)
+    for (size_t i = 0; i < t.size(); ++i)
+      for (size_t j = i + 1; j < t.size(); ++j) C.leaves.push_back({0, t[i], t[j]});
+  order_one(C, O, 1);
+  // bucket elimination along the order: width and sum of 2^|union|
+  std::vector<int> pos(T.n_idx);
+  for (int s = 0; s < T.n_idx; ++s) pos[C.order[s]] = s;
+  std::vector<std::vector<std::vector<int>>> pending(T.n_idx);  // tensors waiting at each bucket
+  auto place = [&](const std::vector<int>& t) {
+    int first = t[0];
+    for (int x : t)
+      if (pos[x] < pos[first]) first = x;
+    pending[pos[first]].push_back(t);
+  };
+  for (const auto& t : T.tensors) place(t);
+  CostEstimate R;
+  R.n_indices = T.n_idx;
+  R.n_tensors = (int)T.tensors.size();
+  double ops = 0;
+  for (int s = 0; s < T.n_idx; ++s) {
+    std::vector<int> uni;
+    for (const auto& t : pending[s]) uni.insert(uni.end(), t.begin(), t.end());
+    std::sort(uni.begin(), uni.end());
+    uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+    if (uni.empty()) continue;
+    ops += std::ldexp(1.0, (int)uni.size());
+    std::vector<int> out;
+    for (int x : uni)
+      if (pos[x] != s) out.push_back(x);
+    R.width = std::max(R.width, (int)out.size());
+    if (!out.empty()) place(out);
+  }
+  R.log2_ops = ops > 0 ? std::log2(ops) : 0.0;
+  return R;
+}
 
 // Symbolic bucket elimination (Section III.B): the bucket of v holds every
 // tensor whose earliest-eliminated index is v; its output carries the union of

@@ -144,6 +144,17 @@ struct OrderOptions {
   uint64_t seed = 0;
 };
 void order_cones(Plan& P, const OrderOptions& O, int n_threads);
+
+// Contraction cost of the single-amplitude network under one of the paper's
+// four constructions (0 default, 1 diagonal, 2 ZZ gates, 3 diagonal + ZZ),
+// ordered by the same greedy / randomized greedy orderer.
+struct CostEstimate {
+  int n_indices = 0, n_tensors = 0;
+  int width = 0;          // largest intermediate rank
+  double log2_ops = 0;    // log2 of sum over buckets of 2^|union|
+};
+CostEstimate cost_model(int n, const std::vector<std::pair<int32_t, int32_t>>& edges, int p, int variant,
+                        const OrderOptions& O);
 // Builds every cone's forward and adjoint programs, places the buffers by
 // lifetime (recomputing bucket outputs in the adjoint sweep where the memory
 // budget requires it) and resolves all operand offsets.

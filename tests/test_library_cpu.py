@@ -195,3 +195,58 @@ def test_amplitude_network_plan(p):
         assert st["n_tensors"][0] == n * (p + 2) + p * len(edges)
     with pytest.raises(QtnError):
         a.amplitude()
+
+
+@pytest.mark.parametrize("variant", ["default", "diagonal", "zz", "diagonal_zz"])
+def test_cost_model_networks_match_the_oracle_constructions(variant):
+    """The cost model builds the same networks as the oracle's constructions
+    (which contract to the state-vector amplitude): same index and tensor
+    counts for every depth."""
+    from oracle import variants
+    from paper_2106_15740_amd import costmodel
+
+    n, edges = 8, random_regular_graph(8, 3, 4)
+    for p in (1, 2, 3):
+        c = costmodel.cost(n, edges, p, variant, repeats=0)
+        assert (c["n_indices"], c["n_tensors"]) == variants.counts(n, edges, p, variant)
+
+
+def test_cost_model_reproduces_the_papers_ordering_of_constructions():
+    """On seeded 40-vertex 3-regular graphs: the diagonal simplification lowers
+    the width at every depth, ZZ gates alone barely help (the paper's remark),
+    and diagonal + ZZ is the cheapest; at p = 5 it saves more than 2^20 in
+    operations (the paper reports up to 10^7 between the two curves)."""
+    from paper_2106_15740_amd import costmodel
+
+    res = costmodel.ops_vs_p(n=40, ps=(1, 3, 5), seeds=(0, 1))
+    for i in range(3):
+        d, dg, z, dz = (res[v][i] for v in costmodel.VARIANTS)
+        assert dz[1] <= dg[1] < d[1] and dz[1] < z[1]
+        assert dz[3] <= dg[3] <= d[3]
+    assert res["default"][2][1] - res["diagonal_zz"][2][1] > 20
+    assert abs(res["zz"][2][1] - res["default"][2][1]) < 10
+
+
+def test_cost_model_table_limits():
+    """Table I's structure: with 4 GB a 40-vertex graph reaches a larger p with
+    the diagonal simplification than with the default construction, and the
+    800 TB machine reaches at least as far as the laptop."""
+    from paper_2106_15740_amd import costmodel
+
+    lap = costmodel.max_p(40, costmodel.LAPTOP_BYTES, seeds=(0, 1), p_max=6)
+    big = costmodel.max_p(40, costmodel.SUPERCOMPUTER_BYTES, seeds=(0, 1), p_max=6)
+    assert lap["diagonal_zz"] >= lap["diagonal"] > lap["default"] >= 1
+    for v in costmodel.VARIANTS:
+        assert big[v] >= lap[v]
+
+
+def test_cost_model_more_repeats_never_cost_more():
+    """The randomized greedy orderer keeps the cheapest of the greedy order and
+    its repeats, drawn from one seeded stream, so more repeats never raise the
+    estimate (the trade-off of ordering time against FLOPs, p = 1, N = 160)."""
+    from paper_2106_15740_amd import costmodel
+
+    rows = costmodel.ops_vs_order_time(n=160, repeats=(0, 2, 8))
+    ops = [r[3] for r in rows]
+    assert all(b <= a + 1e-9 for a, b in zip(ops, ops[1:]))
+    assert all(r[1] >= 0 for r in rows)

@@ -347,3 +347,33 @@ def test_amplitude_closed_forms():
     g = [0.9, 0.4]
     tot = sum(abs(sv.amplitude(n, edges, g, b, x)) ** 2 for x in range(1 << n))
     assert abs(tot - 1) < 1e-12
+
+
+@pytest.mark.parametrize("variant", ["default", "diagonal", "zz", "diagonal_zz"])
+def test_variant_networks_give_the_amplitude(variant):
+    """Each of the paper's four network constructions contracts to the
+    state-vector amplitude <0...0|gamma beta> (so the constructions, whose
+    sizes the cost model compares, are the same computation)."""
+    from oracle import variants
+
+    for n, seed, p in ((4, 0, 1), (6, 1, 2)):
+        edges = random_regular_graph(n, 3, seed) if n % 2 == 0 else [(0, 1)]
+        rng = np.random.default_rng(seed + 7)
+        g, b = rng.uniform(0, np.pi, p), rng.uniform(0, np.pi, p)
+        assert abs(variants.amplitude(n, edges, g, b, variant) - sv.amplitude(n, edges, g, b)) < 1e-12
+
+
+def test_variant_network_sizes_closed_form():
+    """Index and tensor counts of the four constructions: 2N + p(5|E| + 3N)
+    indices for the default circuit, 2N + p(2|E| + 2N) with the diagonal
+    simplification, 2N + p(2|E| + N) for ZZ gates and 2N + pN for diagonal +
+    ZZ; tensors 3N + p(3|E| + 3N), 3N + p(3|E| + 3N), 3N + p(|E| + N) twice."""
+    from oracle import variants
+
+    n, edges = 8, random_regular_graph(8, 3, 4)
+    m = len(edges)
+    for p in (1, 2, 3):
+        assert variants.counts(n, edges, p, "default") == (2 * n + p * (5 * m + 3 * n), 3 * n + p * (3 * m + 3 * n))
+        assert variants.counts(n, edges, p, "diagonal") == (2 * n + p * (2 * m + 2 * n), 3 * n + p * (3 * m + 3 * n))
+        assert variants.counts(n, edges, p, "zz") == (2 * n + p * (2 * m + n), 3 * n + p * (m + n))
+        assert variants.counts(n, edges, p, "diagonal_zz") == (2 * n + p * n, 3 * n + p * (m + n))
