@@ -66,6 +66,10 @@ typedef struct {
   int32_t merge_bits;   /* a bucket is merged into its consumer while the merged step's union has <= merge_bits
                            bits (0: one step per bucket; at most 16) */
   int32_t merge_lam_bits; /* ... and its leaf-product table carries <= merge_lam_bits indices (0..16) */
+  int32_t lane_low;     /* 1: split buckets map lanes to their lowest union bits, summed or not (contiguous input
+                           reads, partial sums combined across lanes); 0: to their lowest output bits first */
+  int32_t fuse_adjoint; /* 1: the adjoint of a split bucket computes every input adjoint in one pass over its
+                           union (output adjoint and inputs read once); 0: one pass per input adjoint */
 } qtn_tuning;
 
 typedef struct {

@@ -37,7 +37,8 @@ class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("lane_cap", C.c_int32), ("seq_max_bits", C.c_int32),
                 ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32),
                 ("lds_kb", C.c_int32), ("par_bits", C.c_int32), ("merge_bits", C.c_int32),
-                ("merge_lam_bits", C.c_int32)]
+                ("merge_lam_bits", C.c_int32), ("lane_low", C.c_int32),
+                ("fuse_adjoint", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

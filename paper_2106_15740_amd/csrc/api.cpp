@@ -149,9 +149,10 @@ qtn_status rebuild_programs(qtn_net* n) {
   build_items(n->P, true);
   n->max_nin = 1;
   for (const OpDesc& d : n->P.ops)
-    if (d.kind == OP_CONTRACT) n->max_nin = std::max(n->max_nin, (int)d.n_in);
+    if (d.kind == OP_CONTRACT || d.kind == OP_ADJOINT) n->max_nin = std::max(n->max_nin, (int)d.n_in);
   n->has_wide = false;
-  for (const OpDesc& d : n->P.ops) n->has_wide |= d.kind == OP_CONTRACT && (d.flags & F_WIDE);
+  for (const OpDesc& d : n->P.ops)
+    n->has_wide |= (d.kind == OP_CONTRACT && (d.flags & F_WIDE)) || d.kind == OP_ADJOINT;
   if (n->ctx->device < 0) {  // host-only context: plan without upload
     for (int g = 0; g < 2; ++g)
       n->prog[g].n_nodes = (int32_t)(g ? n->P.node_init_grad.size() : n->P.node_init_fwd.size());
@@ -656,6 +657,8 @@ qtn_status qtn_get_tuning(const qtn_net* n, qtn_tuning* out) {
   out->par_bits = n->P.tune.par_bits;
   out->merge_bits = n->P.tune.merge_bits;
   out->merge_lam_bits = n->P.tune.merge_lam_bits;
+  out->lane_low = n->P.tune.lane_low;
+  out->fuse_adjoint = n->P.tune.fuse_adjoint;
   return QTN_OK;
 }
 
@@ -673,7 +676,11 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->par_bits < 8 || t->par_bits > 24) return fail(QTN_EINVAL, "par_bits must be in 8..24");
   if (t->merge_bits < 0 || t->merge_bits > 16) return fail(QTN_EINVAL, "merge_bits must be in 0..16");
   if (t->merge_lam_bits < 0 || t->merge_lam_bits > 16) return fail(QTN_EINVAL, "merge_lam_bits must be in 0..16");
+  if (t->lane_low != 0 && t->lane_low != 1) return fail(QTN_EINVAL, "lane_low must be 0 or 1");
+  if (t->fuse_adjoint != 0 && t->fuse_adjoint != 1) return fail(QTN_EINVAL, "fuse_adjoint must be 0 or 1");
   n->P.tune.threads = th;
+  n->P.tune.lane_low = t->lane_low;
+  n->P.tune.fuse_adjoint = t->fuse_adjoint;
   n->P.tune.par_bits = t->par_bits;
   n->P.tune.merge_bits = t->merge_bits;
   n->P.tune.merge_lam_bits = t->merge_lam_bits;
@@ -791,9 +798,10 @@ qtn_status qtn_time_wide_ops(qtn_net* n, int32_t with_grad, int32_t min_width, v
     for (auto& r : ranges)
       for (int32_t o = r.first; o < r.second; ++o) {
         const OpDesc& d = n->P.ops[o];
-        if (d.kind != OP_CONTRACT || d.nbits - 1 < min_width) continue;
-        double b = std::ldexp(1.0, __builtin_popcount(d.out_mask));
-        for (int i = 0; i < d.n_in; ++i) b += std::ldexp(1.0, __builtin_popcount(d.in_mask[i]));
+        if ((d.kind != OP_CONTRACT && d.kind != OP_ADJOINT) || d.nbits - 1 < min_width) continue;
+        double b = d.kind == OP_CONTRACT ? std::ldexp(1.0, __builtin_popcount(d.out_mask)) : 0.0;
+        for (int i = 0; i < d.n_in; ++i)
+          b += std::ldexp(1.0, __builtin_popcount(d.in_mask[i])) * (((d.adj_sel >> i) & 1u) ? 2 : 1);
         b *= n->elem;
         HIPCHECK(launch_op(n->c128, n->d_ops, d, o, env, n->P.tune.threads, 4096, st));  // warm
         HIPCHECK(hipEventRecord(e0, st));

@@ -314,10 +314,13 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
 // every other input holds it and is loaded as a 16-byte pair), UU = 2^nu
 // outputs per thread.  All loads of a step are issued before the first use.
 // When the op has more per-thread output bits than UU covers (nu > log2 UU,
-// at most one more), the step repeats for the extra bit.  The block range
+// at most one more), the step repeats for the extra bit.  KS: the UU slots
+// hold the first log2 UU bits of the summation loop instead of outputs (ops
+// with nu = 0 and nk >= log2 UU), so reductions keep as many loads in flight
+// as element-wise ops and add the slots before the store.  The block range
 // [blk_begin, blk_end) is an aligned power of two of at least one block per
 // sub-block; offsets fit 32 bits (tensor rank <= 30).
-template <typename R, int NIN, int S0, int UU>
+template <typename R, int NIN, int S0, int UU, bool KS = false>
 __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
                                           int64_t blk_end, int64_t wg_rank, int64_t wg_count,
                                           RedBuf<typename CT<R>::E>* __restrict__ red) {
@@ -352,13 +355,16 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
     const uint32_t sh = d.lsh[MAXIN][j];
     if (j < nl && sh != LSH_NONE) lout |= ((uint32_t)(lane >> j) & 1u) << sh;
   }
-  // offsets of the UU outputs of a thread (unroll bits zbit[nl], zbit[nl + 1])
+  // offsets of the UU slots of a thread: output bits zbit[nl], zbit[nl + 1],
+  // or with KS the first loop bits (summed, so their output stride is 0)
+  constexpr int LGU = UU == 4 ? 2 : (UU == 2 ? 1 : 0);
+  const int zs = KS ? nl + d.nu : nl;
   uint32_t us[NIN][UU], uo[UU];
 #pragma unroll
   for (int i = 0; i <= NIN; ++i) {
     const uint32_t m = i < NIN ? mask[i] : out_mask;
-    const uint32_t s0 = UU > 1 ? bit_stride(m, d.zbit[nl]) : 0u;
-    const uint32_t s1 = UU > 2 ? bit_stride(m, d.zbit[nl + 1]) : 0u;
+    const uint32_t s0 = UU > 1 ? bit_stride(m, d.zbit[zs]) : 0u;
+    const uint32_t s1 = UU > 2 ? bit_stride(m, d.zbit[zs + 1]) : 0u;
 #pragma unroll
     for (int k = 0; k < UU; ++k) {
       const uint32_t v = ((k & 1) ? s0 : 0u) + ((k & 2) ? s1 : 0u);
@@ -369,14 +375,14 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
     }
   }
   E* outp = arena + d.out_off;
-  constexpr int NU = UU == 4 ? 2 : (UU == 2 ? 1 : 0);
+  constexpr int NU = KS ? 0 : LGU;
   const int nrep = d.nu > NU ? 2 : 1;
   uint32_t rs[NIN], rso = 0;  // strides of the repeated output bit
 #pragma unroll
   for (int i = 0; i < NIN; ++i) rs[i] = nrep > 1 ? bit_stride(mask[i], d.zbit[nl + NU]) : 0u;
   if (nrep > 1) rso = bit_stride(out_mask, d.zbit[nl + NU]);
-  const int zk0 = nl + d.nu, zb0 = nl + d.nu + nk;
-  const int nloop = 1 << nk;
+  const int zk0 = nl + d.nu + (KS ? LGU : 0), zb0 = nl + d.nu + nk;
+  const int nloop = 1 << (KS ? nk - LGU : nk);
   const uint32_t base_blk = (uint32_t)blk_begin;
   const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
   const int lg_st = lg_nblk - sbits;
@@ -469,8 +475,17 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
         }
       }
       if (carry) continue;  // uniform
+      if (KS) {
 #pragma unroll
-      for (int k = 0; k < UU; ++k) {
+        for (int k = 1; k < UU; ++k) {
+          acc0[0] = cadd(acc0[0], acc0[k]);
+          acc1[0] = cadd(acc1[0], acc1[k]);
+          acc0[k] = E{0, 0};
+          acc1[k] = E{0, 0};
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < (KS ? 1 : UU); ++k) {
         E s0 = acc0[k], s1 = acc1[k];
         acc0[k] = E{0, 0};
         acc1[k] = E{0, 0};
@@ -530,7 +545,11 @@ template <typename R, int NIN, int S0>
 __device__ __forceinline__ void exec_wide_u(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
                                             int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
   constexpr int M = WideMaxU<R>::in_persistent;
-  if (d.nu == 0 || M == 1)
+  if (M == 1 || (d.nu == 0 && d.nk == 0))
+    exec_wide<R, NIN, S0, 1>(d, arena, b0, b1, r, c, red);
+  else if (d.nu == 0 && d.nk >= (M == 4 ? 2 : 1))
+    exec_wide<R, NIN, S0, M, true>(d, arena, b0, b1, r, c, red);
+  else if (d.nu == 0)
     exec_wide<R, NIN, S0, 1>(d, arena, b0, b1, r, c, red);
   else
     exec_wide<R, NIN, S0, M>(d, arena, b0, b1, r, c, red);
@@ -549,6 +568,201 @@ __device__ __forceinline__ void exec_wide_any(const OpDesc& d, typename CT<R>::E
     case 7: exec_wide_u<R, 3, 1>(d, arena, b0, b1, r, c, red); break;
     case 8: exec_wide_u<R, 4, 0>(d, arena, b0, b1, r, c, red); break;
     default: exec_wide_u<R, 4, 1>(d, arena, b0, b1, r, c, red); break;
+  }
+}
+
+// ------------------------------------------------------------------ fused adjoint
+// Executor of OP_ADJOINT: every input adjoint of one wide bucket in one pass
+// over its union, so the output adjoint and each input are read once.  Input
+// 0 is the output adjoint (without bit 0), inputs 1..NIN-1 hold bit 0 and are
+// loaded as pairs.  For each union element the adjoint of input i receives
+// the output adjoint times the product of the other inputs, formed from
+// prefix and suffix products.  An output that holds the loop bits gets one
+// value per loop step: combined across the lanes it sums (shuffles; a
+// sub-block is at most one wavefront) and stored.  Every other output sums
+// the loop steps in registers and is written once per run of block steps
+// that flip only bits it lacks: stored, or added with atomics into zeroed
+// memory when it sums a block bit.  SL = 2: the first loop bit is unrolled
+// into two slots whose loads are in flight together.  Block ranges as in
+// exec_wide.
+template <typename R, int NIN, int SL>
+__device__ __forceinline__ void exec_adjoint(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                             int64_t blk_end, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk;
+  const int sbits = 31 - __clz(blockDim.x >> nl);
+  const int sub = tid >> nl;
+  const int lane = tid & ((1 << nl) - 1);
+  const int zk0 = nl + (SL > 1 ? 1 : 0), zb0 = nl + nk;
+  uint32_t blockbits = 0;
+  for (int z = zb0; z < d.nbits - 1; ++z) blockbits |= 1u << d.zbit[z];
+  uint32_t mask[NIN], loff[NIN], lsum[NIN], ss[NIN];
+  bool hold[NIN], atom[NIN];
+  const E* inp[NIN];
+  E* outp[NIN];
+  uint32_t aheld = 0;  // bits held by an output that accumulates over the loop
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    inp[i] = arena + d.in_off[i];
+    outp[i] = arena + (i ? d.adj_off[i] : 0);
+    hold[i] = i > 0 && nk > 0 && ((mask[i] >> d.zbit[nl]) & 1u);
+    atom[i] = (blockbits & ~mask[i]) != 0;
+    if (i > 0 && !hold[i]) aheld |= mask[i];
+    uint32_t o = 0, ls = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl) {
+        if (sh != LSH_NONE)
+          o |= ((uint32_t)(lane >> j) & 1u) << sh;
+        else
+          ls |= 1u << j;
+      }
+    }
+    loff[i] = o;
+    lsum[i] = ls;
+    ss[i] = SL > 1 ? bit_stride(mask[i], d.zbit[nl]) : 0u;
+  }
+  const int nloop = 1 << (nk - (SL > 1 ? 1 : 0));
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_st = lg_nblk - sbits;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_st - lg_chunk);
+  // combine a pair across the lanes in ls, then store or add it
+  auto put = [&](E* p, E s0, E s1, uint32_t ls, bool at) {
+    for (int j = 0; j < 6; ++j)
+      if ((ls >> j) & 1u) {
+        s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+        s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+      }
+    if ((lane & ls) == 0) {
+      if (at) {
+        atomic_add_c(p, s0);
+        atomic_add_c(p + 1, s1);
+      } else {
+        store_pair(p, s0, s1);
+      }
+    }
+  };
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t q0 = (uint32_t)ch << lg_chunk;
+    const uint32_t blk = base_blk + (q0 << sbits) + (uint32_t)sub;
+    uint32_t boff[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    for (int j = 0; j < d.nb; ++j)
+      if ((blk >> j) & 1u) {
+        const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+      }
+    E acc0[NIN], acc1[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) {
+      acc0[i] = E{0, 0};
+      acc1[i] = E{0, 0};
+    }
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      if (c) {
+        const int t = __ffs(c) - 1;
+        const bool up = ((c ^ (c >> 1)) >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
+        }
+      }
+      // an accumulating output keeps its sums while the next step flips a bit
+      // it does not hold
+      const uint32_t nxt = c + 1 < chunk ? 1u << d.zbit[zb0 + sbits + __ffs(c + 1) - 1] : 0u;
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = boff[i];
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
+        }
+        E ob[SL], a0[SL][NIN], a1[SL][NIN];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          ob[s] = inp[0][koff[0] + (s ? ss[0] : 0u)];
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) load_pair(inp[i] + koff[i] + (s ? ss[i] : 0u), a0[s][i], a1[s][i]);
+        }
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          E ex0[NIN], ex1[NIN];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            // prefix products pr[i] = ob * x[1] ... x[i-1]; ex[i] = pr[i] * suffix
+            E pr[NIN];
+            pr[1] = ob[s];
+#pragma unroll
+            for (int i = 1; i + 1 < NIN; ++i) pr[i + 1] = cmul(pr[i], h ? a1[s][i] : a0[s][i]);
+            E suf = E{1, 0};
+#pragma unroll
+            for (int i = NIN - 1; i >= 1; --i) {
+              const E x = h ? a1[s][i] : a0[s][i];
+              const E e = i == NIN - 1 ? pr[i] : cmul(pr[i], suf);
+              suf = i == NIN - 1 ? x : cmul(x, suf);
+              if (h)
+                ex1[i] = e;
+              else
+                ex0[i] = e;
+            }
+          }
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) {
+            if (hold[i]) {
+              put(outp[i] + koff[i] + (s ? ss[i] : 0u), ex0[i], ex1[i], lsum[i], atom[i]);
+            } else {
+              acc0[i] = cadd(acc0[i], ex0[i]);
+              acc1[i] = cadd(acc1[i], ex1[i]);
+            }
+          }
+        }
+      }
+      if (nxt && !(aheld & nxt)) continue;  // uniform: every accumulating output carries
+#pragma unroll
+      for (int i = 1; i < NIN; ++i) {
+        if (hold[i] || (nxt && !(mask[i] & nxt))) continue;
+        put(outp[i] + boff[i], acc0[i], acc1[i], lsum[i], atom[i]);
+        acc0[i] = E{0, 0};
+        acc1[i] = E{0, 0};
+      }
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void exec_adjoint_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                                 int64_t r, int64_t c) {
+  constexpr bool two = WideMaxU<R>::in_persistent > 1;
+  const bool sl = two && d.nk >= 1;
+  switch (d.n_in * 2 + (sl ? 1 : 0)) {
+    case 6: exec_adjoint<R, 3, 1>(d, arena, b0, b1, r, c); break;
+    case 7: exec_adjoint<R, 3, two ? 2 : 1>(d, arena, b0, b1, r, c); break;
+    case 8: exec_adjoint<R, 4, 1>(d, arena, b0, b1, r, c); break;
+    case 9: exec_adjoint<R, 4, two ? 2 : 1>(d, arena, b0, b1, r, c); break;
+    default: break;
   }
 }
 
@@ -719,6 +933,9 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
       else
         exec_contract_any<R, MAXNIN, USE_LDS>(d, arena, b0, b1, wg_rank, wg_count, red, lds);
       break;
+    case OP_ADJOINT:
+      if constexpr (WIDE && !USE_LDS) exec_adjoint_any<R>(d, arena, b0, b1, wg_rank, wg_count);
+      break;
     case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
     case OP_RESULT:
       if (wg_rank == 0) exec_result<R>(d, arena, env, USE_LDS ? lds : nullptr);
@@ -760,14 +977,23 @@ __global__ void __launch_bounds__(512) op_kernel(const OpDesc* __restrict__ ops,
 }
 
 // One F_WIDE op per launch, specialised like the executor.
-template <typename R, int NIN, int S0, int UU>
+template <typename R, int NIN, int S0, int UU, bool KS>
 __global__ void __launch_bounds__(512) wide_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
   __shared__ RedBuf<typename CT<R>::E> red;
   __shared__ OpDesc d;
   stage_desc(d, ops, op);
   const int64_t nblocks = int64_t(1) << d.nb;
-  exec_wide<R, NIN, S0, UU>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x,
+  exec_wide<R, NIN, S0, UU, KS>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x,
                             &red);
+}
+
+// One OP_ADJOINT op per launch.
+template <typename R, int NIN, int SL>
+__global__ void __launch_bounds__(512) adjoint_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  __shared__ OpDesc d;
+  stage_desc(d, ops, op);
+  const int64_t nblocks = int64_t(1) << d.nb;
+  exec_adjoint<R, NIN, SL>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x);
 }
 
 // Leaf tables, results, zeroing and leaf gradients (one op per launch).
@@ -850,7 +1076,7 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
           for (int j = 0; j < nd; ++j) {
             const OpDesc& d = sdesc[j];
             if (j > 0 && (d.flags & F_SYNC)) __syncthreads();
-            const int64_t nblocks = d.kind == OP_CONTRACT ? (int64_t(1) << d.nb) : 1;
+            const int64_t nblocks = (d.kind == OP_CONTRACT || d.kind == OP_ADJOINT) ? (int64_t(1) << d.nb) : 1;
             const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
             const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
             if (lds)
@@ -1065,7 +1291,7 @@ template <typename R>
 static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads, int max_grid,
                               hipStream_t st) {
   int64_t grid = 1;
-  if (h.kind == OP_CONTRACT) {
+  if (h.kind == OP_CONTRACT || h.kind == OP_ADJOINT) {
     const int64_t nsub = threads >> h.nl;
     const int64_t nblocks = int64_t(1) << h.nb;
     grid = (nblocks + nsub - 1) / nsub;
@@ -1079,6 +1305,17 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
   // a power of two: the contraction executor splits its blocks by shifts
   grid = int64_t(1) << (63 - __builtin_clzll((unsigned long long)grid));
   const dim3 g((unsigned)grid), b(threads);
+  if (h.kind == OP_ADJOINT) {
+    const bool sl = h.nk >= 1;
+    switch (h.n_in * 2 + (sl ? 1 : 0)) {
+      case 6: hipLaunchKernelGGL((adjoint_kernel<R, 3, 1>), g, b, 0, st, d_ops, op, env); break;
+      case 7: hipLaunchKernelGGL((adjoint_kernel<R, 3, 2>), g, b, 0, st, d_ops, op, env); break;
+      case 8: hipLaunchKernelGGL((adjoint_kernel<R, 4, 1>), g, b, 0, st, d_ops, op, env); break;
+      case 9: hipLaunchKernelGGL((adjoint_kernel<R, 4, 2>), g, b, 0, st, d_ops, op, env); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (h.kind != OP_CONTRACT) {
     hipLaunchKernelGGL((misc_kernel<R>), g, b, 0, st, d_ops, op, env);
     return hipGetLastError();
@@ -1086,15 +1323,21 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
   if (h.flags & F_WIDE) {
     const bool s0 = !(h.in_mask[0] & 1u);
     const int uu = 1 << h.nu;
-#define QTN_WIDE(N, S, UU) hipLaunchKernelGGL((wide_kernel<R, N, S, UU>), g, b, 0, st, d_ops, op, env)
+    // no output bits per thread: the slots take the first loop bits (one or two)
+    const int ks = h.nu == 0 ? std::min(h.nk, WideMaxU<R>::value == 4 ? 2 : 1) : 0;
+#define QTN_WIDE(N, S, UU, KS) hipLaunchKernelGGL((wide_kernel<R, N, S, UU, KS>), g, b, 0, st, d_ops, op, env)
 #define QTN_WIDE_U(N, S)                              \
   do {                                                \
-    if (uu == 1)                                      \
-      QTN_WIDE(N, S, 1);                              \
+    if (ks == 1)                                      \
+      QTN_WIDE(N, S, 2, true);                        \
+    else if (ks == 2)                                 \
+      QTN_WIDE(N, S, 4, true);                        \
+    else if (uu == 1)                                 \
+      QTN_WIDE(N, S, 1, false);                       \
     else if (uu == 2 || WideMaxU<R>::value < 4)       \
-      QTN_WIDE(N, S, 2);                              \
+      QTN_WIDE(N, S, 2, false);                       \
     else                                              \
-      QTN_WIDE(N, S, WideMaxU<R>::value);             \
+      QTN_WIDE(N, S, WideMaxU<R>::value, false);      \
   } while (0)
     switch (h.n_in * 2 + (s0 ? 1 : 0)) {
       case 2: QTN_WIDE_U(1, 0); break;

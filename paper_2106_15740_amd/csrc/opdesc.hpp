@@ -17,6 +17,7 @@ enum OpKind : int32_t {
   OP_ZERO = 3,      // zero a range of the arena
   OP_LEAFGRAD = 4,  // dR/dtheta from the adjoint of one leaf-product table
   OP_COPYIN = 5,    // copy a cone's leaf-product block into its LDS window (persistent sweep only)
+  OP_ADJOINT = 6,   // every input adjoint of one wide bucket in one pass over its union (see adj_off)
 };
 
 enum OpFlags : int32_t {
@@ -59,6 +60,14 @@ struct alignas(16) OpDesc {
   // when lsh[i][j] == LSH_NONE
   uint8_t lsh[MAXIN + 1][MAXLANE];
   uint8_t pad_[14];
+  // OP_ADJOINT: input 0 is the output adjoint (without the eliminated index,
+  // bit 0), inputs 1.. hold bit 0; for every i with bit i of adj_sel set, the
+  // adjoint of input i (same index set in_mask[i]) is written at adj_off[i]:
+  // stored element by element when in_mask[i] holds every union bit, else
+  // summed into zeroed memory with atomics.  out_off / out_mask are unused.
+  int64_t adj_off[MAXIN];
+  uint32_t adj_sel;
+  uint32_t pad2_[3];
 };
 static_assert(sizeof(OpDesc) % 16 == 0, "OpDesc is copied in 16-byte words");
 

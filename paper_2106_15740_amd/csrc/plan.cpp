@@ -8,6 +8,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <map>
 #include <functional>
 #include <iterator>
 #include <cstring>
@@ -645,16 +646,34 @@ void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool w
   const int max_lanes = std::min({T.lane_cap, MAXLANE, 31 - __builtin_clz((unsigned)std::max(T.threads, 1))});
   std::vector<int> lanes, unroll, loop, blocks;
   size_t fi = 0, si = 0;
-  // lanes: the lowest output bits (coalesced stores and, since every tensor
-  // keeps its indices in elimination order, mostly coalesced loads); small
-  // outputs fill the remaining lanes with summed bits (shuffle / LDS reduce)
-  while (fi < freeb.size() && (int)lanes.size() < max_lanes) lanes.push_back(freeb[fi++]);
   d.lane_sum = 0;
-  while (si < sumb.size() && (int)lanes.size() < max_lanes) {
-    d.lane_sum |= 1u << lanes.size();
-    lanes.push_back(sumb[si++]);
+  std::vector<int> rfree, rsum;
+  if (wide && T.lane_low) {
+    // wide ops: lanes on the lowest union bits, summed or not.  Every tensor
+    // keeps its indices in elimination order, so neighbouring lanes read
+    // neighbouring elements of every input; summed lane bits are combined
+    // across lanes (shuffles, LDS above bit 5) before the store
+    for (int u = 1; u < nbits; ++u) {
+      const bool fr = (out_mask >> u) & 1;
+      if ((int)lanes.size() < max_lanes) {
+        if (!fr) d.lane_sum |= 1u << lanes.size();
+        lanes.push_back(u);
+      } else {
+        (fr ? rfree : rsum).push_back(u);
+      }
+    }
+  } else {
+    // lanes: the lowest output bits (coalesced stores and, since every tensor
+    // keeps its indices in elimination order, mostly coalesced loads); small
+    // outputs fill the remaining lanes with summed bits (shuffle / LDS reduce)
+    while (fi < freeb.size() && (int)lanes.size() < max_lanes) lanes.push_back(freeb[fi++]);
+    while (si < sumb.size() && (int)lanes.size() < max_lanes) {
+      d.lane_sum |= 1u << lanes.size();
+      lanes.push_back(sumb[si++]);
+    }
+    rfree.assign(freeb.begin() + fi, freeb.end());
+    rsum.assign(sumb.begin() + si, sumb.end());
   }
-  std::vector<int> rfree(freeb.begin() + fi, freeb.end()), rsum(sumb.begin() + si, sumb.end());
   if (!seq) {
     // several outputs per thread: more loads in flight, block offsets amortised
     // (bounded by the register budget of the kernel variant for this input count)
@@ -730,6 +749,90 @@ void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool w
     }
 }
 
+// Bit split of an OP_ADJOINT op (inputs already set: the output adjoint, then
+// every input of the bucket; output i is the adjoint of input i).  The loop
+// bits are taken from one group of union bits that the same outputs hold:
+// those outputs ("holders") get one value per loop step, combined across the
+// lanes they sum and written at once, so every bit a holder sums must be a
+// lane; the other outputs sum the loop bits in registers and write once per
+// run of block steps that flip only bits they lack.  Lanes (at most 6, one
+// wavefront) are the lowest union bits; among the groups of the other bits,
+// the largest whose holders sum no bit outside the lanes is taken (so
+// holders never need atomics).  An output that sums a block bit is added with atomics
+// into zeroed memory.  Returns false (the bucket keeps one op per input
+// adjoint) for a single input (its adjoint does not read it, so it need not
+// be kept), more than 3 inputs, an input without the eliminated index, no
+// group of at least 2 bits, or too few blocks per tile.
+bool fused_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) {
+  if (d.n_in < 3 || d.n_in > 4 || (d.in_mask[0] & 1u)) return false;
+  d.adj_sel = 0;
+  for (int i = 1; i < d.n_in; ++i) {
+    if (!(d.in_mask[i] & 1u)) return false;
+    d.adj_sel |= 1u << i;
+  }
+  const int max_lanes = std::min({T.lane_cap, 6, 31 - __builtin_clz((unsigned)std::max(T.threads, 1))});
+  // lanes: the lowest union bits (neighbouring lanes read neighbouring
+  // elements of every input)
+  uint32_t lanes = 0;
+  for (int u = 1; u < nbits && __builtin_popcount(lanes) < max_lanes; ++u) lanes |= 1u << u;
+  // group the other bits by the set of outputs that hold them
+  std::map<uint32_t, uint32_t> groups;  // holders -> bits
+  for (int u = 1; u < nbits; ++u) {
+    if ((lanes >> u) & 1u) continue;
+    uint32_t h = 0;
+    for (int i = 1; i < d.n_in; ++i) h |= ((d.in_mask[i] >> u) & 1u) << i;
+    groups[h] |= 1u << u;
+  }
+  uint32_t best_bits = 0;
+  for (const auto& g : groups) {
+    uint32_t req = 0;  // bits some holder sums
+    for (int i = 1; i < d.n_in; ++i)
+      if ((g.first >> i) & 1u) req |= all & ~d.in_mask[i] & ~1u;
+    if ((req & ~lanes) || __builtin_popcount(g.second) < 2) continue;
+    if (__builtin_popcount(g.second) > __builtin_popcount(best_bits)) best_bits = g.second;
+  }
+  if (!best_bits) return false;
+  std::vector<int> lane_v, loopable, others;
+  for (int u = 1; u < nbits; ++u) {
+    if ((lanes >> u) & 1u)
+      lane_v.push_back(u);
+    else
+      (((best_bits >> u) & 1u) ? loopable : others).push_back(u);
+  }
+  const int nl = (int)lane_v.size();
+  const int need = std::max(0, T.par_bits - nl - (int)others.size());
+  int nk = std::max(0, (int)loopable.size() - need);
+  nk = std::min(nk, T.loop_cap);
+  nk = std::max(nk, std::min((int)loopable.size(), 3));
+  const int nb = nbits - 1 - nl - nk;
+  const int64_t nsub = std::max(1, T.threads >> nl);
+  if (std::min<int64_t>(std::max(1, T.tile_blocks), int64_t(1) << nb) < nsub) return false;
+  d.nl = nl;
+  d.nu = 0;
+  d.nk = nk;
+  d.nb = nb;
+  int z = 0;
+  for (int u : lane_v) d.zbit[z++] = (uint8_t)u;
+  for (int u : loopable) d.zbit[z++] = (uint8_t)u;  // loop bits, then block bits of the same group
+  for (int u : others) d.zbit[z++] = (uint8_t)u;
+  for (; z < 32; ++z) d.zbit[z] = 0;
+  uint32_t blockbits = 0;
+  for (int q = nl + nk; q < nbits - 1; ++q) blockbits |= 1u << d.zbit[q];
+  bool atomic = false;
+  for (int i = 1; i < d.n_in; ++i) atomic |= (blockbits & ~d.in_mask[i]) != 0;
+  d.lane_sum = 0;
+  d.out_mask = 0;
+  d.out_off = 0;
+  d.flags = F_WIDE | (atomic ? F_ATOMIC : 0);
+  for (int i = 0; i <= MAXIN; ++i)
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t m = i < d.n_in ? d.in_mask[i] : 0u;
+      const uint32_t u = d.zbit[j];
+      d.lsh[i][j] = (j < d.nl && ((m >> u) & 1u)) ? (uint8_t)__builtin_popcount(m & ((1u << u) - 1u)) : LSH_NONE;
+    }
+  return true;
+}
+
 OpDesc blank(int kind, int cone) {
   OpDesc d;
   std::memset(&d, 0, sizeof(d));
@@ -764,7 +867,8 @@ static void lds_layout(Plan& P) {
     bool ok = C.lam_size <= budget;
     for (int32_t o : prog) {
       const OpDesc& d = P.ops[o];
-      if (d.kind == OP_ZERO || (d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits)) ok = false;
+      if (d.kind == OP_ZERO || d.kind == OP_ADJOINT || (d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits))
+        ok = false;
     }
     if (!ok) continue;
     std::unordered_map<int64_t, int64_t> lam_local;  // leaf tables: offset inside the block
@@ -880,6 +984,12 @@ static void mark_barriers(Plan& P) {
         for (int i = 0; i < d.n_in; ++i)
           rd.push_back(opnd(i, d.in_off[i], int64_t(1) << __builtin_popcount(d.in_mask[i])));
         wr.push_back(opnd(MAXIN, d.out_off, int64_t(1) << __builtin_popcount(d.out_mask)));
+      } else if (d.kind == OP_ADJOINT) {
+        for (int i = 0; i < d.n_in; ++i) {
+          const int64_t sz = int64_t(1) << __builtin_popcount(d.in_mask[i]);
+          rd.push_back({0, d.in_off[i], d.in_off[i] + sz});
+          if ((d.adj_sel >> i) & 1u) wr.push_back({0, d.adj_off[i], d.adj_off[i] + sz});
+        }
       } else if (d.kind == OP_RESULT) {
         for (int i = 0; i < d.n_in; ++i) rd.push_back(opnd(i, d.in_off[i], 1));
         if (d.flags & F_GRAD)
@@ -1065,6 +1175,38 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       d.n_in = ni;
     };
     auto push_adj = [&](OpDesc& d) { push_zeroed(G.adj, d); };
+    auto push_leafgrad = [&]() {
+      OpDesc g = blank(OP_LEAFGRAD, (int)c);
+      g.nbits = Bk.lam_rank();
+      g.in_off[0] = buf_code(BK_LAMADJ, (int)bb);
+      g.aux0 = ref_lo[bb];
+      g.aux1 = ref_n[bb];
+      G.lgrad.push_back(g);
+    };
+    if (!seq && T.fuse_adjoint) {
+      OpDesc d = blank(OP_ADJOINT, (int)c);
+      d.nbits = nbits;
+      add_common(d, -1, true);
+      if (fused_adjoint_bits(d, nbits, all, T)) {
+        int i = 1;
+        if (Bk.lam_mask) d.adj_off[i++] = buf_code(BK_LAMADJ, (int)bb);
+        for (int t = 0; t < nin; ++t) d.adj_off[i++] = buf_code(BK_ADJ, Bk.in_bkt[t]);
+        // outputs summed with atomics (those that sum a block bit) start from zero
+        uint32_t blockbits = 0;
+        for (int q = d.nl + d.nk; q < nbits - 1; ++q) blockbits |= 1u << d.zbit[q];
+        for (int k = 1; k < d.n_in; ++k)
+          if (blockbits & ~d.in_mask[k]) {
+            OpDesc z = blank(OP_ZERO, (int)c);
+            z.out_off = d.adj_off[k];
+            z.in_off[0] = int64_t(1) << __builtin_popcount(d.in_mask[k]);
+            G.adj.push_back(z);
+          }
+        G.adj.push_back(d);
+        for (int t = 0; t < nin; ++t) C.bwd_bytes_alg += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t])) * eb;
+        if (Bk.lam_mask) push_leafgrad();
+        continue;
+      }
+    }
     for (int t = 0; t < nin; ++t) {
       OpDesc d = blank(OP_CONTRACT, (int)c);
       d.nbits = nbits;
@@ -1085,12 +1227,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       d.out_off = buf_code(BK_LAMADJ, (int)bb);
       partition_bits(d, nbits, d.out_mask, seq, T);
       push_adj(d);
-      OpDesc g = blank(OP_LEAFGRAD, (int)c);
-      g.nbits = Bk.lam_rank();
-      g.in_off[0] = buf_code(BK_LAMADJ, (int)bb);
-      g.aux0 = ref_lo[bb];
-      g.aux1 = ref_n[bb];
-      G.lgrad.push_back(g);
+      push_leafgrad();
     }
   }
   return "";
@@ -1120,6 +1257,12 @@ int64_t alloc_cone(Cone& C, const ConeProg& G) {
       case OP_CONTRACT:
         for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], t);
         touch(d.out_off, t);
+        break;
+      case OP_ADJOINT:
+        for (int i = 0; i < d.n_in; ++i) {
+          touch(d.in_off[i], t);
+          if ((d.adj_sel >> i) & 1u) touch(d.adj_off[i], t);
+        }
         break;
       case OP_RESULT:
         for (int i = 0; i < 2 * d.n_in; ++i) touch(d.in_off[i], t);
@@ -1288,6 +1431,12 @@ std::string build_programs(Plan& P, int elem_bytes) {
           for (int i = 0; i < d.n_in; ++i) d.in_off[i] = resolve_off(C, W, d.in_off[i]);
           d.out_off = resolve_off(C, W, d.out_off);
           break;
+        case OP_ADJOINT:
+          for (int i = 0; i < d.n_in; ++i) {
+            d.in_off[i] = resolve_off(C, W, d.in_off[i]);
+            if ((d.adj_sel >> i) & 1u) d.adj_off[i] = resolve_off(C, W, d.adj_off[i]);
+          }
+          break;
         case OP_RESULT:
           for (int i = 0; i < 2 * d.n_in; ++i) d.in_off[i] = resolve_off(C, W, d.in_off[i]);
           break;
@@ -1309,6 +1458,53 @@ std::string build_programs(Plan& P, int elem_bytes) {
       P.cone_copyin[c] = (int32_t)P.ops.size();
       P.ops.push_back(d);
     }
+  return "";
+}
+
+// Invariants of an OP_ADJOINT op that its executor relies on.
+static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
+  const uint32_t all = (uint32_t)((uint64_t(1) << d.nbits) - 1);
+  if (d.nbits <= P.tune.seq_max_bits || !(d.flags & F_WIDE)) return "adjoint op not wide";
+  if (d.n_in < 3 || d.n_in > 4 || d.lds_mask) return "adjoint op with a bad input count or LDS operands";
+  if (d.nu != 0 || d.nl < 1 || d.nl > 6 || d.nl + d.nk + d.nb != d.nbits - 1) return "adjoint op bit partition";
+  if (d.adj_sel != (((1u << d.n_in) - 1u) & ~1u)) return "adjoint op output selection";
+  if ((d.in_mask[0] & 1u) || (d.in_mask[0] & ~all)) return "adjoint op output adjoint mask";
+  for (int i = 1; i < d.n_in; ++i)
+    if (!(d.in_mask[i] & 1u) || (d.in_mask[i] & ~all)) return "adjoint op input mask";
+  uint32_t seen = 0, lanes = 0, loop = 0, blocks = 0;
+  for (int z = 0; z < d.nbits - 1; ++z) {
+    const uint32_t u = d.zbit[z];
+    if (u < 1 || (int)u >= d.nbits || (seen >> u) & 1) return "adjoint op bad zbit";
+    seen |= 1u << u;
+    (z < d.nl ? lanes : (z < d.nl + d.nk ? loop : blocks)) |= 1u << u;
+  }
+  bool atomic = false;
+  for (int i = 1; i < d.n_in; ++i) {
+    const uint32_t held = d.in_mask[i] & loop;
+    if (held != 0 && held != loop) return "adjoint op output holds part of the loop bits";
+    if (held && (all & ~d.in_mask[i] & ~lanes & ~1u)) return "adjoint op loop holder sums a non-lane bit";
+    atomic |= (blocks & ~d.in_mask[i]) != 0;
+  }
+  if (atomic != bool(d.flags & F_ATOMIC)) return "adjoint op atomic flag mismatch";
+  const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
+  if (std::min<int64_t>(std::max(1, P.tune.tile_blocks), int64_t(1) << d.nb) < nsub)
+    return "adjoint op block range smaller than a workgroup step";
+  for (int i = 0; i < d.n_in; ++i) {
+    const int64_t sz = int64_t(1) << __builtin_popcount(d.in_mask[i]);
+    if (d.in_off[i] < 0 || d.in_off[i] + sz > P.arena_grad) return "adjoint op input range out of bounds";
+    if (i > 0 && (d.adj_off[i] < 0 || d.adj_off[i] + sz > P.arena_grad)) return "adjoint op output out of bounds";
+    if (i > 0 && (d.adj_off[i] & 1)) return "adjoint op output pair not aligned";
+    for (int k = 0; k < d.n_in; ++k)
+      if (k > 0 && d.adj_off[k] < d.in_off[i] + sz &&
+          d.in_off[i] < d.adj_off[k] + (int64_t(1) << __builtin_popcount(d.in_mask[k])))
+        return "adjoint op output overlaps an input";
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t m = d.in_mask[i];
+      const uint32_t st = j < d.nl && ((m >> d.zbit[j]) & 1) ? (1u << __builtin_popcount(m & ((1u << d.zbit[j]) - 1))) : 0u;
+      const uint32_t got = d.lsh[i][j] == LSH_NONE ? 0u : (1u << d.lsh[i][j]);
+      if (st != got) return "adjoint op lane shift table mismatch";
+    }
+  }
   return "";
 }
 
@@ -1405,6 +1601,11 @@ std::string validate_plan(const Plan& P) {
   (void)iv;
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const OpDesc& d = P.ops[o];
+    if (d.kind == OP_ADJOINT) {
+      const std::string e = validate_adjoint_op(P, d);
+      if (!e.empty()) return "op " + S(o) + e;
+      continue;
+    }
     if (d.kind != OP_CONTRACT) continue;
     if (d.nl + d.nu + d.nk + d.nb != d.nbits - 1) return "op " + S(o) + "bit partition does not cover the union";
     if (d.flags & F_WIDE) {
@@ -1503,8 +1704,9 @@ void build_items(Plan& P, bool grad) {
       bool open_here = false;
       for (int32_t o = rg.first; o < rg.second; ++o) {
         const OpDesc& d = P.ops[o];
-        const bool wide = d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits;
-        if (d.kind == OP_CONTRACT) cost[c] += std::ldexp(1.0, d.nbits) * (d.n_in + 1);
+        const bool contract = d.kind == OP_CONTRACT || d.kind == OP_ADJOINT;
+        const bool wide = contract && d.nbits > T.seq_max_bits;
+        if (contract) cost[c] += std::ldexp(1.0, d.nbits) * (d.n_in + 1);
         if (wide) {
           close();
           open_here = false;

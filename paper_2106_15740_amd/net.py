@@ -134,7 +134,10 @@ class QaoaNet:
     def set_tuning(self, **kw) -> None:
         t = L.Tuning()
         L.check(self._lib.qtn_get_tuning(self.handle, C.byref(t)))
+        names = {f for f, _ in L.Tuning._fields_}
         for k, v in kw.items():
+            if k not in names:
+                raise ValueError(f"unknown tuning field {k!r} (fields: {sorted(names)})")
             setattr(t, k, int(v))
         L.check(self._lib.qtn_set_tuning(self.handle, C.byref(t)))
         self._ws = {k: v for k, v in self._ws.items() if k == "buf"}

@@ -99,6 +99,31 @@ def test_tuning_roundtrip_and_validation():
     assert ei.value.status == L.QTN_EINVAL
 
 
+@pytest.mark.parametrize("fuse,lane_low", [(0, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("seq_max_bits,threads", [(7, 64), (9, 256), (12, 512)])
+def test_wide_plans_fused_and_separate_adjoints(fuse, lane_low, seq_max_bits, threads):
+    """Wide buckets (p = 4, N = 100) planned with one adjoint pass per input or
+    one fused pass per bucket, under both lane policies, satisfy every plan
+    invariant (validate_plan checks the fused ops' bit groups, atomics flags,
+    output ranges and lane tables); fusing lowers the op count and keeps the
+    algorithmic bytes."""
+    w = workload("p4_n100")
+    infos = {}
+    for f in (0, fuse):
+        net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=None)
+        net.set_tuning(seq_max_bits=seq_max_bits, threads=threads, lane_cap=6, tile_blocks=64, lane_low=lane_low,
+                       fuse_adjoint=f)
+        net.validate()
+        infos[f] = net.info()
+    if fuse:
+        assert infos[1]["n_ops_grad"] < infos[0]["n_ops_grad"]
+        assert infos[1]["bwd_bytes"] == infos[0]["bwd_bytes"]
+    with pytest.raises(ValueError):
+        net.set_tuning(no_such_field=1)
+    with pytest.raises(QtnError):
+        net.set_tuning(fuse_adjoint=2)
+
+
 @pytest.mark.parametrize("edges,n,p", [([(0, 0)], 2, 1), ([(0, 1), (1, 0)], 2, 1), ([(0, 5)], 3, 1),
                                        ([(0, 1)], 2, 0), ([(-1, 1)], 2, 1)])
 def test_invalid_graphs_rejected(edges, n, p):
