@@ -1295,6 +1295,9 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
     const int64_t nsub = threads >> h.nl;
     const int64_t nblocks = int64_t(1) << h.nb;
     grid = (nblocks + nsub - 1) / nsub;
+    // partial sums that meet in atomics: each workgroup walks several block
+    // steps (carrying its sums across them) instead of adding once per step
+    if (h.flags & F_ATOMIC) grid = std::min<int64_t>(grid, 1024);
   } else if (h.kind == OP_LEAF) {
     grid = ((int64_t(1) << h.nbits) + threads - 1) / threads;
   } else if (h.kind == OP_ZERO) {
