@@ -145,6 +145,10 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 qtn_status rebuild_programs(qtn_net* n) {
   std::string err = build_programs(n->P, n->elem);
   if (!err.empty()) return fail(QTN_EUNSUPPORTED, err);
+  // workgroups resident at once: 16 wavefronts per compute unit (the
+  // persistent kernel's register budget), at most the launched grid
+  const int waves_per_wg = std::max(1, n->P.tune.threads / 64);
+  n->P.sched_workers = std::max(1, std::min(n->grid, n->ctx->n_cu * std::max(1, 16 / waves_per_wg)));
   build_items(n->P, false);
   build_items(n->P, true);
   n->max_nin = 1;

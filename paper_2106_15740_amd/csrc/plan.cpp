@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <queue>
 #include <functional>
 #include <iterator>
 #include <cstring>
@@ -1676,15 +1677,8 @@ void build_items(Plan& P, bool grad) {
     bool wide;
     int64_t nblocks;
   };
-  struct Key {
-    int level;
-    double cost;
-    int32_t cone, seg;
-  };
   const size_t nc = P.cones.size();
   std::vector<std::vector<Seg>> segs(nc);
-  std::vector<double> cost(nc, 0.0);
-  std::vector<Key> keys;
   for (size_t c = 0; c < nc; ++c) {
     std::vector<std::pair<int32_t, int32_t>> ranges;
     if (grad) {
@@ -1706,7 +1700,6 @@ void build_items(Plan& P, bool grad) {
         const OpDesc& d = P.ops[o];
         const bool contract = d.kind == OP_CONTRACT || d.kind == OP_ADJOINT;
         const bool wide = contract && d.nbits > T.seq_max_bits;
-        if (contract) cost[c] += std::ldexp(1.0, d.nbits) * (d.n_in + 1);
         if (wide) {
           close();
           open_here = false;
@@ -1728,12 +1721,8 @@ void build_items(Plan& P, bool grad) {
   }
   std::vector<std::vector<int32_t>> node_of(nc);
   int32_t nn = 0;
-  for (size_t c = 0; c < nc; ++c) {
-    for (size_t s = 0; s < segs[c].size(); ++s) {
-      node_of[c].push_back(nn++);
-      keys.push_back({(int)s, cost[c], (int32_t)c, (int32_t)s});
-    }
-  }
+  for (size_t c = 0; c < nc; ++c)
+    for (size_t s = 0; s < segs[c].size(); ++s) node_of[c].push_back(nn++);
   init.assign(nn, 0);
   auto n_items = [&](const Seg& g) -> int32_t {
     if (!g.wide) return 1;
@@ -1742,32 +1731,112 @@ void build_items(Plan& P, bool grad) {
   };
   for (size_t c = 0; c < nc; ++c)
     for (size_t s = 1; s < segs[c].size(); ++s) init[node_of[c][s]] = n_items(segs[c][s - 1]);
-  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
-    if (a.level != b.level) return a.level < b.level;
-    if (a.cost != b.cost) return a.cost > b.cost;
-    return a.cone < b.cone;
-  });
-  for (const Key& k : keys) {
-    const Seg& g = segs[k.cone][k.seg];
-    const int32_t node = node_of[k.cone][k.seg];
-    const bool has_next = (size_t)k.seg + 1 < segs[k.cone].size();
-    int32_t slo = (int32_t)succ.size(), shi = slo;
-    if (has_next) {
-      succ.push_back(node_of[k.cone][k.seg + 1]);
-      shi = slo + 1;
+  // Queue order: a list schedule of the segments on the resident workgroups,
+  // longest remaining chain first.  Durations are estimates (a fixed cost per
+  // item and per op plus bytes at a nominal per-workgroup rate); an item
+  // enters the queue only when its predecessor segment has finished in the
+  // schedule, so every item waits only on items earlier in the queue.
+  auto op_bytes = [&](const OpDesc& d) -> double {
+    double b = 0;
+    if (d.kind == OP_CONTRACT) {
+      b = std::ldexp(1.0, __builtin_popcount(d.out_mask));
+      for (int i = 0; i < d.n_in; ++i) b += std::ldexp(1.0, __builtin_popcount(d.in_mask[i]));
+    } else if (d.kind == OP_ADJOINT) {
+      for (int i = 0; i < d.n_in; ++i)
+        b += std::ldexp(1.0, __builtin_popcount(d.in_mask[i])) * (((d.adj_sel >> i) & 1u) ? 2 : 1);
+    } else if (d.kind == OP_ZERO) {
+      b = (double)d.in_off[0];
     }
-    const int32_t wait_node = k.seg > 0 ? node : -1;
-    // a cone that runs LDS-resident is one narrow segment
-    const bool lds = !P.cone_lds.empty() && P.cone_lds[k.cone] && segs[k.cone].size() == 1 && !g.wide;
-    const int32_t cp = lds ? P.cone_copyin[k.cone] : -1;
-    if (!g.wide) {
-      items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, cp, {0, 0}});
-    } else {
-      const int64_t tb = std::max(1, T.tile_blocks);
-      for (int64_t b = 0; b < g.nblocks; b += tb)
+    return b * T.elem_bytes;
+  };
+  // bytes per microsecond of one workgroup, by kind of work (measured on
+  // MI355X for 256-thread workgroups, four resident per compute unit)
+  auto rate = [](const OpDesc& d) -> double {
+    if (d.kind == OP_ADJOINT) return 7.0e3;
+    if (d.kind != OP_CONTRACT) return 2.0e3;
+    const bool adj = !(d.in_mask[0] & 1u);
+    const bool red = __builtin_popcount(d.out_mask) < d.nbits - (adj ? 0 : 1);
+    return adj ? (red ? 2.6e3 : 6.2e3) : 3.7e3;
+  };
+  std::vector<std::vector<double>> item_us(nc), span(nc);  // per segment: one item's duration
+  for (size_t c = 0; c < nc; ++c) {
+    for (const Seg& g : segs[c]) {
+      double t = 2.0;
+      if (g.wide) {
+        const OpDesc& d = P.ops[g.r[0]];
+        t += op_bytes(d) / (double)n_items(g) / rate(d);
+      } else {
+        for (int r = 0; r < 2; ++r)
+          if (g.r[2 * r] >= 0)
+            for (int32_t o = g.r[2 * r]; o < g.r[2 * r + 1]; ++o) t += 4.0 + op_bytes(P.ops[o]) / 1.7e3;
+      }
+      item_us[c].push_back(t);
+    }
+    span[c].assign(segs[c].size() + 1, 0.0);  // remaining chain length from each segment
+    for (size_t s = segs[c].size(); s-- > 0;) span[c][s] = span[c][s + 1] + item_us[c][s];
+  }
+  const int workers = std::max(1, P.sched_workers);
+  struct Ready {
+    double prio;
+    int32_t cone, seg, item;
+    bool operator<(const Ready& o) const {
+      if (prio != o.prio) return prio < o.prio;
+      if (cone != o.cone) return cone > o.cone;
+      return item > o.item;
+    }
+  };
+  struct Done {
+    double t;
+    int32_t cone, seg;
+    bool operator<(const Done& o) const { return t > o.t; }
+  };
+  std::priority_queue<Ready> ready;
+  std::priority_queue<Done> running;
+  std::vector<std::vector<int32_t>> left(nc);  // unfinished items per segment
+  auto release = [&](size_t c, size_t s) {
+    const int32_t k = n_items(segs[c][s]);
+    left[c][s] = k;
+    for (int32_t it = 0; it < k; ++it) ready.push({span[c][s], (int32_t)c, (int32_t)s, it});
+  };
+  for (size_t c = 0; c < nc; ++c) {
+    left[c].assign(segs[c].size(), 0);
+    if (!segs[c].empty()) release(c, 0);
+  }
+  double now = 0;
+  int free_w = workers;
+  for (;;) {
+    while (free_w > 0 && !ready.empty()) {
+      const Ready r = ready.top();
+      ready.pop();
+      const Seg& g = segs[r.cone][r.seg];
+      const int32_t node = node_of[r.cone][r.seg];
+      const bool has_next = (size_t)r.seg + 1 < segs[r.cone].size();
+      int32_t slo = (int32_t)succ.size(), shi = slo;
+      if (has_next) {
+        succ.push_back(node_of[r.cone][r.seg + 1]);
+        shi = slo + 1;
+      }
+      const int32_t wait_node = r.seg > 0 ? node : -1;
+      if (!g.wide) {
+        // a cone that runs LDS-resident is one narrow segment
+        const bool lds = !P.cone_lds.empty() && P.cone_lds[r.cone] && segs[r.cone].size() == 1;
+        const int32_t cp = lds ? P.cone_copyin[r.cone] : -1;
+        items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, cp, {0, 0}});
+      } else {
+        const int64_t tb = std::max(1, T.tile_blocks);
+        const int64_t b = (int64_t)r.item * tb;
         items.push_back({g.r[0], g.r[1], -1, -1, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node,
                          slo, shi, -1, {0, 0}});
+      }
+      running.push({now + item_us[r.cone][r.seg], r.cone, r.seg});
+      --free_w;
     }
+    if (running.empty()) break;
+    const Done d = running.top();
+    running.pop();
+    now = d.t;
+    ++free_w;
+    if (--left[d.cone][d.seg] == 0 && (size_t)d.seg + 1 < segs[d.cone].size()) release(d.cone, d.seg + 1);
   }
 }
 

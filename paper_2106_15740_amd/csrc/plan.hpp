@@ -126,6 +126,7 @@ struct Plan {
   int64_t lds_elems = 0;               // largest LDS window needed (elements)
   int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
   int64_t mem_budget = 0;           // arena budget in elements (0: unlimited)
+  int sched_workers = 1024;  // resident workgroups the queue order is scheduled for
   // persistent-queue items (forward-only and forward+gradient programs)
   std::vector<QItem> items_fwd, items_grad;
   std::vector<int32_t> node_init_fwd, node_init_grad;   // initial dependency counts
