@@ -69,7 +69,9 @@ typedef struct {
   int32_t lane_low;     /* 1: split buckets map lanes to their lowest union bits, summed or not (contiguous input
                            reads, partial sums combined across lanes); 0: to their lowest output bits first */
   int32_t fuse_adjoint; /* 1: the adjoint of a split bucket computes every input adjoint in one pass over its
-                           union (output adjoint and inputs read once); 0: one pass per input adjoint */
+                           union (output adjoint and inputs read once) where the loop bits can be chosen so
+                           that no output needs atomics per step; 2: also the other buckets, summed tile by tile
+                           in LDS (slower on MI355X: LDS atomics); 0: one pass per input adjoint */
 } qtn_tuning;
 
 typedef struct {

@@ -681,7 +681,7 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->merge_bits < 0 || t->merge_bits > 16) return fail(QTN_EINVAL, "merge_bits must be in 0..16");
   if (t->merge_lam_bits < 0 || t->merge_lam_bits > 16) return fail(QTN_EINVAL, "merge_lam_bits must be in 0..16");
   if (t->lane_low != 0 && t->lane_low != 1) return fail(QTN_EINVAL, "lane_low must be 0 or 1");
-  if (t->fuse_adjoint != 0 && t->fuse_adjoint != 1) return fail(QTN_EINVAL, "fuse_adjoint must be 0 or 1");
+  if (t->fuse_adjoint < 0 || t->fuse_adjoint > 2) return fail(QTN_EINVAL, "fuse_adjoint must be 0, 1 or 2");
   n->P.tune.threads = th;
   n->P.tune.lane_low = t->lane_low;
   n->P.tune.fuse_adjoint = t->fuse_adjoint;

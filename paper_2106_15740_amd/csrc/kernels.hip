@@ -752,9 +752,182 @@ __device__ __forceinline__ void exec_adjoint(const OpDesc& d, typename CT<R>::E*
   }
 }
 
+__device__ __forceinline__ void lds_add(float2* p, float2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ void lds_add(double2* p, double2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+
+// Executor of OP_ADJOINT ops flagged F_TILE: every input adjoint of a bucket
+// whose inputs each lack part of the union, summed tile by tile in LDS.  A
+// block is a tile; the workgroup's threads are its lanes (nl = log2 of the
+// workgroup size) and walk the remaining tile bits in a per-thread loop.  Per
+// union element, each output's value is combined across the lanes of the
+// wavefront that it sums (shuffles) and added into its tile sum in LDS
+// (2^(tile bits it holds) pairs, at lds + its base); at the end of the tile
+// the sums are stored, or added with atomics when the output sums a block bit.
+template <typename R, int NIN>
+__device__ __forceinline__ void exec_tile(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                          int64_t blk_end, int64_t wg_rank, int64_t wg_count,
+                                          typename CT<R>::E* __restrict__ lds) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk, nb = d.nb;
+  const int lane = tid & 63;
+  uint32_t tmask = 0, blockbits = 0;
+  for (int z = 0; z < nl + nk; ++z) tmask |= 1u << d.zbit[z];
+  for (int z = nl + nk; z < d.nbits - 1; ++z) blockbits |= 1u << d.zbit[z];
+  uint32_t mask[NIN], tm[NIN], loff[NIN], lidx[NIN], lsum[NIN], lbase[NIN];
+  bool atom[NIN];
+  const E* inp[NIN];
+  E* outp[NIN];
+  uint32_t total = 0;
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    tm[i] = tmask & mask[i];
+    inp[i] = arena + d.in_off[i];
+    outp[i] = arena + (i ? d.adj_off[i] : 0);
+    atom[i] = (blockbits & ~mask[i]) != 0;
+    uint32_t o = 0, li = 0, ls = 0;
+    for (int j = 0; j < nl; ++j) {
+      const uint32_t u = d.zbit[j];
+      const uint32_t bit = (uint32_t)(tid >> j) & 1u;
+      if ((mask[i] >> u) & 1u) {
+        o += bit * bit_stride(mask[i], u);
+        li += bit * bit_stride(tm[i], u);
+      } else if (j < 6) {
+        ls |= 1u << j;
+      }
+    }
+    loff[i] = o;
+    lidx[i] = li;
+    lsum[i] = ls;
+    lbase[i] = total;
+    if (i > 0) total += 2u << __popc(tm[i]);
+  }
+  const int nloop = 1 << nk;
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_nblk > lg_wg ? lg_nblk - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_nblk - lg_chunk);
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t blk0 = base_blk + ((uint32_t)ch << lg_chunk);
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      const uint32_t blk = blk0 + (uint32_t)c;
+      uint32_t bb[NIN];  // block part of every operand's offset
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) bb[i] = 0;
+      for (int j = 0; j < nb; ++j)
+        if ((blk >> j) & 1u) {
+          const uint32_t u = d.zbit[nl + nk + j];
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) bb[i] += bit_stride(mask[i], u);
+        }
+      for (uint32_t e = tid; e < total; e += blockDim.x) lds[e] = E{0, 0};
+      __syncthreads();
+      uint32_t koff[NIN], kl[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) {
+        koff[i] = bb[i] + loff[i];
+        kl[i] = lidx[i];
+      }
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;
+          const uint32_t u = d.zbit[nl + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u), sl = bit_stride(tm[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+            kl[i] = up ? kl[i] + sl : kl[i] - sl;
+          }
+        }
+        E ob, a0[NIN], a1[NIN];
+        ob = inp[0][koff[0]];
+#pragma unroll
+        for (int i = 1; i < NIN; ++i) load_pair(inp[i] + koff[i], a0[i], a1[i]);
+        E ex0[NIN], ex1[NIN];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          E pr[NIN];
+          pr[1] = ob;
+#pragma unroll
+          for (int i = 1; i + 1 < NIN; ++i) pr[i + 1] = cmul(pr[i], h ? a1[i] : a0[i]);
+          E suf = E{1, 0};
+#pragma unroll
+          for (int i = NIN - 1; i >= 1; --i) {
+            const E x = h ? a1[i] : a0[i];
+            const E e = i == NIN - 1 ? pr[i] : cmul(pr[i], suf);
+            suf = i == NIN - 1 ? x : cmul(x, suf);
+            if (h)
+              ex1[i] = e;
+            else
+              ex0[i] = e;
+          }
+        }
+#pragma unroll
+        for (int i = 1; i < NIN; ++i) {
+          E s0 = ex0[i], s1 = ex1[i];
+          for (int j = 0; j < 6; ++j)
+            if ((lsum[i] >> j) & 1u) {
+              s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+              s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+            }
+          if ((lane & lsum[i]) == 0) {
+            lds_add(lds + lbase[i] + 2 * kl[i], s0);
+            lds_add(lds + lbase[i] + 2 * kl[i] + 1, s1);
+          }
+        }
+      }
+      __syncthreads();
+      // the tile's sums: element e of output i holds its tile bits in order
+#pragma unroll
+      for (int i = 1; i < NIN; ++i) {
+        const uint32_t n = 1u << __popc(tm[i]);
+        for (uint32_t e = tid; e < n; e += blockDim.x) {
+          uint32_t off = bb[i], rest = tm[i], k = e;
+          while (rest) {
+            const uint32_t u = __ffs(rest) - 1;
+            rest &= rest - 1;
+            if (k & 1u) off += bit_stride(mask[i], u);
+            k >>= 1;
+          }
+          const E v0 = lds[lbase[i] + 2 * e], v1 = lds[lbase[i] + 2 * e + 1];
+          if (atom[i]) {
+            atomic_add_c(outp[i] + off, v0);
+            atomic_add_c(outp[i] + off + 1, v1);
+          } else {
+            store_pair(outp[i] + off, v0, v1);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void exec_adjoint_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
-                                                 int64_t r, int64_t c) {
+                                                 int64_t r, int64_t c, typename CT<R>::E* lds) {
+  if (d.flags & F_TILE) {
+    if (d.n_in == 3)
+      exec_tile<R, 3>(d, arena, b0, b1, r, c, lds);
+    else if (d.n_in == 4)
+      exec_tile<R, 4>(d, arena, b0, b1, r, c, lds);
+    return;
+  }
   constexpr bool two = WideMaxU<R>::in_persistent > 1;
   const bool sl = two && d.nk >= 1;
   switch (d.n_in * 2 + (sl ? 1 : 0)) {
@@ -934,7 +1107,7 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
         exec_contract_any<R, MAXNIN, USE_LDS>(d, arena, b0, b1, wg_rank, wg_count, red, lds);
       break;
     case OP_ADJOINT:
-      if constexpr (WIDE && !USE_LDS) exec_adjoint_any<R>(d, arena, b0, b1, wg_rank, wg_count);
+      if constexpr (WIDE && !USE_LDS) exec_adjoint_any<R>(d, arena, b0, b1, wg_rank, wg_count, lds);
       break;
     case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
     case OP_RESULT:
@@ -996,6 +1169,17 @@ __global__ void __launch_bounds__(512) adjoint_kernel(const OpDesc* __restrict__
   exec_adjoint<R, NIN, SL>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x);
 }
 
+// One LDS-tiled OP_ADJOINT op per launch (dynamic LDS: the tile sums).
+template <typename R, int NIN>
+__global__ void __launch_bounds__(512) tile_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  __shared__ OpDesc d;
+  extern __shared__ __align__(16) char tile_lds[];
+  stage_desc(d, ops, op);
+  const int64_t nblocks = int64_t(1) << d.nb;
+  exec_tile<R, NIN>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x,
+                    reinterpret_cast<typename CT<R>::E*>(tile_lds));
+}
+
 // Leaf tables, results, zeroing and leaf gradients (one op per launch).
 template <typename R>
 __global__ void __launch_bounds__(512) misc_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
@@ -1013,7 +1197,7 @@ constexpr int DESC_CHUNK = 16;
 // WIDE: the plan has F_WIDE ops (a separate instantiation keeps the register
 // budget of narrow-only sweeps unchanged).
 template <typename R, int MAXNIN, bool WIDE>
-__global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, 8))) persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items,
                                                           int n_items, const int32_t* __restrict__ succ, int32_t* ctl,
                                                           Env env, long long spin_limit) {
   __shared__ RedBuf<typename CT<R>::E> red;
@@ -1082,7 +1266,7 @@ __global__ void __launch_bounds__(512) persistent_kernel(const OpDesc* __restric
             if (lds)
               exec_op<R, MAXNIN, true>(d, env, b0, b1, 0, 1, &red, lds);
             else
-              exec_op<R, MAXNIN, false, WIDE>(d, env, b0, b1, 0, 1, &red);
+              exec_op<R, MAXNIN, false, WIDE>(d, env, b0, b1, 0, 1, &red, reinterpret_cast<E*>(dyn_lds));
           }
           __syncthreads();
         }
@@ -1308,6 +1492,16 @@ static hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, cons
   // a power of two: the contraction executor splits its blocks by shifts
   grid = int64_t(1) << (63 - __builtin_clzll((unsigned long long)grid));
   const dim3 g((unsigned)grid), b(threads);
+  if (h.kind == OP_ADJOINT && (h.flags & F_TILE)) {
+    const size_t lb = (size_t)h.aux0 * sizeof(typename CT<R>::E);
+    if (h.n_in == 3)
+      hipLaunchKernelGGL((tile_kernel<R, 3>), g, b, lb, st, d_ops, op, env);
+    else if (h.n_in == 4)
+      hipLaunchKernelGGL((tile_kernel<R, 4>), g, b, lb, st, d_ops, op, env);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (h.kind == OP_ADJOINT) {
     const bool sl = h.nk >= 1;
     switch (h.n_in * 2 + (sl ? 1 : 0)) {

@@ -27,6 +27,8 @@ enum OpFlags : int32_t {
   F_SYNC = 8,    // in a sequential program: barrier before this op (it depends on an op since the last one)
   F_WIDE = 16,   // run by the wide-op executor: <= 4 inputs, inputs 1.. hold the eliminated index, every block
                  // range it is given holds at least one block per sub-block
+  F_TILE = 32,   // OP_ADJOINT summed per tile in LDS: the workgroup's threads are the lanes, blocks are tiles,
+                 // aux0 = LDS elements of the tile sums
 };
 
 // A contraction op iterates the union index u of a bucket.  Bit 0 of u is the

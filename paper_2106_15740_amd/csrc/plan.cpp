@@ -834,6 +834,71 @@ bool fused_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T)
   return true;
 }
 
+// Bit split of an OP_ADJOINT op summed per tile in LDS (F_TILE), for buckets
+// whose inputs each lack part of the union (no group of loop bits works for
+// them): a workgroup takes one tile at a time (a value of the block bits) and
+// walks the tile bits with all its threads, the lowest tile bits being the
+// lanes of the whole workgroup and the rest a per-thread loop.  Every output
+// sums its share of the tile in LDS (shuffles within a wavefront, then LDS
+// atomics) and writes it once per tile: stored when it sums no block bit,
+// else added with atomics into zeroed memory.  Tile bits: every bit summed by
+// an output with more than 6 indices (those outputs are then stored), the
+// lowest union bits that fit (contiguous reads), then the lowest others up to
+// the workgroup size; the tile sums must fit kTileLdsBytes.
+constexpr int64_t kTileLdsBytes = 24 * 1024;
+
+bool tile_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) {
+  if (d.n_in < 3 || d.n_in > 4 || (d.in_mask[0] & 1u)) return false;
+  const int lt = 31 - __builtin_clz((unsigned)std::max(T.threads, 64));
+  d.adj_sel = 0;
+  uint32_t tile = 0;
+  for (int i = 1; i < d.n_in; ++i) {
+    if (!(d.in_mask[i] & 1u) || d.in_mask[i] == all) return false;
+    d.adj_sel |= 1u << i;
+    if (__builtin_popcount(d.in_mask[i]) > 6) tile |= all & ~d.in_mask[i] & ~1u;
+  }
+  const int64_t budget = kTileLdsBytes / (2 * T.elem_bytes);  // pairs
+  auto need = [&](uint32_t t) {
+    int64_t s = 0;
+    for (int i = 1; i < d.n_in; ++i) s += int64_t(1) << __builtin_popcount(t & d.in_mask[i]);
+    return s;
+  };
+  if (need(tile) > budget) return false;
+  for (int u = 1; u < std::min(nbits, 5); ++u)
+    if (need(tile | (1u << u)) <= budget) tile |= 1u << u;
+  for (int u = 1; u < nbits && __builtin_popcount(tile) < lt; ++u)
+    if (need(tile | (1u << u)) <= budget) tile |= 1u << u;
+  if (__builtin_popcount(tile) < lt || __builtin_popcount(tile) > lt + 12) return false;
+  d.nl = lt;
+  d.nu = 0;
+  d.nk = __builtin_popcount(tile) - lt;
+  d.nb = nbits - 1 - __builtin_popcount(tile);
+  int z = 0;
+  for (int u = 1; u < nbits; ++u)
+    if ((tile >> u) & 1u) d.zbit[z++] = (uint8_t)u;  // lanes, then the loop
+  uint32_t blockbits = 0;
+  for (int u = 1; u < nbits; ++u)
+    if (!((tile >> u) & 1u)) {
+      d.zbit[z++] = (uint8_t)u;
+      blockbits |= 1u << u;
+    }
+  for (; z < 32; ++z) d.zbit[z] = 0;
+  bool atomic = false;
+  for (int i = 1; i < d.n_in; ++i) atomic |= (blockbits & ~d.in_mask[i]) != 0;
+  d.lane_sum = 0;
+  d.out_mask = 0;
+  d.out_off = 0;
+  d.aux0 = (int32_t)(2 * need(tile));
+  d.flags = F_WIDE | F_TILE | (atomic ? F_ATOMIC : 0);
+  for (int i = 0; i <= MAXIN; ++i)
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t m = i < d.n_in ? d.in_mask[i] : 0u;
+      const uint32_t u = d.zbit[j];
+      d.lsh[i][j] = (j < d.nl && ((m >> u) & 1u)) ? (uint8_t)__builtin_popcount(m & ((1u << u) - 1u)) : LSH_NONE;
+    }
+  return true;
+}
+
 OpDesc blank(int kind, int cone) {
   OpDesc d;
   std::memset(&d, 0, sizeof(d));
@@ -1188,7 +1253,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       OpDesc d = blank(OP_ADJOINT, (int)c);
       d.nbits = nbits;
       add_common(d, -1, true);
-      if (fused_adjoint_bits(d, nbits, all, T)) {
+      if (fused_adjoint_bits(d, nbits, all, T) || (T.fuse_adjoint >= 2 && tile_adjoint_bits(d, nbits, all, T))) {
         int i = 1;
         if (Bk.lam_mask) d.adj_off[i++] = buf_code(BK_LAMADJ, (int)bb);
         for (int t = 0; t < nin; ++t) d.adj_off[i++] = buf_code(BK_ADJ, Bk.in_bkt[t]);
@@ -1420,6 +1485,9 @@ std::string build_programs(Plan& P, int elem_bytes) {
   }
   P.arena_grad = P.arena_fwd = align_elems(off, 64);
   lds_layout(P);
+  // the LDS window also holds the tile sums of LDS-tiled adjoints
+  for (const OpDesc& d : P.ops)
+    if (d.kind == OP_ADJOINT && (d.flags & F_TILE)) P.lds_elems = std::max<int64_t>(P.lds_elems, d.aux0);
   {
     std::vector<std::unordered_map<int64_t, int64_t>> where(nc);
     for (size_t c = 0; c < nc; ++c)
@@ -1467,7 +1535,9 @@ static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
   const uint32_t all = (uint32_t)((uint64_t(1) << d.nbits) - 1);
   if (d.nbits <= P.tune.seq_max_bits || !(d.flags & F_WIDE)) return "adjoint op not wide";
   if (d.n_in < 3 || d.n_in > 4 || d.lds_mask) return "adjoint op with a bad input count or LDS operands";
-  if (d.nu != 0 || d.nl < 1 || d.nl > 6 || d.nl + d.nk + d.nb != d.nbits - 1) return "adjoint op bit partition";
+  const bool tiled = d.flags & F_TILE;
+  if (d.nu != 0 || d.nl < 1 || d.nl + d.nk + d.nb != d.nbits - 1) return "adjoint op bit partition";
+  if (tiled ? (1 << d.nl) != P.tune.threads : d.nl > 6) return "adjoint op lane count";
   if (d.adj_sel != (((1u << d.n_in) - 1u) & ~1u)) return "adjoint op output selection";
   if ((d.in_mask[0] & 1u) || (d.in_mask[0] & ~all)) return "adjoint op output adjoint mask";
   for (int i = 1; i < d.n_in; ++i)
@@ -1480,12 +1550,19 @@ static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
     (z < d.nl ? lanes : (z < d.nl + d.nk ? loop : blocks)) |= 1u << u;
   }
   bool atomic = false;
+  int64_t tile_elems = 0;
   for (int i = 1; i < d.n_in; ++i) {
     const uint32_t held = d.in_mask[i] & loop;
-    if (held != 0 && held != loop) return "adjoint op output holds part of the loop bits";
-    if (held && (all & ~d.in_mask[i] & ~lanes & ~1u)) return "adjoint op loop holder sums a non-lane bit";
+    if (tiled) {
+      if (d.in_mask[i] == all) return "LDS-tiled adjoint with an output holding the whole union";
+      tile_elems += int64_t(2) << __builtin_popcount(d.in_mask[i] & (lanes | loop));
+    } else {
+      if (held != 0 && held != loop) return "adjoint op output holds part of the loop bits";
+      if (held && (all & ~d.in_mask[i] & ~lanes & ~1u)) return "adjoint op loop holder sums a non-lane bit";
+    }
     atomic |= (blocks & ~d.in_mask[i]) != 0;
   }
+  if (tiled && (tile_elems != d.aux0 || d.aux0 > P.lds_elems)) return "LDS-tiled adjoint tile size";
   if (atomic != bool(d.flags & F_ATOMIC)) return "adjoint op atomic flag mismatch";
   const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
   if (std::min<int64_t>(std::max(1, P.tune.tile_blocks), int64_t(1) << d.nb) < nsub)
@@ -1676,6 +1753,7 @@ void build_items(Plan& P, bool grad) {
     int32_t r[4];
     bool wide;
     int64_t nblocks;
+    int64_t per_item;  // blocks per item of a wide op
   };
   const size_t nc = P.cones.size();
   std::vector<std::vector<Seg>> segs(nc);
@@ -1687,11 +1765,11 @@ void build_items(Plan& P, bool grad) {
     } else {
       ranges.push_back({P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1});
     }
-    Seg cur{{-1, -1, -1, -1}, false, 1};
+    Seg cur{{-1, -1, -1, -1}, false, 1, 1};
     int nr = 0;  // physical ranges used by the open narrow segment
     auto close = [&]() {
       if (nr) segs[c].push_back(cur);
-      cur = Seg{{-1, -1, -1, -1}, false, 1};
+      cur = Seg{{-1, -1, -1, -1}, false, 1, 1};
       nr = 0;
     };
     for (auto& rg : ranges) {
@@ -1703,7 +1781,11 @@ void build_items(Plan& P, bool grad) {
         if (wide) {
           close();
           open_here = false;
-          segs[c].push_back(Seg{{o, o + 1, -1, -1}, true, int64_t(1) << d.nb});
+          // tiles of an LDS-tiled adjoint: about 2^16 union elements per item
+          const int64_t per = (d.flags & F_TILE) ? std::min<int64_t>(std::max(1, T.tile_blocks),
+                                                                       int64_t(1) << std::max(0, 16 - d.nl - d.nk))
+                                                 : std::max(1, T.tile_blocks);
+          segs[c].push_back(Seg{{o, o + 1, -1, -1}, true, int64_t(1) << d.nb, per});
         } else {
           if (!open_here) {
             if (nr == 2) close();
@@ -1726,8 +1808,7 @@ void build_items(Plan& P, bool grad) {
   init.assign(nn, 0);
   auto n_items = [&](const Seg& g) -> int32_t {
     if (!g.wide) return 1;
-    const int64_t tb = std::max(1, T.tile_blocks);
-    return (int32_t)((g.nblocks + tb - 1) / tb);
+    return (int32_t)((g.nblocks + g.per_item - 1) / g.per_item);
   };
   for (size_t c = 0; c < nc; ++c)
     for (size_t s = 1; s < segs[c].size(); ++s) init[node_of[c][s]] = n_items(segs[c][s - 1]);
@@ -1823,7 +1904,7 @@ void build_items(Plan& P, bool grad) {
         const int32_t cp = lds ? P.cone_copyin[r.cone] : -1;
         items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, cp, {0, 0}});
       } else {
-        const int64_t tb = std::max(1, T.tile_blocks);
+        const int64_t tb = g.per_item;
         const int64_t b = (int64_t)r.item * tb;
         items.push_back({g.r[0], g.r[1], -1, -1, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node,
                          slo, shi, -1, {0, 0}});

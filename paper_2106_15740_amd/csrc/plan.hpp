@@ -105,7 +105,8 @@ struct TuneParams {
   int merge_bits = 12;       // merge a bucket into its consumer while the merged union has <= this many bits (0: off)
   int merge_lam_bits = 7;   // ... and its leaf-product table has <= this many bits
   int lane_low = 1;         // wide ops: lanes on the lowest union bits (1) or the lowest output bits (0)
-  int fuse_adjoint = 1;     // wide buckets: every input adjoint in one pass (1) or one op per input (0)
+  int fuse_adjoint = 1;     // wide buckets: every input adjoint in one pass where a loop-bit group fits (1), also
+                            // LDS tiles for the others (2), or one op per input (0)
 };
 
 struct Plan {
