@@ -1304,8 +1304,18 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
   const int lane = threadIdx.x & 63;
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
-  const E* vals = reinterpret_cast<const E*>(env.leafvals);
-  const E* dvals = reinterpret_cast<const E*>(env.dleafvals);
+  // the leaf values and their derivatives (4 entries per kind, 3 + 4p kinds,
+  // p <= 16) are looked up once per leaf and table entry: keep them in LDS
+  constexpr int NV = 4 * (3 + 4 * 16);
+  __shared__ E s_vals[NV], s_dvals[NV];
+  const int nv = 4 * (3 + 4 * env.p);
+  for (int i = threadIdx.x; i < nv && i < NV; i += blockDim.x) {
+    s_vals[i] = reinterpret_cast<const E*>(env.leafvals)[i];
+    s_dvals[i] = reinterpret_cast<const E*>(env.dleafvals)[i];
+  }
+  __syncthreads();
+  const E* vals = s_vals;
+  const E* dvals = s_dvals;
   E* arena = reinterpret_cast<E*>(env.arena);
   for (int op = lo + wave; op < hi; op += nwaves) {
     const OpDesc& d = ops[op];

@@ -11,8 +11,8 @@ namespace qtn {
 struct Env {
   void* arena;              // tensor elements (complex64 or complex128)
   double* res;              // per cone: R (re, im), dR/dgamma_l, dR/dbeta_l (re, im)
-  const void* leafvals;     // [4p+2][4] leaf entries, element type
-  const void* dleafvals;    // [4p+2][4] their derivatives in the leaf's angle
+  const void* leafvals;     // [4p+3][4] leaf entries, element type (p <= 16)
+  const void* dleafvals;    // [4p+3][4] their derivatives in the leaf's angle
   const LeafRef* leafrefs;
   int p;
   int res_stride;           // 2 + 4p doubles
