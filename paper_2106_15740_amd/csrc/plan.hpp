@@ -11,10 +11,10 @@
 
 namespace qtn {
 
-// Leaf tensor kinds.  Every leaf has rank 1 or 2 and is one of 4p+2 distinct
-// values: |+> (1,1)/sqrt2, the observable Z = (1,-1), and per layer l the ket
-// ZZ phase tensor, its conjugate (bra), the ket mixer exp(-i beta X) and its
-// conjugate.
+// Leaf tensor kinds.  Every leaf has rank 1 or 2 and is one of 4p+3 distinct
+// values: |+> (1,1)/sqrt2, the observable Z = (1,-1), per layer l the ket ZZ
+// phase tensor, its conjugate (bra), the ket mixer exp(-i beta X) and its
+// conjugate, and the projector <0| = (1,0) of single-amplitude networks.
 enum LeafKind : int32_t { LK_PLUS = 0, LK_ZOBS = 1 };
 inline int32_t lk_zz(int l) { return 2 + 4 * l + 0; }     // l is 0-based layer
 inline int32_t lk_zzb(int l) { return 2 + 4 * l + 1; }
