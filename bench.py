@@ -81,7 +81,15 @@ def cpu_baseline(w, budget_s: float = 12.0):
             done += len(batch)
             i += cores
     dt = time.perf_counter() - t0
+    # the same work on one core, for a few seconds
+    t1 = time.perf_counter()
+    one = 0
+    while time.perf_counter() - t1 < min(4.0, budget_s / 3):
+        _oracle_edge_grad(w.n, w.edges, w.gamma, w.beta, w.edges[int(order[one % len(order)])], h)
+        one += 1
+    dt1 = time.perf_counter() - t1
     return {"value": done / dt, "unit": "edge light-cones/s", "cores": cores, "kind": "oracle",
+            "single_core": {"value": one / dt1, "sample": f"{one} edge light cones on one core, {dt1:.1f} s"},
             "sample": f"{done} edge light cones ({done / len(w.edges):.1f} passes over the {len(w.edges)} edges in a "
                       f"seeded order), numpy einsum bucket elimination in complex128, energy + gradient by central "
                       f"differences ({4 * p + 1} contractions per edge), {cores} worker processes, {dt:.1f} s"}
@@ -144,6 +152,20 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     pk_ms = net.time_persistent(with_grad=True, reps=2)
     alg = info["fwd_bytes"] + info["bwd_bytes"]
     wb, wms, wn = net.time_wide_ops(min_width=20, with_grad=True, reps=2)
+    del net
+    torch.cuda.empty_cache()
+    # the other greedy order (min-fill: narrower, widths up to 23 on this graph)
+    net_mf = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=0, repeats=repeats)
+    net_mf.set_tuning(seq_max_bits=14, tile_blocks=64, par_bits=21)
+    net_mf.set_params(w.gamma, w.beta)
+    info_mf = net_mf.info()
+    dt_mf, e_mf, k_ms_mf, _ = time_sweeps(net_mf, steps, 1)
+    pk_mf = net_mf.time_persistent(with_grad=True, reps=2)
+    alg_mf = info_mf["fwd_bytes"] + info_mf["bwd_bytes"]
+    other = {"order": "min_fill", "max_width": info_mf["max_width"],
+             "edge_light_cones_per_s": len(w.edges) * steps / dt_mf, "persistent_kernel_ms": pk_mf,
+             "alg_bytes_per_sweep": alg_mf, "achieved_GBps": alg_mf / (pk_mf * 1e-3) / 1e9, "energy": e_mf}
+    del net_mf
     out = {
         "workload": f"QAOA-MaxCut p=5, random 3-regular N=1000 (1500 edges), c64, min-degree randomized greedy "
                     f"({repeats} repeats), batched energy + gradient",
@@ -165,8 +187,8 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
                                   "2 replays between HIP events"},
         "energy": e,
         "plan_s": plan_s,
+        "other_order": other,
     }
-    del net
     torch.cuda.empty_cache()
     return out
 
