@@ -748,7 +748,7 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
         }
     } else if (stage == 1) {
       for (int sq : {12, 14, 16})
-        for (int tb : {16, 64}) {
+        for (int tb : {16, 64, 128}) {
           qtn_tuning t = b0;
           t.seq_max_bits = sq;
           t.tile_blocks = tb;
