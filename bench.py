@@ -145,7 +145,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     t0 = time.perf_counter()
     net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_degree", device=0, repeats=repeats)
     plan_s = time.perf_counter() - t0
-    net.set_tuning(seq_max_bits=14, tile_blocks=128, par_bits=21)
+    net.set_tuning(seq_max_bits=16, tile_blocks=128, par_bits=21)
     net.set_params(w.gamma, w.beta)
     info = net.info()
     dt, e, k_ms, _ = time_sweeps(net, steps, 1)
@@ -156,7 +156,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     torch.cuda.empty_cache()
     # the other greedy order (min-fill: narrower, widths up to 23 on this graph)
     net_mf = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=0, repeats=repeats)
-    net_mf.set_tuning(seq_max_bits=14, tile_blocks=128, par_bits=21)
+    net_mf.set_tuning(seq_max_bits=16, tile_blocks=128, par_bits=21)
     net_mf.set_params(w.gamma, w.beta)
     info_mf = net_mf.info()
     dt_mf, e_mf, k_ms_mf, _ = time_sweeps(net_mf, steps, 1)

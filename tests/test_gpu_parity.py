@@ -337,7 +337,7 @@ def test_fused_adjoint_gradient_vs_statevector(dtype, tol, lane_low):
 def test_config5_full_size_sampled_edges_and_properties():
     """p = 5, N = 1000 (1500 edges) at full size, in the launch configuration
     the benchmark times (min-degree randomized greedy with 10 repeats;
-    seq_max_bits 14, tile_blocks 128, par_bits 21; fused adjoints): one edge
+    seq_max_bits 16, tile_blocks 128, par_bits 21; fused adjoints): one edge
     per contraction width (12 to 26) against the TN oracle, every <ZZ> real
     and within [-1, 1], and two symmetries of the whole energy: beta_1 + pi/2
     and (gamma, beta) -> (-gamma, -beta), under which the gradient flips
@@ -347,7 +347,7 @@ def test_config5_full_size_sampled_edges_and_properties():
     w = workload("p5_n1000")
     print(f"[case] p5_n1000 c64 min_degree repeats=10", flush=True)
     net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_degree", device=0, repeats=10)
-    net.set_tuning(seq_max_bits=14, tile_blocks=128, par_bits=21)
+    net.set_tuning(seq_max_bits=16, tile_blocks=128, par_bits=21)
     net.set_params(w.gamma, w.beta)
     e, dg, db = net.energy_grad("batched")
     zz = net.edge_results()
