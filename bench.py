@@ -152,6 +152,17 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     pk_ms = net.time_persistent(with_grad=True, reps=2)
     alg = info["fwd_bytes"] + info["bwd_bytes"]
     wb, wms, wn = net.time_wide_ops(min_width=20, with_grad=True, reps=2)
+    # the same measurement by width band (ops launched alone, cumulative above
+    # each threshold, differenced)
+    cum = {wmin: net.time_wide_ops(min_width=wmin, with_grad=True, reps=2) for wmin in (16, 24)}
+    cum[20] = (wb, wms, wn)
+    bands = []
+    for lo, hi in ((16, 20), (20, 24), (24, None)):
+        b, ms, k = cum[lo]
+        if hi is not None:
+            b, ms, k = b - cum[hi][0], ms - cum[hi][1], k - cum[hi][2]
+        bands.append({"widths": f"{lo}-{hi - 1}" if hi else f">={lo}", "ops": k, "alg_bytes": b, "ms": ms,
+                      "achieved_GBps": b / (ms * 1e-3) / 1e9 if ms > 0 else None})
     del net
     torch.cuda.empty_cache()
     # the other greedy order (min-fill: narrower, widths up to 23 on this graph)
@@ -185,6 +196,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
                         "frac_of_copy": (wb / (wms * 1e-3) / 1e9 / copy_gbps) if (wms and copy_gbps) else None,
                         "method": "each contraction op of a bucket with output rank >= 20 launched alone, "
                                   "2 replays between HIP events"},
+        "width_bands": bands,
         "energy": e,
         "plan_s": plan_s,
         "other_order": other,
