@@ -35,8 +35,11 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_persistent_kernel_p3_n244
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "plan.cpp", "opdesc.hpp"):
-        with open(os.path.join(ROOT, "paper_2106_15740_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2106_15740_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if not f.endswith((".hip", ".hpp", ".cpp")) or f == "api.cpp":
+            continue
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -1,0 +1,1139 @@
+// Device executors of the contraction, adjoint and leaf ops (shared by the
+// per-op kernels and the persistent sweep; every kernel translation unit
+// includes this header and instantiates only its own kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace qtn {
+
+
+// ------------------------------------------------------------------ complex helpers
+template <typename R>
+struct CT;
+template <>
+struct CT<float> {
+  using E = float2;
+};
+template <>
+struct CT<double> {
+  using E = double2;
+};
+
+template <typename E>
+__device__ __forceinline__ E cmul(E a, E b) {
+  E r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename E>
+__device__ __forceinline__ E cadd(E a, E b) {
+  E r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+
+__device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
+  float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void load_pair(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
+}
+__device__ __forceinline__ void store_pair(float2* p, float2 a, float2 b) {
+  *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void store_pair(double2* p, double2 a, double2 b) {
+  p[0] = a;
+  p[1] = b;
+}
+__device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ float2 shfl_xor_c(float2 v, int m) {
+  return make_float2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+__device__ __forceinline__ double2 shfl_xor_c(double2 v, int m) {
+  return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+
+// Element stride of union bit u inside a tensor whose union-bit mask is m.
+__device__ __forceinline__ uint32_t bit_stride(uint32_t m, uint32_t u) {
+  return ((m >> u) & 1u) ? (1u << __popc(m & ((1u << u) - 1u))) : 0u;
+}
+
+// ------------------------------------------------------------------ contraction op
+// Runs the blocks [blk_begin, blk_end) of one OP_CONTRACT that fall to this
+// workgroup.  A workgroup step covers nsub consecutive blocks (one per
+// sub-block); the steps are cut into aligned power-of-two chunks, chunk
+// wg_rank, wg_rank + wg_count, ... go to this workgroup, and each chunk is
+// walked in Gray-code order so that consecutive steps differ in one block bit
+// and every input offset moves by a single stride.  All threads take part in
+// every step (tails are masked), so the LDS reduction may synchronise.
+
+// Outputs per thread (2^nu) allowed for NIN inputs; the planner applies the
+// same bound.
+template <typename R, int NIN>
+struct MaxU {
+  static constexpr int value = (sizeof(R) == 4 && NIN <= 2) ? 2 : 1;
+};
+
+template <typename E>
+struct RedBuf {
+  E v[512 * 2];
+};
+
+template <typename R, int NIN, bool USE_LDS = false>
+__device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                              int64_t blk_end, int64_t wg_rank, int64_t wg_count,
+                              RedBuf<typename CT<R>::E>* __restrict__ red, typename CT<R>::E* lds = nullptr) {
+  using E = typename CT<R>::E;
+  constexpr int MAXU = MaxU<R, NIN>::value;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nu = d.nu, nk = d.nk;
+  const int lanes = 1 << nl;
+  const int sbits = 31 - __clz(blockDim.x >> nl);  // log2(sub-blocks per workgroup)
+  const int sub = tid >> nl;
+  const int lane = tid & (lanes - 1);
+  const uint32_t out_mask = d.out_mask;
+  const bool out_pair = out_mask & 1u;
+  const bool atomic = d.flags & F_ATOMIC;
+  const bool ldsred = d.flags & F_LDSRED;
+  const int U = 1 << nu;
+
+  uint32_t mask[NIN];
+  uint32_t loff[NIN];
+  const E* inp[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    if constexpr (USE_LDS)
+      inp[i] = ((d.lds_mask >> i) & 1u) ? lds + d.lds_off[i] : arena + d.in_off[i];
+    else
+      inp[i] = arena + d.in_off[i];
+    // lane offset: the strides of the lane bits are distinct powers of two
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl && sh != LSH_NONE) o |= ((uint32_t)(lane >> j) & 1u) << sh;
+    }
+    loff[i] = o;
+  }
+  uint32_t lout = 0;
+#pragma unroll
+  for (int j = 0; j < MAXLANE; ++j) {
+    const uint32_t sh = d.lsh[MAXIN][j];
+    if (j < nl && sh != LSH_NONE) lout |= ((uint32_t)(lane >> j) & 1u) << sh;
+  }
+  uint32_t us0[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) us0[i] = (MAXU > 1 && nu > 0) ? bit_stride(mask[i], d.zbit[nl]) : 0u;
+  const uint32_t uo0 = (MAXU > 1 && nu > 0) ? bit_stride(out_mask, d.zbit[nl]) : 0u;
+  E* outp;
+  if constexpr (USE_LDS)
+    outp = ((d.lds_mask >> MAXIN) & 1u) ? lds + d.lds_off[MAXIN] : arena + d.out_off;
+  else
+    outp = arena + d.out_off;
+  const uint32_t lane_sum = d.lane_sum;
+  const int zk0 = nl + nu;
+  const int zb0 = nl + nu + nk;
+  const int nb = d.nb;
+  const int64_t nloop = int64_t(1) << nk;
+
+  // workgroup steps and chunks: the block range (2^nb blocks, or an aligned
+  // power-of-two tile of them) and wg_count are powers of two
+  const int32_t nblk = (int32_t)(blk_end - blk_begin);
+  const int lg_nblk = 31 - __clz(nblk);
+  const int lg_st = lg_nblk > sbits ? lg_nblk - sbits : 0;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int64_t chunk = int64_t(1) << lg_chunk;
+  const int64_t steps = int64_t(1) << lg_st;
+  const int64_t nchunks = steps >> lg_chunk;
+
+#pragma unroll 1
+  for (int64_t ch = wg_rank; ch < nchunks; ch += wg_count) {
+    const int64_t q0 = ch << lg_chunk;
+    int64_t blk = blk_begin + (q0 << sbits) + sub;
+    bool valid = blk < blk_end;
+    uint32_t boff[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    uint32_t bout = lout;
+    {
+      const int64_t b = valid ? blk : blk_begin;
+      if (b) {
+        for (int j = 0; j < nb; ++j)
+          if ((b >> j) & 1) {
+            const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+            bout += bit_stride(out_mask, u);
+          }
+      }
+    }
+#pragma unroll 1
+    for (int64_t c = 0; c < chunk; ++c) {
+      if (c) {
+        // Gray step: block bit sbits + t flips
+        const int t = __ffsll((unsigned long long)c) - 1;
+        const int64_t g = c ^ (c >> 1);
+        const bool up = (g >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
+        }
+        const uint32_t so = bit_stride(out_mask, u);
+        bout = up ? bout + so : bout - so;
+        blk = blk_begin + ((q0 + g) << sbits) + sub;
+        valid = blk < blk_end;
+      }
+      if (q0 + c >= steps) break;  // uniform
+      E acc0[MAXU], acc1[MAXU];
+#pragma unroll
+      for (int k = 0; k < MAXU; ++k) {
+        acc0[k] = E{0, 0};
+        acc1[k] = E{0, 0};
+      }
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = valid ? boff[i] : loff[i];
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int64_t it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffsll((unsigned long long)it) - 1;  // Gray code over the summed loop bits
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < MAXU; ++k) {
+          if (k < U) {
+            E p0, p1;
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+              const uint32_t o = koff[i] + (k ? us0[i] : 0u);
+              E a0, a1;
+              if (mask[i] & 1u) {
+                load_pair(inp[i] + o, a0, a1);
+              } else {
+                a0 = inp[i][o];
+                a1 = a0;
+              }
+              if (i == 0) {
+                p0 = a0;
+                p1 = a1;
+              } else {
+                p0 = cmul(p0, a0);
+                p1 = cmul(p1, a1);
+              }
+            }
+            acc0[k] = cadd(acc0[k], p0);
+            acc1[k] = cadd(acc1[k], p1);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < MAXU; ++k) {
+        if (k < U) {  // uniform
+          E s0 = acc0[k], s1 = acc1[k];
+          if (!out_pair) s0 = cadd(s0, s1);
+          if (lane_sum & 63u) {
+            for (int j = 0; j < 6; ++j)
+              if ((lane_sum >> j) & 1) {
+                s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+                if (out_pair) s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+              }
+          }
+          if (ldsred) {
+            // lanes of the same sub-block in other wavefronts: combine in LDS
+            __syncthreads();
+            red->v[2 * tid] = s0;
+            red->v[2 * tid + 1] = s1;
+            __syncthreads();
+            const uint32_t hi = lane_sum & ~63u;
+            if ((lane & hi) == 0)
+              for (uint32_t m = hi; m; m = (m - 1) & hi) {
+                s0 = cadd(s0, red->v[2 * (tid ^ (int)m)]);
+                s1 = cadd(s1, red->v[2 * (tid ^ (int)m) + 1]);
+              }
+          }
+          if (valid && (lane & lane_sum) == 0) {
+            const uint32_t o = bout + (k ? uo0 : 0u);
+            if (out_pair) {
+              if (atomic) {
+                atomic_add_c(outp + o, s0);
+                atomic_add_c(outp + o + 1, s1);
+              } else {
+                store_pair(outp + o, s0, s1);
+              }
+            } else {
+              if (atomic)
+                atomic_add_c(outp + o, s0);
+              else
+                outp[o] = s0;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ wide ops
+// Executor of the ops flagged F_WIDE (buckets too wide for one workgroup).
+// Everything that decides the instruction stream is a template parameter, so
+// the step body has no branches between its loads: NIN inputs, S0 = 1 when
+// input 0 lacks the eliminated index (the output adjoint of an adjoint op;
+// every other input holds it and is loaded as a 16-byte pair), UU = 2^nu
+// outputs per thread.  All loads of a step are issued before the first use.
+// When the op has more per-thread output bits than UU covers (nu > log2 UU,
+// at most one more), the step repeats for the extra bit.  KS: the UU slots
+// hold the first log2 UU bits of the summation loop instead of outputs (ops
+// with nu = 0 and nk >= log2 UU), so reductions keep as many loads in flight
+// as element-wise ops and add the slots before the store.  The block range
+// [blk_begin, blk_end) is an aligned power of two of at least one block per
+// sub-block; offsets fit 32 bits (tensor rank <= 30).
+template <typename R, int NIN, int S0, int UU, bool KS = false>
+__device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                          int64_t blk_end, int64_t wg_rank, int64_t wg_count,
+                                          RedBuf<typename CT<R>::E>* __restrict__ red) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk;
+  const int sbits = 31 - __clz(blockDim.x >> nl);
+  const int sub = tid >> nl;
+  const int lane = tid & ((1 << nl) - 1);
+  const uint32_t out_mask = d.out_mask;
+  const bool out_pair = out_mask & 1u;
+  const bool atomic = d.flags & F_ATOMIC;
+  const bool ldsred = d.flags & F_LDSRED;
+  const uint32_t lane_sum = d.lane_sum;
+  uint32_t mask[NIN], loff[NIN];
+  const E* inp[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    inp[i] = arena + d.in_off[i];
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl && sh != LSH_NONE) o |= ((uint32_t)(lane >> j) & 1u) << sh;
+    }
+    loff[i] = o;
+  }
+  uint32_t lout = 0;
+#pragma unroll
+  for (int j = 0; j < MAXLANE; ++j) {
+    const uint32_t sh = d.lsh[MAXIN][j];
+    if (j < nl && sh != LSH_NONE) lout |= ((uint32_t)(lane >> j) & 1u) << sh;
+  }
+  // offsets of the UU slots of a thread: output bits zbit[nl], zbit[nl + 1],
+  // or with KS the first loop bits (summed, so their output stride is 0)
+  constexpr int LGU = UU == 4 ? 2 : (UU == 2 ? 1 : 0);
+  const int zs = KS ? nl + d.nu : nl;
+  uint32_t us[NIN][UU], uo[UU];
+#pragma unroll
+  for (int i = 0; i <= NIN; ++i) {
+    const uint32_t m = i < NIN ? mask[i] : out_mask;
+    const uint32_t s0 = UU > 1 ? bit_stride(m, d.zbit[zs]) : 0u;
+    const uint32_t s1 = UU > 2 ? bit_stride(m, d.zbit[zs + 1]) : 0u;
+#pragma unroll
+    for (int k = 0; k < UU; ++k) {
+      const uint32_t v = ((k & 1) ? s0 : 0u) + ((k & 2) ? s1 : 0u);
+      if (i < NIN)
+        us[i][k] = v;
+      else
+        uo[k] = v;
+    }
+  }
+  E* outp = arena + d.out_off;
+  constexpr int NU = KS ? 0 : LGU;
+  const int nrep = d.nu > NU ? 2 : 1;
+  uint32_t rs[NIN], rso = 0;  // strides of the repeated output bit
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) rs[i] = nrep > 1 ? bit_stride(mask[i], d.zbit[nl + NU]) : 0u;
+  if (nrep > 1) rso = bit_stride(out_mask, d.zbit[nl + NU]);
+  const int zk0 = nl + d.nu + (KS ? LGU : 0), zb0 = nl + d.nu + nk;
+  const int nloop = 1 << (KS ? nk - LGU : nk);
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_st = lg_nblk - sbits;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_st - lg_chunk);
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t q0 = (uint32_t)ch << lg_chunk;
+    const uint32_t blk = base_blk + (q0 << sbits) + (uint32_t)sub;
+    uint32_t boff[NIN], bout = lout;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    for (int j = 0; j < d.nb; ++j)
+      if ((blk >> j) & 1u) {
+        const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+        bout += bit_stride(out_mask, u);
+      }
+    // partial sums carried across block steps that flip only summed bits
+    E acc0[UU], acc1[UU];
+#pragma unroll
+    for (int k = 0; k < UU; ++k) {
+      acc0[k] = E{0, 0};
+      acc1[k] = E{0, 0};
+    }
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      if (c) {
+        // Gray step: block bit sbits + t flips
+        const int t = __ffs(c) - 1;
+        const bool up = ((c ^ (c >> 1)) >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
+        }
+        const uint32_t so = bit_stride(out_mask, u);
+        bout = up ? bout + so : bout - so;
+      }
+      // keep accumulating when the next step of this chunk flips a summed
+      // bit (same outputs); nrep > 1 never has summed block bits
+      const bool carry = nrep == 1 && c + 1 < chunk &&
+                         bit_stride(out_mask, d.zbit[zb0 + sbits + __ffs(c + 1) - 1]) == 0u;
+#pragma unroll 1
+      for (int rep = 0; rep < nrep; ++rep) {
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = boff[i] + (rep ? rs[i] : 0u);
+      const uint32_t rout = bout + (rep ? rso : 0u);
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;  // Gray code over the summed loop bits
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
+        }
+        E a0[UU][NIN], a1[UU][NIN];
+#pragma unroll
+        for (int k = 0; k < UU; ++k)
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t o = koff[i] + us[i][k];
+            if (i == 0 && S0 == 1)
+              a0[k][i] = inp[i][o];
+            else
+              load_pair(inp[i] + o, a0[k][i], a1[k][i]);
+          }
+#pragma unroll
+        for (int k = 0; k < UU; ++k) {
+          E p0 = a0[k][0];
+          E p1 = S0 == 1 ? a0[k][0] : a1[k][0];
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) {
+            p0 = cmul(p0, a0[k][i]);
+            p1 = cmul(p1, a1[k][i]);
+          }
+          acc0[k] = cadd(acc0[k], p0);
+          acc1[k] = cadd(acc1[k], p1);
+        }
+      }
+      if (carry) continue;  // uniform
+      if (KS) {
+#pragma unroll
+        for (int k = 1; k < UU; ++k) {
+          acc0[0] = cadd(acc0[0], acc0[k]);
+          acc1[0] = cadd(acc1[0], acc1[k]);
+          acc0[k] = E{0, 0};
+          acc1[k] = E{0, 0};
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < (KS ? 1 : UU); ++k) {
+        E s0 = acc0[k], s1 = acc1[k];
+        acc0[k] = E{0, 0};
+        acc1[k] = E{0, 0};
+        if (!out_pair) s0 = cadd(s0, s1);
+        if (lane_sum & 63u) {
+          for (int j = 0; j < 6; ++j)
+            if ((lane_sum >> j) & 1) {
+              s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+              if (out_pair) s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+            }
+        }
+        if (ldsred) {
+          // lanes of the same sub-block in other wavefronts: combine in LDS
+          __syncthreads();
+          red->v[2 * tid] = s0;
+          red->v[2 * tid + 1] = s1;
+          __syncthreads();
+          const uint32_t hi = lane_sum & ~63u;
+          if ((lane & hi) == 0)
+            for (uint32_t m = hi; m; m = (m - 1) & hi) {
+              s0 = cadd(s0, red->v[2 * (tid ^ (int)m)]);
+              s1 = cadd(s1, red->v[2 * (tid ^ (int)m) + 1]);
+            }
+        }
+        if ((lane & lane_sum) == 0) {
+          const uint32_t o = rout + uo[k];
+          if (out_pair) {
+            if (atomic) {
+              atomic_add_c(outp + o, s0);
+              atomic_add_c(outp + o + 1, s1);
+            } else {
+              store_pair(outp + o, s0, s1);
+            }
+          } else {
+            if (atomic)
+              atomic_add_c(outp + o, s0);
+            else
+              outp[o] = s0;
+          }
+        }
+      }
+      }
+    }
+  }
+}
+
+// Largest per-thread output count of the wide executor for element type R:
+// its own launches, and inside the persistent kernel (whose other state
+// competes for registers; the rest of the op's output bits repeat the step).
+template <typename R>
+struct WideMaxU {
+  static constexpr int value = sizeof(R) == 4 ? 4 : 2;
+  static constexpr int in_persistent = sizeof(R) == 4 ? 2 : 1;
+};
+
+template <typename R, int NIN, int S0>
+__device__ __forceinline__ void exec_wide_u(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                            int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
+  constexpr int M = WideMaxU<R>::in_persistent;
+  if (M == 1 || (d.nu == 0 && d.nk == 0))
+    exec_wide<R, NIN, S0, 1>(d, arena, b0, b1, r, c, red);
+  else if (d.nu == 0 && d.nk >= (M == 4 ? 2 : 1))
+    exec_wide<R, NIN, S0, M, true>(d, arena, b0, b1, r, c, red);
+  else if (d.nu == 0)
+    exec_wide<R, NIN, S0, 1>(d, arena, b0, b1, r, c, red);
+  else
+    exec_wide<R, NIN, S0, M>(d, arena, b0, b1, r, c, red);
+}
+
+template <typename R>
+__device__ __forceinline__ void exec_wide_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                              int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
+  const bool s0 = !(d.in_mask[0] & 1u);
+  switch (d.n_in * 2 + (s0 ? 1 : 0)) {
+    case 2: exec_wide_u<R, 1, 0>(d, arena, b0, b1, r, c, red); break;
+    case 3: exec_wide_u<R, 1, 1>(d, arena, b0, b1, r, c, red); break;
+    case 4: exec_wide_u<R, 2, 0>(d, arena, b0, b1, r, c, red); break;
+    case 5: exec_wide_u<R, 2, 1>(d, arena, b0, b1, r, c, red); break;
+    case 6: exec_wide_u<R, 3, 0>(d, arena, b0, b1, r, c, red); break;
+    case 7: exec_wide_u<R, 3, 1>(d, arena, b0, b1, r, c, red); break;
+    case 8: exec_wide_u<R, 4, 0>(d, arena, b0, b1, r, c, red); break;
+    default: exec_wide_u<R, 4, 1>(d, arena, b0, b1, r, c, red); break;
+  }
+}
+
+// ------------------------------------------------------------------ fused adjoint
+// Executor of OP_ADJOINT: every input adjoint of one wide bucket in one pass
+// over its union, so the output adjoint and each input are read once.  Input
+// 0 is the output adjoint (without bit 0), inputs 1..NIN-1 hold bit 0 and are
+// loaded as pairs.  For each union element the adjoint of input i receives
+// the output adjoint times the product of the other inputs, formed from
+// prefix and suffix products.  An output that holds the loop bits gets one
+// value per loop step: combined across the lanes it sums (shuffles; a
+// sub-block is at most one wavefront) and stored.  Every other output sums
+// the loop steps in registers and is written once per run of block steps
+// that flip only bits it lacks: stored, or added with atomics into zeroed
+// memory when it sums a block bit.  SL = 2: the first loop bit is unrolled
+// into two slots whose loads are in flight together.  Block ranges as in
+// exec_wide.
+template <typename R, int NIN, int SL>
+__device__ __forceinline__ void exec_adjoint(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                             int64_t blk_end, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk;
+  const int sbits = 31 - __clz(blockDim.x >> nl);
+  const int sub = tid >> nl;
+  const int lane = tid & ((1 << nl) - 1);
+  const int zk0 = nl + (SL > 1 ? 1 : 0), zb0 = nl + nk;
+  uint32_t blockbits = 0;
+  for (int z = zb0; z < d.nbits - 1; ++z) blockbits |= 1u << d.zbit[z];
+  uint32_t mask[NIN], loff[NIN], lsum[NIN], ss[NIN];
+  bool hold[NIN], atom[NIN];
+  const E* inp[NIN];
+  E* outp[NIN];
+  uint32_t aheld = 0;  // bits held by an output that accumulates over the loop
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    inp[i] = arena + d.in_off[i];
+    outp[i] = arena + (i ? d.adj_off[i] : 0);
+    hold[i] = i > 0 && nk > 0 && ((mask[i] >> d.zbit[nl]) & 1u);
+    atom[i] = (blockbits & ~mask[i]) != 0;
+    if (i > 0 && !hold[i]) aheld |= mask[i];
+    uint32_t o = 0, ls = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl) {
+        if (sh != LSH_NONE)
+          o |= ((uint32_t)(lane >> j) & 1u) << sh;
+        else
+          ls |= 1u << j;
+      }
+    }
+    loff[i] = o;
+    lsum[i] = ls;
+    ss[i] = SL > 1 ? bit_stride(mask[i], d.zbit[nl]) : 0u;
+  }
+  const int nloop = 1 << (nk - (SL > 1 ? 1 : 0));
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_st = lg_nblk - sbits;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_st - lg_chunk);
+  // combine a pair across the lanes in ls, then store or add it
+  auto put = [&](E* p, E s0, E s1, uint32_t ls, bool at) {
+    for (int j = 0; j < 6; ++j)
+      if ((ls >> j) & 1u) {
+        s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+        s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+      }
+    if ((lane & ls) == 0) {
+      if (at) {
+        atomic_add_c(p, s0);
+        atomic_add_c(p + 1, s1);
+      } else {
+        store_pair(p, s0, s1);
+      }
+    }
+  };
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t q0 = (uint32_t)ch << lg_chunk;
+    const uint32_t blk = base_blk + (q0 << sbits) + (uint32_t)sub;
+    uint32_t boff[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    for (int j = 0; j < d.nb; ++j)
+      if ((blk >> j) & 1u) {
+        const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+      }
+    E acc0[NIN], acc1[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) {
+      acc0[i] = E{0, 0};
+      acc1[i] = E{0, 0};
+    }
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      if (c) {
+        const int t = __ffs(c) - 1;
+        const bool up = ((c ^ (c >> 1)) >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
+        }
+      }
+      // an accumulating output keeps its sums while the next step flips a bit
+      // it does not hold
+      const uint32_t nxt = c + 1 < chunk ? 1u << d.zbit[zb0 + sbits + __ffs(c + 1) - 1] : 0u;
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = boff[i];
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
+        }
+        E ob[SL], a0[SL][NIN], a1[SL][NIN];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          ob[s] = inp[0][koff[0] + (s ? ss[0] : 0u)];
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) load_pair(inp[i] + koff[i] + (s ? ss[i] : 0u), a0[s][i], a1[s][i]);
+        }
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          E ex0[NIN], ex1[NIN];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            // prefix products pr[i] = ob * x[1] ... x[i-1]; ex[i] = pr[i] * suffix
+            E pr[NIN];
+            pr[1] = ob[s];
+#pragma unroll
+            for (int i = 1; i + 1 < NIN; ++i) pr[i + 1] = cmul(pr[i], h ? a1[s][i] : a0[s][i]);
+            E suf = E{1, 0};
+#pragma unroll
+            for (int i = NIN - 1; i >= 1; --i) {
+              const E x = h ? a1[s][i] : a0[s][i];
+              const E e = i == NIN - 1 ? pr[i] : cmul(pr[i], suf);
+              suf = i == NIN - 1 ? x : cmul(x, suf);
+              if (h)
+                ex1[i] = e;
+              else
+                ex0[i] = e;
+            }
+          }
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) {
+            if (hold[i]) {
+              put(outp[i] + koff[i] + (s ? ss[i] : 0u), ex0[i], ex1[i], lsum[i], atom[i]);
+            } else {
+              acc0[i] = cadd(acc0[i], ex0[i]);
+              acc1[i] = cadd(acc1[i], ex1[i]);
+            }
+          }
+        }
+      }
+      if (nxt && !(aheld & nxt)) continue;  // uniform: every accumulating output carries
+#pragma unroll
+      for (int i = 1; i < NIN; ++i) {
+        if (hold[i] || (nxt && !(mask[i] & nxt))) continue;
+        put(outp[i] + boff[i], acc0[i], acc1[i], lsum[i], atom[i]);
+        acc0[i] = E{0, 0};
+        acc1[i] = E{0, 0};
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void lds_add(float2* p, float2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ void lds_add(double2* p, double2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+
+// Executor of OP_ADJOINT ops flagged F_TILE: every input adjoint of a bucket
+// whose inputs each lack part of the union, summed tile by tile in LDS.  A
+// block is a tile; the workgroup's threads are its lanes (nl = log2 of the
+// workgroup size) and walk the remaining tile bits in a per-thread loop.  Per
+// union element, each output's value is combined across the lanes of the
+// wavefront that it sums (shuffles) and added into its tile sum in LDS
+// (2^(tile bits it holds) pairs, at lds + its base); at the end of the tile
+// the sums are stored, or added with atomics when the output sums a block bit.
+template <typename R, int NIN>
+__device__ __forceinline__ void exec_tile(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                          int64_t blk_end, int64_t wg_rank, int64_t wg_count,
+                                          typename CT<R>::E* __restrict__ lds) {
+  using E = typename CT<R>::E;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk, nb = d.nb;
+  const int lane = tid & 63;
+  uint32_t tmask = 0, blockbits = 0;
+  for (int z = 0; z < nl + nk; ++z) tmask |= 1u << d.zbit[z];
+  for (int z = nl + nk; z < d.nbits - 1; ++z) blockbits |= 1u << d.zbit[z];
+  uint32_t mask[NIN], tm[NIN], loff[NIN], lidx[NIN], lsum[NIN], lbase[NIN];
+  bool atom[NIN];
+  const E* inp[NIN];
+  E* outp[NIN];
+  uint32_t total = 0;
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    tm[i] = tmask & mask[i];
+    inp[i] = arena + d.in_off[i];
+    outp[i] = arena + (i ? d.adj_off[i] : 0);
+    atom[i] = (blockbits & ~mask[i]) != 0;
+    uint32_t o = 0, li = 0, ls = 0;
+    for (int j = 0; j < nl; ++j) {
+      const uint32_t u = d.zbit[j];
+      const uint32_t bit = (uint32_t)(tid >> j) & 1u;
+      if ((mask[i] >> u) & 1u) {
+        o += bit * bit_stride(mask[i], u);
+        li += bit * bit_stride(tm[i], u);
+      } else if (j < 6) {
+        ls |= 1u << j;
+      }
+    }
+    loff[i] = o;
+    lidx[i] = li;
+    lsum[i] = ls;
+    lbase[i] = total;
+    if (i > 0) total += 2u << __popc(tm[i]);
+  }
+  const int nloop = 1 << nk;
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_nblk > lg_wg ? lg_nblk - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_nblk - lg_chunk);
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t blk0 = base_blk + ((uint32_t)ch << lg_chunk);
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      const uint32_t blk = blk0 + (uint32_t)c;
+      uint32_t bb[NIN];  // block part of every operand's offset
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) bb[i] = 0;
+      for (int j = 0; j < nb; ++j)
+        if ((blk >> j) & 1u) {
+          const uint32_t u = d.zbit[nl + nk + j];
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) bb[i] += bit_stride(mask[i], u);
+        }
+      for (uint32_t e = tid; e < total; e += blockDim.x) lds[e] = E{0, 0};
+      __syncthreads();
+      uint32_t koff[NIN], kl[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) {
+        koff[i] = bb[i] + loff[i];
+        kl[i] = lidx[i];
+      }
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;
+          const uint32_t u = d.zbit[nl + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u), sl = bit_stride(tm[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+            kl[i] = up ? kl[i] + sl : kl[i] - sl;
+          }
+        }
+        E ob, a0[NIN], a1[NIN];
+        ob = inp[0][koff[0]];
+#pragma unroll
+        for (int i = 1; i < NIN; ++i) load_pair(inp[i] + koff[i], a0[i], a1[i]);
+        E ex0[NIN], ex1[NIN];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          E pr[NIN];
+          pr[1] = ob;
+#pragma unroll
+          for (int i = 1; i + 1 < NIN; ++i) pr[i + 1] = cmul(pr[i], h ? a1[i] : a0[i]);
+          E suf = E{1, 0};
+#pragma unroll
+          for (int i = NIN - 1; i >= 1; --i) {
+            const E x = h ? a1[i] : a0[i];
+            const E e = i == NIN - 1 ? pr[i] : cmul(pr[i], suf);
+            suf = i == NIN - 1 ? x : cmul(x, suf);
+            if (h)
+              ex1[i] = e;
+            else
+              ex0[i] = e;
+          }
+        }
+#pragma unroll
+        for (int i = 1; i < NIN; ++i) {
+          E s0 = ex0[i], s1 = ex1[i];
+          for (int j = 0; j < 6; ++j)
+            if ((lsum[i] >> j) & 1u) {
+              s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+              s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+            }
+          if ((lane & lsum[i]) == 0) {
+            lds_add(lds + lbase[i] + 2 * kl[i], s0);
+            lds_add(lds + lbase[i] + 2 * kl[i] + 1, s1);
+          }
+        }
+      }
+      __syncthreads();
+      // the tile's sums: element e of output i holds its tile bits in order
+#pragma unroll
+      for (int i = 1; i < NIN; ++i) {
+        const uint32_t n = 1u << __popc(tm[i]);
+        for (uint32_t e = tid; e < n; e += blockDim.x) {
+          uint32_t off = bb[i], rest = tm[i], k = e;
+          while (rest) {
+            const uint32_t u = __ffs(rest) - 1;
+            rest &= rest - 1;
+            if (k & 1u) off += bit_stride(mask[i], u);
+            k >>= 1;
+          }
+          const E v0 = lds[lbase[i] + 2 * e], v1 = lds[lbase[i] + 2 * e + 1];
+          if (atom[i]) {
+            atomic_add_c(outp[i] + off, v0);
+            atomic_add_c(outp[i] + off + 1, v1);
+          } else {
+            store_pair(outp[i] + off, v0, v1);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void exec_adjoint_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                                 int64_t r, int64_t c, typename CT<R>::E* lds) {
+  if (d.flags & F_TILE) {
+    if (d.n_in == 3)
+      exec_tile<R, 3>(d, arena, b0, b1, r, c, lds);
+    else if (d.n_in == 4)
+      exec_tile<R, 4>(d, arena, b0, b1, r, c, lds);
+    return;
+  }
+  constexpr bool two = WideMaxU<R>::in_persistent > 1;
+  const bool sl = two && d.nk >= 1;
+  switch (d.n_in * 2 + (sl ? 1 : 0)) {
+    case 6: exec_adjoint<R, 3, 1>(d, arena, b0, b1, r, c); break;
+    case 7: exec_adjoint<R, 3, two ? 2 : 1>(d, arena, b0, b1, r, c); break;
+    case 8: exec_adjoint<R, 4, 1>(d, arena, b0, b1, r, c); break;
+    case 9: exec_adjoint<R, 4, two ? 2 : 1>(d, arena, b0, b1, r, c); break;
+    default: break;
+  }
+}
+
+template <typename R, int MAXNIN, bool USE_LDS>
+__device__ __forceinline__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
+                                                  int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red,
+                                                  typename CT<R>::E* lds) {
+  switch (d.n_in) {
+    case 1: exec_contract<R, 1, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 2: exec_contract<R, 2, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 3: exec_contract<R, 3, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 4: if constexpr (MAXNIN >= 4) exec_contract<R, 4, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 5: if constexpr (MAXNIN >= 5) exec_contract<R, 5, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 6: if constexpr (MAXNIN >= 6) exec_contract<R, 6, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 7: if constexpr (MAXNIN >= 7) exec_contract<R, 7, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    default: if constexpr (MAXNIN >= 8) exec_contract<R, 8, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+  }
+}
+
+// ------------------------------------------------------------------ leaf tables
+// Leaf-product table of one bucket: entry e = prod over the bucket's leaves of
+// leaf[e restricted to the leaf's indices].
+template <typename R>
+__device__ __forceinline__ void exec_leaf(const OpDesc& d, typename CT<R>::E* arena, const Env& env, int64_t wg_rank,
+                          int64_t wg_count) {
+  using E = typename CT<R>::E;
+  const E* vals = reinterpret_cast<const E*>(env.leafvals);
+  const int64_t n = int64_t(1) << d.nbits;
+  E* out = arena + d.out_off;
+  for (int64_t e = wg_rank * blockDim.x + threadIdx.x; e < n; e += wg_count * blockDim.x) {
+    E p = {1, 0};
+    for (int r = 0; r < d.aux1; ++r) {
+      const LeafRef L = env.leafrefs[d.aux0 + r];
+      int idx = (e >> L.pa) & 1;
+      if (L.pb >= 0) idx |= ((e >> L.pb) & 1) << 1;
+      p = cmul(p, vals[L.kind * 4 + idx]);
+    }
+    out[e] = p;
+  }
+}
+
+// Parameter slot of a leaf kind inside a cone's result record: gamma_l at
+// 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+>, Z and <0|.
+__device__ __forceinline__ int theta_slot(int kind, int p) {
+  if (kind < 2 || kind >= 2 + 4 * p) return -1;
+  const int l = (kind - 2) >> 2, t = (kind - 2) & 3;
+  return t < 2 ? 2 + 2 * l : 2 + 2 * p + 2 * l;
+}
+
+template <typename R>
+__device__ double2 block_sum(double2 v) {
+  __shared__ double2 red[32];
+  for (int m = 32; m >= 1; m >>= 1) {
+    v.x += __shfl_xor(v.x, m);
+    v.y += __shfl_xor(v.y, m);
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double2 s = make_double2(0, 0);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) {
+      s.x += red[i].x;
+      s.y += red[i].y;
+    }
+  return s;  // valid in thread 0
+}
+
+// dR/dtheta += sum_e Lbar[e] * d(leaf product)/dtheta [e], split per leaf:
+// the derivative of one leaf times the product of the others.
+template <typename R>
+__device__ __forceinline__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
+  using E = typename CT<R>::E;
+  const E* vals = reinterpret_cast<const E*>(env.leafvals);
+  const E* dvals = reinterpret_cast<const E*>(env.dleafvals);
+  const int64_t n = int64_t(1) << d.nbits;
+  const E* lbar = arena + d.in_off[0];
+  double* res = env.res + (int64_t)d.cone * env.res_stride;
+  for (int r = 0; r < d.aux1; ++r) {
+    const LeafRef L = env.leafrefs[d.aux0 + r];
+    const int slot = theta_slot(L.kind, env.p);
+    if (slot < 0) continue;  // uniform across the workgroup
+    double2 acc = make_double2(0, 0);
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+      E t = lbar[e];
+      for (int s = 0; s < d.aux1; ++s) {
+        const LeafRef Ls = env.leafrefs[d.aux0 + s];
+        int idx = (e >> Ls.pa) & 1;
+        if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
+        t = cmul(t, s == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
+      }
+      acc.x += (double)t.x;
+      acc.y += (double)t.y;
+    }
+    const double2 s = block_sum<R>(acc);
+    if (threadIdx.x == 0) {
+      atomicAdd(res + slot, s.x);
+      atomicAdd(res + slot + 1, s.y);
+    }
+  }
+}
+
+// Cone value R = product of the scalar outputs; with F_GRAD also the seed
+// dR/dO_s = product of the other scalars, and zeroed gradient accumulators.
+template <typename R>
+__device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env,
+                                            typename CT<R>::E* lds = nullptr) {
+  using E = typename CT<R>::E;
+  double* res = env.res + (int64_t)d.cone * env.res_stride;
+  const int ns = d.n_in;
+  auto at = [&](int i) -> E* {
+    return (lds && ((d.lds_mask >> i) & 1u)) ? lds + d.lds_off[i] : arena + d.in_off[i];
+  };
+  if (threadIdx.x == 0) {
+    double2 prod = make_double2(1, 0);
+    for (int s = 0; s < ns; ++s) {
+      const E x = *at(s);
+      prod = cmul(prod, make_double2(x.x, x.y));
+    }
+    res[0] = prod.x;
+    res[1] = prod.y;
+  }
+  if (d.flags & F_GRAD) {
+    // seed of scalar s: product of the other scalars (thread s; no private arrays)
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      double2 seed = make_double2(1, 0);
+      for (int t = 0; t < ns; ++t)
+        if (t != s) {
+          const E x = *at(t);
+          seed = cmul(seed, make_double2(x.x, x.y));
+        }
+      E o;
+      o.x = (R)seed.x;
+      o.y = (R)seed.y;
+      *at(ns + s) = o;
+    }
+    for (int i = threadIdx.x; i < 4 * env.p; i += blockDim.x) res[2 + i] = 0.0;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void exec_zero(const OpDesc& d, typename CT<R>::E* arena, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  E* out = arena + d.out_off;
+  const int64_t n = d.in_off[0];
+  for (int64_t e = wg_rank * blockDim.x + threadIdx.x; e < n; e += wg_count * blockDim.x) out[e] = E{0, 0};
+}
+
+// MAXNIN < 0: contraction ops have exactly -MAXNIN inputs (plain launches are
+// specialised per input count on the host); else up to MAXNIN inputs.
+template <typename R, int MAXNIN, bool USE_LDS = false, bool WIDE = false>
+__device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank,
+                                        int64_t wg_count, RedBuf<typename CT<R>::E>* red,
+                                        typename CT<R>::E* lds = nullptr) {
+  using E = typename CT<R>::E;
+  E* arena = reinterpret_cast<E*>(env.arena);
+  switch (d.kind) {
+    case OP_CONTRACT:
+      if constexpr (WIDE && !USE_LDS) {
+        if (d.flags & F_WIDE) {
+          exec_wide_any<R>(d, arena, b0, b1, wg_rank, wg_count, red);
+          break;
+        }
+      }
+      if constexpr (MAXNIN < 0)
+        exec_contract<R, -MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
+      else
+        exec_contract_any<R, MAXNIN, USE_LDS>(d, arena, b0, b1, wg_rank, wg_count, red, lds);
+      break;
+    case OP_ADJOINT:
+      if constexpr (WIDE && !USE_LDS) exec_adjoint_any<R>(d, arena, b0, b1, wg_rank, wg_count, lds);
+      break;
+    case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
+    case OP_RESULT:
+      if (wg_rank == 0) exec_result<R>(d, arena, env, USE_LDS ? lds : nullptr);
+      break;
+    case OP_ZERO: exec_zero<R>(d, arena, wg_rank, wg_count); break;
+    case OP_LEAFGRAD:
+      if (wg_rank == 0) exec_leafgrad<R>(d, arena, env);
+      break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+// One op per launch (the plain per-edge loop).
+// The descriptor is staged in LDS: the executors read its bit tables inside
+// their loops, and an LDS read does not wait for the loads in flight.
+__device__ __forceinline__ void stage_desc(OpDesc& sd, const OpDesc* ops, int op) {
+  constexpr int W = sizeof(OpDesc) / sizeof(uint4);
+  if (threadIdx.x < W) reinterpret_cast<uint4*>(&sd)[threadIdx.x] = reinterpret_cast<const uint4*>(ops + op)[threadIdx.x];
+  __syncthreads();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs: give each XCD a
+// contiguous range of logical workgroups (and so of blocks), so blocks that
+// share input data meet in the same L2.
+__device__ __forceinline__ int64_t xcd_rank() {
+  const int64_t G = gridDim.x;
+  const int64_t w = blockIdx.x;
+  return G % 8 == 0 ? (w % 8) * (G / 8) + w / 8 : w;
+}
+
+}  // namespace qtn

@@ -39,6 +39,30 @@ hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* op
                              size_t lds_bytes, long long spin_limit, hipStream_t st);
 // E, dE/dgamma, dE/dbeta into fin and, when host_fin is given, into mapped
 // pinned host memory, with ctl[0..1] (or zeros without ctl) into host_ctl
+// Per-element-type launchers, each instantiated in its own translation unit
+// (kern_ops.hip, kern_persist.hip) so the kernels compile in parallel.
+template <typename R>
+hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads, int max_grid,
+                       hipStream_t st);
+template <typename R, bool W>
+hipError_t launch_persistent_t(int max_nin, const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
+                               int32_t* ctl, const Env& env, int threads, int grid, size_t lds_bytes,
+                               long long spin_limit, hipStream_t st);
+extern template hipError_t launch_op_t<float>(const OpDesc*, const OpDesc&, int, const Env&, int, int, hipStream_t);
+extern template hipError_t launch_op_t<double>(const OpDesc*, const OpDesc&, int, const Env&, int, int, hipStream_t);
+extern template hipError_t launch_persistent_t<float, false>(int, const OpDesc*, const QItem*, int, const int32_t*,
+                                                             int32_t*, const Env&, int, int, size_t, long long,
+                                                             hipStream_t);
+extern template hipError_t launch_persistent_t<float, true>(int, const OpDesc*, const QItem*, int, const int32_t*,
+                                                            int32_t*, const Env&, int, int, size_t, long long,
+                                                            hipStream_t);
+extern template hipError_t launch_persistent_t<double, false>(int, const OpDesc*, const QItem*, int, const int32_t*,
+                                                              int32_t*, const Env&, int, int, size_t, long long,
+                                                              hipStream_t);
+extern template hipError_t launch_persistent_t<double, true>(int, const OpDesc*, const QItem*, int, const int32_t*,
+                                                             int32_t*, const Env&, int, int, size_t, long long,
+                                                             hipStream_t);
+
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
                         double* fin, double* host_fin, const int32_t* ctl, int32_t* host_ctl, hipStream_t st);
 
