@@ -149,9 +149,32 @@ qtn_status qtn_contract(qtn_net* net, qtn_mode mode, void* workspace, size_t ws_
 qtn_status qtn_energy_grad(qtn_net* net, qtn_mode mode, void* workspace, size_t ws_bytes, void* stream,
                            void* zz_out, double* energy_out, double* dgamma_out, double* dbeta_out);
 
+/* Allocation-free variant of qtn_energy_grad, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is the library's static
+ * device scratch (QTN_SCRATCH_BYTES per GPU, reserved when the library's code
+ * object is loaded on that GPU and held until the process ends); the caller
+ * passes only the stream and the outputs, which mean what they mean for
+ * qtn_energy_grad.  The sweep's kernels are launched directly on `stream` (the
+ * batched form is not captured into a graph) and the call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.  Needs qtn_order and
+ * qtn_set_params as usual.  QTN_ENOMEM when qtn_workspace_size(net, 1) exceeds
+ * QTN_SCRATCH_BYTES (e.g. p >= 4 at tens of vertices).  Every call on one GPU
+ * uses the same scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (other threads, or streams not ordered with each other)
+ * race and must be serialised by the caller.  qtn_edge_results with a NULL
+ * workspace reads the per-edge results of such a call. */
+#define QTN_SCRATCH_BYTES ((size_t)64 << 20)
+qtn_status qtn_energy_grad_noalloc(qtn_net* net, qtn_mode mode, void* stream, void* zz_out, double* energy_out,
+                                   double* dgamma_out, double* dbeta_out);
+
 /* Per-edge results of the last sweep, host float64: zz[2*e] = Re <Z_j Z_k>,
  * zz[2*e+1] = Im; dzz (nullable) [n_edges][2p][2]: d<Z_j Z_k>/d(gamma_1..p,
- * beta_1..p), complex.  Reads the workspace of that sweep; synchronises `stream`. */
+ * beta_1..p), complex.  Reads the workspace of that sweep (`workspace` must be
+ * the one it used, or NULL for "the last sweep's"); synchronises `stream` and
+ * the sweep.  QTN_ESTATE before any sweep, or for dzz after a sweep without
+ * the adjoint; QTN_EDEVICE when that sweep's persistent kernel reported an
+ * error. */
 qtn_status qtn_edge_results(qtn_net* net, const void* workspace, void* stream, double* zz, double* dzz);
 
 qtn_status qtn_get_info(const qtn_net* net, qtn_info* out);

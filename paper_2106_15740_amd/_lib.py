@@ -12,6 +12,7 @@ QTN_C64, QTN_C128 = 0, 1
 QTN_ORDER_MIN_DEGREE, QTN_ORDER_MIN_FILL = 0, 1
 QTN_PLAIN, QTN_BATCHED = 0, 1
 QTN_HOST_ONLY = -1
+QTN_SCRATCH_BYTES = 64 << 20
 
 STATUS_NAMES = {0: "QTN_OK", 1: "QTN_EINVAL", 2: "QTN_ENOMEM", 3: "QTN_EDEVICE", 4: "QTN_EUNSUPPORTED",
                 5: "QTN_ESTATE"}
@@ -22,7 +23,7 @@ EXPORTS = [
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
-    "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model",
+    "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model", "qtn_energy_grad_noalloc",
     "qtn_net_free",
 ]
 
@@ -104,6 +105,7 @@ def lib() -> C.CDLL:
         "qtn_build_amplitude": (I32, [P, I32, I32, P, I32, I32, C.POINTER(P)]),
         "qtn_amplitude": (I32, [P, I32, P, SZ, P, P, P]),
         "qtn_cost_model": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost)]),
+        "qtn_energy_grad_noalloc": (I32, [P, I32, P, P, P, P, P]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

@@ -19,6 +19,8 @@
 #include "kernels.hpp"
 #include "plan.hpp"
 
+static_assert(qtn::kScratchBytes == QTN_SCRATCH_BYTES, "scratch size of the header and the kernels differ");
+
 using namespace qtn;
 
 namespace {
@@ -44,6 +46,7 @@ struct qtn_ctx {
   int device = 0;
   int n_cu = 256;
   hipStream_t cap_stream = nullptr;
+  void* scratch = nullptr;  // device address of this device's static scratch (allocation-free entry point)
 };
 
 struct DevProg {
@@ -87,6 +90,11 @@ struct qtn_net {
   double kernel_ms_sum = 0;
   int64_t kernel_count = 0;
   std::vector<double> gamma, beta;
+  // the last sweep enqueued: its mode (-1: none yet), whether it ran the
+  // adjoint, and its workspace (qtn_edge_results reads it)
+  int last_mode = -1;
+  bool last_grad = false;
+  const void* last_ws = nullptr;
 };
 
 namespace {
@@ -196,6 +204,9 @@ Env make_env(qtn_net* n, char* ws, const WsLayout& L) {
 // pk0/pk1 (not under capture) the persistent kernel is bracketed by them.
 qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t st, void* zz_out,
                          hipEvent_t pk0 = nullptr, hipEvent_t pk1 = nullptr) {
+  n->last_mode = mode;
+  n->last_grad = grad;
+  n->last_ws = ws;
   const WsLayout L = ws_layout(n, grad);
   char* w = static_cast<char*>(ws);
   Env env = make_env(n, w, L);
@@ -245,6 +256,25 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
   return QTN_OK;
 }
 
+// Waits for the last sweep's completion event.  Polls rather than blocks: a
+// blocking wait can add a scheduler wake-up (up to a millisecond) to every
+// sweep.
+hipError_t wait_done(qtn_net* n) {
+  hipError_t q;
+  while ((q = hipEventQuery(n->ev_done)) == hipErrorNotReady) std::this_thread::yield();
+  return q;
+}
+
+// The persistent kernel's error flag as the final kernel copied it into the
+// mapped host buffer (valid once the sweep has completed).
+int32_t sweep_flag(const qtn_net* n) {
+  const WsLayout L = ws_layout(n, true);
+  int32_t flag = 0;
+  std::memcpy(&flag, reinterpret_cast<const char*>(n->h_fin) + (L.ctl_off - L.fin_off) + sizeof(int32_t),
+              sizeof(int32_t));
+  return flag;
+}
+
 qtn_status check_ready(qtn_net* n, void* ws, size_t ws_bytes, bool grad) {
   if (!n) return fail(QTN_EINVAL, "net is NULL");
   if (n->ctx->device < 0) return fail(QTN_ESTATE, "host-only context cannot run contractions");
@@ -289,6 +319,9 @@ qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes,
     // events on the caller's stream around the replay time the device work
     // of the whole sweep (events recorded inside a captured graph carry no
     // timestamps)
+    n->last_mode = mode;
+    n->last_grad = grad;
+    n->last_ws = ws;
     HIPCHECK(hipEventRecord(n->ev_k0, st));
     HIPCHECK(hipGraphLaunch(g.exec, st));
     HIPCHECK(hipEventRecord(n->ev_k1, st));
@@ -299,10 +332,7 @@ qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes,
   }
   HIPCHECK(hipEventRecord(n->ev_done, st));
   if (want_host) {
-    // poll rather than block: a blocking wait can add a scheduler wake-up
-    // (up to a millisecond) to every sweep
-    hipError_t q;
-    while ((q = hipEventQuery(n->ev_done)) == hipErrorNotReady) std::this_thread::yield();
+    hipError_t q = wait_done(n);
     if (q != hipSuccess) return fail(QTN_EDEVICE, std::string("sweep: ") + hipGetErrorString(q));
     if (mode == QTN_BATCHED && n->ev_pending) {
       float ms = 0;
@@ -314,14 +344,7 @@ qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes,
       }
       n->ev_pending = false;
     }
-    // the persistent kernel's error flag
-    if (mode == QTN_BATCHED) {
-      const WsLayout L = ws_layout(n, grad);
-      int32_t flag = 0;
-      std::memcpy(&flag, reinterpret_cast<const char*>(n->h_fin) + (L.ctl_off - L.fin_off) + sizeof(int32_t),
-                  sizeof(int32_t));
-      if (flag) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
-    }
+    if (mode == QTN_BATCHED && sweep_flag(n)) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
   }
   return QTN_OK;
 }
@@ -354,6 +377,13 @@ qtn_status qtn_create(int device, qtn_ctx** out) {
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return fail(QTN_EDEVICE, "stream creation failed");
+  }
+  // the static scratch's device address on this device (current here)
+  hipError_t se = scratch_address(device, &c->scratch);
+  if (se != hipSuccess || !c->scratch) {
+    (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return fail(QTN_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(se));
   }
   *out = c;
   return QTN_OK;
@@ -580,12 +610,55 @@ qtn_status qtn_energy_grad(qtn_net* n, qtn_mode mode, void* ws, size_t ws_bytes,
   return QTN_OK;
 }
 
+qtn_status qtn_energy_grad_noalloc(qtn_net* n, qtn_mode mode, void* stream, void* zz_out, double* energy_out,
+                                   double* dgamma_out, double* dbeta_out) {
+  if (mode != QTN_PLAIN && mode != QTN_BATCHED) return fail(QTN_EINVAL, "unknown mode");
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (!energy_out) return fail(QTN_EINVAL, "energy_out is NULL");
+  if ((dgamma_out == nullptr) != (dbeta_out == nullptr)) return fail(QTN_EINVAL, "dgamma_out/dbeta_out mismatch");
+  if (n->ctx->device < 0) return fail(QTN_ESTATE, "host-only context cannot run contractions");
+  if (!n->P.ordered || !n->d_ops) return fail(QTN_ESTATE, "qtn_order has not been called");
+  void* ws = n->ctx->scratch;
+  if (!ws) return fail(QTN_EDEVICE, "the static scratch has no device address");
+  const size_t need = ws_layout(n, true).total;
+  if (need > kScratchBytes)
+    return fail(QTN_ENOMEM, "the network needs " + std::to_string(need) + " bytes of workspace; the static scratch " +
+                                "of the allocation-free entry point holds " + std::to_string(kScratchBytes));
+  qtn_status s = check_ready(n, ws, kScratchBytes, true);
+  if (s != QTN_OK) return s;
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // kernels launched directly on the caller's stream: no graph capture or
+  // instantiation, nothing allocated
+  s = enqueue_sweep(n, mode, true, ws, st, zz_out);
+  if (s != QTN_OK) return s;
+  HIPCHECK(hipEventRecord(n->ev_done, st));
+  hipError_t q = wait_done(n);
+  if (q != hipSuccess) return fail(QTN_EDEVICE, std::string("sweep: ") + hipGetErrorString(q));
+  if (mode == QTN_BATCHED && sweep_flag(n)) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
+  const int p = n->P.p;
+  *energy_out = n->h_fin[0];
+  if (dgamma_out)
+    for (int l = 0; l < p; ++l) {
+      dgamma_out[l] = n->h_fin[1 + l];
+      dbeta_out[l] = n->h_fin[1 + p + l];
+    }
+  return QTN_OK;
+}
+
 qtn_status qtn_edge_results(qtn_net* n, const void* ws, void* stream, double* zz, double* dzz) {
-  if (!n || !ws) return fail(QTN_EINVAL, "net or workspace is NULL");
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
   if (n->ctx->device < 0) return fail(QTN_ESTATE, "host-only context has no device results");
   if (!n->P.ordered) return fail(QTN_ESTATE, "qtn_order has not been called");
+  if (n->last_mode < 0) return fail(QTN_ESTATE, "no sweep has run");
+  if (!ws) ws = n->last_ws;
+  if (ws != n->last_ws) return fail(QTN_EINVAL, "workspace is not the one the last sweep used");
+  if (dzz && !n->last_grad) return fail(QTN_ESTATE, "the last sweep computed no gradient");
   HIPCHECK(hipSetDevice(n->ctx->device));
   HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  HIPCHECK(hipEventSynchronize(n->ev_done));
+  if (n->last_mode == QTN_BATCHED && sweep_flag(n))
+    return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
   const size_t nc = n->P.cones.size();
   const int rs = 2 + 4 * n->P.p;
   std::vector<double> res(nc * rs);
@@ -724,6 +797,7 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
       if ((r = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, false)) != QTN_OK) return r;
     HIPCHECK(hipEventRecord(e1, st));
     HIPCHECK(hipEventSynchronize(e1));
+    if (sweep_flag(n)) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
     float ms = 0;
     HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
     *ms_out = ms;
@@ -851,11 +925,7 @@ qtn_status qtn_time_persistent(qtn_net* n, int32_t with_grad, void* ws, size_t w
   (void)hipEventDestroy(e1);
   if (s != QTN_OK) return s;
   HIPCHECK(hipStreamSynchronize(st));
-  int32_t flag = 0;
-  const WsLayout L = ws_layout(n, with_grad != 0);
-  std::memcpy(&flag, reinterpret_cast<const char*>(n->h_fin) + (L.ctl_off - L.fin_off) + sizeof(int32_t),
-              sizeof(int32_t));
-  if (flag) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
+  if (sweep_flag(n)) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
   if (ms_out) *ms_out = tot / reps;
   return QTN_OK;
 }

@@ -8,6 +8,8 @@
 // lowest bit, so the eliminated index of a bucket is bit 0 of every input that
 // holds it: each thread loads the (x_v = 0, 1) pair of such an input with one
 // 16-byte load and sums the pair in registers.
+#include <mutex>
+
 #include "exec.hpp"
 
 namespace qtn {
@@ -209,6 +211,39 @@ __global__ void final_kernel(const double* __restrict__ res, int res_stride, int
   }
   // the queue head and the persistent kernel's error flag, next to the results
   if (host_ctl && threadIdx.x < 2) host_ctl[threadIdx.x] = ctl ? ctl[threadIdx.x] : 0;
+}
+
+// ------------------------------------------------------------------ static scratch
+// Device workspace of the allocation-free entry point: one array per GPU,
+// held until the process ends.  Host code must never pass `scratch` itself to
+// a kernel (in host code the name is a host-side stand-in, not a device
+// address): scratch_address() looks up the device address once per device
+// with that device current and every later use goes through it.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, void** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------------ host launchers

@@ -37,8 +37,6 @@ hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStrea
 hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
                              size_t lds_bytes, long long spin_limit, hipStream_t st);
-// E, dE/dgamma, dE/dbeta into fin and, when host_fin is given, into mapped
-// pinned host memory, with ctl[0..1] (or zeros without ctl) into host_ctl
 // Per-element-type launchers, each instantiated in its own translation unit
 // (kern_ops.hip, kern_persist.hip) so the kernels compile in parallel.
 template <typename R>
@@ -63,6 +61,14 @@ extern template hipError_t launch_persistent_t<double, true>(int, const OpDesc*,
                                                              int32_t*, const Env&, int, int, size_t, long long,
                                                              hipStream_t);
 
+// Bytes of the static device scratch used by the allocation-free entry
+// point, and its device address on `device` (looked up once per device with
+// that device current, then cached).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(int device, void** ptr);
+
+// E, dE/dgamma, dE/dbeta into fin and, when host_fin is given, into mapped
+// pinned host memory, with ctl[0..1] (or zeros without ctl) into host_ctl
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,
                         double* fin, double* host_fin, const int32_t* ctl, int32_t* host_ctl, hipStream_t st);
 

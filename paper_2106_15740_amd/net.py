@@ -197,16 +197,27 @@ class QaoaNet:
                                           dg.ctypes.data_as(C.c_void_p), db.ctypes.data_as(C.c_void_p)))
         return e.value, dg, db
 
+    def energy_grad_noalloc(self, mode: str = "batched", zz_out=None) -> Tuple[float, np.ndarray, np.ndarray]:
+        """energy_grad through the allocation-free entry point: the workspace is
+        the library's static device scratch (64 MiB per GPU), nothing is
+        allocated."""
+        e = C.c_double()
+        dg = np.zeros(self.p)
+        db = np.zeros(self.p)
+        L.check(self._lib.qtn_energy_grad_noalloc(self.handle, _MODES[mode], self._stream(),
+                                                  C.c_void_p(zz_out.data_ptr() if zz_out is not None else 0),
+                                                  C.byref(e), dg.ctypes.data_as(C.c_void_p),
+                                                  db.ctypes.data_as(C.c_void_p)))
+        return e.value, dg, db
+
     def edge_results(self, with_grad: bool = False):
         """Per-edge <Z_j Z_k> (complex128) and, with_grad, d<ZZ>/d(gamma, beta)
         of shape [n_edges, 2p] from the last sweep."""
-        ws = self._ws.get("buf")
-        if ws is None:
-            raise RuntimeError("no sweep has run")
         m = len(self.edges)
         zz = np.zeros(2 * m)
         dzz = np.zeros(m * 4 * self.p) if with_grad else None
-        L.check(self._lib.qtn_edge_results(self.handle, C.c_void_p(ws.data_ptr()), self._stream(),
+        # NULL workspace: the one the last sweep used (the library tracks it)
+        L.check(self._lib.qtn_edge_results(self.handle, None, self._stream(),
                                            zz.ctypes.data_as(C.c_void_p),
                                            dzz.ctypes.data_as(C.c_void_p) if with_grad else None))
         z = zz[0::2] + 1j * zz[1::2]
