@@ -93,6 +93,11 @@ typedef struct {
   double rec_bytes;         /* extra bytes of those recomputations per gradient sweep (not algorithmic) */
   size_t arena_keep_all;    /* arena bytes the gradient sweep would need keeping every output */
   int64_t n_steps;          /* contraction steps over all cones (buckets after merging small ones) */
+  double fwd_bytes_bucket;  /* the same counts per bucket of the elimination order (one bucket per index, before
+                               merging): forward s * sum_b (sum_t 2^rank(t) + 2^rank(out_b)) over intermediate
+                               inputs t (rank <= 2 leaves left out); adjoint s * sum_b (2^rank(out_b) + 2 sum_t
+                               2^rank(t)) (read the output adjoint and the stored inputs, write the input adjoints) */
+  double bwd_bytes_bucket;
 } qtn_info;
 
 /* Context bound to HIP device `device` (hipSetDevice is called on it).  Owns a
@@ -227,6 +232,21 @@ qtn_status qtn_kernel_time(qtn_net* net, double* ms_sum, int64_t* count, int32_t
  * once; per replay) and their summed average device time. */
 qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width, void* workspace, size_t ws_bytes,
                              void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out);
+
+/* In-sweep rate of the wide buckets: the contraction ops of buckets whose
+ * output rank is >= min_width (forward and, with with_grad, adjoint ops) as a
+ * queue of their own -- chained per light cone in program order, split into
+ * the same tiles and list-scheduled as in the batched sweep -- run by one
+ * launch of the persistent kernel, `reps` times (after one warm-up) between
+ * HIP events on `stream`.  Reads the tensors left in `workspace` by the last
+ * sweep of the same kind (outputs are overwritten or accumulated, so run a
+ * sweep again before reading results).  Returns the ops' algorithmic bytes
+ * (each input read once, output written once), the average device time, and
+ * the op and queue-item counts.  Allocates (and frees) the sub-queue's device
+ * copy.  QTN_EDEVICE if a dependency wait gave up. */
+qtn_status qtn_time_wide_sweep(qtn_net* net, int32_t with_grad, int32_t min_width, void* workspace,
+                               size_t ws_bytes, void* stream, int32_t reps, double* bytes_out, double* ms_out,
+                               int64_t* n_ops_out, int64_t* n_items_out);
 
 /* Device time of the persistent kernel alone: `reps` batched sweeps (after
  * one warm-up) are enqueued on `stream` without graph capture, each with HIP

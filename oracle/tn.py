@@ -78,8 +78,10 @@ def mixer_tensor(b: float) -> np.ndarray:
     return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
 
 
-def network(n: int, edges: Sequence[Edge], gamma, beta, j: int, k: int):
-    """Tensors (array, [index ids]) of <gamma beta| Z_j Z_k |gamma beta>."""
+def network(n: int, edges: Sequence[Edge], gamma, beta, j: int, k: int, dtype=np.complex128):
+    """Tensors (array, [index ids]) of <gamma beta| Z_j Z_k |gamma beta>.
+    The tensors are built in complex128 and stored as `dtype` (complex64 only
+    for timing the oracle at the GPU path's precision)."""
     p = len(gamma)
     kept = prune(circuit(n, edges, p), j, k)
     qubits = sorted({q for _, _, qs in kept for q in qs} | {j, k})
@@ -114,7 +116,7 @@ def network(n: int, edges: Sequence[Edge], gamma, beta, j: int, k: int):
     tensors = ket + [(a, [rename.get(i, i) for i in ix]) for a, ix in bra]
     zvec = np.array([1.0, -1.0], dtype=np.complex128)
     tensors += [(zvec, [kcur[j]]), (zvec, [kcur[k]])]
-    return tensors
+    return [(a.astype(dtype), ix) for a, ix in tensors]
 
 
 def min_fill_order(tensors) -> Tuple[List[int], int]:
@@ -181,9 +183,9 @@ def contract(tensors, order: Sequence[int]) -> complex:
     return val
 
 
-def zz_edge(n: int, edges: Sequence[Edge], gamma, beta, j: int, k: int) -> complex:
+def zz_edge(n: int, edges: Sequence[Edge], gamma, beta, j: int, k: int, dtype=np.complex128) -> complex:
     """<gamma beta| Z_j Z_k |gamma beta> by tensor-network contraction."""
-    t = network(n, edges, gamma, beta, j, k)
+    t = network(n, edges, gamma, beta, j, k, dtype)
     order, _ = min_fill_order(t)
     return contract(t, order)
 

@@ -24,6 +24,7 @@ EXPORTS = [
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
     "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model", "qtn_energy_grad_noalloc",
+    "qtn_time_wide_sweep",
     "qtn_net_free",
 ]
 
@@ -60,7 +61,7 @@ class Info(C.Structure):
                 ("bwd_bytes", C.c_double), ("fwd_flops", C.c_double), ("ws_fwd", C.c_size_t),
                 ("ws_grad", C.c_size_t), ("n_lds_cones", C.c_int32), ("lds_window", C.c_int32),
                 ("n_recomputed", C.c_int64), ("rec_bytes", C.c_double), ("arena_keep_all", C.c_size_t),
-                ("n_steps", C.c_int64)]
+                ("n_steps", C.c_int64), ("fwd_bytes_bucket", C.c_double), ("bwd_bytes_bucket", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -106,6 +107,8 @@ def lib() -> C.CDLL:
         "qtn_amplitude": (I32, [P, I32, P, SZ, P, P, P]),
         "qtn_cost_model": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost)]),
         "qtn_energy_grad_noalloc": (I32, [P, I32, P, P, P, P, P]),
+        "qtn_time_wide_sweep": (I32, [P, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64),
+                                      C.POINTER(I64)]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

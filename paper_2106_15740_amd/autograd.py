@@ -18,14 +18,16 @@ class QaoaEnergy(torch.autograd.Function):
     def forward(ctx, gamma: torch.Tensor, beta: torch.Tensor, net: QaoaNet, mode: str = "batched"):
         net.set_params(gamma.detach().cpu().double().numpy(), beta.detach().cpu().double().numpy())
         e, dg, db = net.energy_grad(mode)
-        ctx.save_for_backward(torch.from_numpy(dg).to(gamma.dtype), torch.from_numpy(db).to(beta.dtype))
-        return torch.tensor(e, dtype=torch.float64)
+        # outputs and saved gradients live where the angles do
+        ctx.save_for_backward(torch.from_numpy(dg).to(device=gamma.device, dtype=gamma.dtype),
+                              torch.from_numpy(db).to(device=beta.device, dtype=beta.dtype))
+        return torch.tensor(e, dtype=torch.float64, device=gamma.device)
 
     @staticmethod
     def backward(ctx, grad_e):
         dg, db = ctx.saved_tensors
-        g = grad_e.to(torch.float64).cpu()
-        return g * dg, g * db, None, None
+        return grad_e.to(device=dg.device, dtype=dg.dtype) * dg, grad_e.to(device=db.device, dtype=db.dtype) * db, \
+            None, None
 
 
 def qaoa_energy(gamma: torch.Tensor, beta: torch.Tensor, net: QaoaNet, mode: str = "batched") -> torch.Tensor:

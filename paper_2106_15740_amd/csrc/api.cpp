@@ -689,6 +689,13 @@ qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
     out->fwd_bytes += C.fwd_bytes_alg;
     out->bwd_bytes += C.bwd_bytes_alg;
     out->fwd_flops += C.fwd_flops;
+    for (const Bucket& B : C.plain) {
+      double in = 0;
+      for (uint32_t m : B.in_mask) in += std::ldexp(1.0, __builtin_popcount(m));
+      const double o = std::ldexp(1.0, B.out_rank());
+      out->fwd_bytes_bucket += (in + o) * n->elem;
+      out->bwd_bytes_bucket += (o + 2 * in) * n->elem;
+    }
     out->n_ops_fwd += n->P.cone_fwd_hi[c] + 1 - n->P.cone_fwd_lo[c];
     out->n_ops_grad += (n->P.cone_fwd_hi[c] - n->P.cone_fwd_lo[c]) + (n->P.cone_adj_hi[c] - n->P.cone_adj_lo[c]);
   }
@@ -901,6 +908,100 @@ qtn_status qtn_time_wide_ops(qtn_net* n, int32_t with_grad, int32_t min_width, v
   return QTN_OK;
 }
 
+qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width, void* ws, size_t ws_bytes,
+                               void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out,
+                               int64_t* n_items_out) {
+  qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
+  if (s != QTN_OK) return s;
+  if (reps < 1) return fail(QTN_EINVAL, "reps must be >= 1");
+  const bool grad = with_grad != 0;
+  // the ops of buckets with output rank >= min_width, in each cone's program
+  // order, as a queue of their own
+  std::vector<char> in_prog(n->P.ops.size(), 0);
+  for (size_t c = 0; c < n->P.cones.size(); ++c) {
+    for (int32_t o = n->P.cone_fwd_lo[c]; o < n->P.cone_fwd_hi[c]; ++o) in_prog[o] = 1;
+    if (grad)
+      for (int32_t o = n->P.cone_adj_lo[c]; o < n->P.cone_adj_hi[c]; ++o) in_prog[o] = 1;
+  }
+  double bytes = 0;
+  int64_t cnt = 0;
+  auto keep = [&](int32_t o) {
+    const OpDesc& d = n->P.ops[o];
+    return in_prog[o] && (d.kind == OP_CONTRACT || d.kind == OP_ADJOINT) && d.nbits - 1 >= min_width;
+  };
+  for (size_t o = 0; o < n->P.ops.size(); ++o) {
+    if (!keep((int32_t)o)) continue;
+    const OpDesc& d = n->P.ops[o];
+    double b = d.kind == OP_CONTRACT ? std::ldexp(1.0, __builtin_popcount(d.out_mask)) : 0.0;
+    for (int i = 0; i < d.n_in; ++i)
+      b += std::ldexp(1.0, __builtin_popcount(d.in_mask[i])) * (((d.adj_sel >> i) & 1u) ? 2 : 1);
+    bytes += b * n->elem;
+    ++cnt;
+  }
+  Queue q;
+  try {
+    build_queue(n->P, grad, keep, q);
+  } catch (const std::bad_alloc&) {
+    return fail(QTN_ENOMEM, "host allocation failed");
+  }
+  if (bytes_out) *bytes_out = bytes;
+  if (n_ops_out) *n_ops_out = cnt;
+  if (n_items_out) *n_items_out = (int64_t)q.items.size();
+  if (ms_out) *ms_out = 0;
+  if (q.items.empty()) return QTN_OK;
+  if (q.init.size() > (size_t)std::max(n->prog[0].n_nodes, n->prog[1].n_nodes))
+    return fail(QTN_EUNSUPPORTED, "sub-sweep has more queue nodes than the workspace holds");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(hipSetDevice(n->ctx->device));
+  DevProg pg;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    (void)hipFree(pg.items);
+    (void)hipFree(pg.succ);
+    (void)hipFree(pg.init);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  hipError_t e = upload(&pg.items, q.items);
+  if (e == hipSuccess) e = upload(&pg.succ, q.succ);
+  if (e == hipSuccess) e = upload(&pg.init, q.init);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    release();
+    return fail(QTN_EDEVICE, std::string("sub-sweep setup: ") + hipGetErrorString(e));
+  }
+  const WsLayout L = ws_layout(n, grad);
+  char* w = static_cast<char*>(ws);
+  Env env = make_env(n, w, L);
+  int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
+  const int n_items = (int)q.items.size();
+  const int grid = std::max(1, std::min<int>(n->grid, n_items));
+  const size_t lds_bytes = (size_t)n->P.lds_elems * n->elem;
+  double tot = 0;
+  int32_t flag = 0;
+  (void)hipGetLastError();
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // the first run warms up
+    e = launch_reset(ctl, pg.init, (int)q.init.size(), st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess)
+      e = launch_persistent(n->c128, n->has_wide, n->max_nin, n->d_ops, pg.items, n_items, pg.succ, ctl, env,
+                            n->P.tune.threads, grid, lds_bytes, kSpinLimit, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) e = hipMemcpy(&flag, ctl + 1, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && flag) break;
+    if (r > 0) tot += ms;
+  }
+  release();
+  if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("sub-sweep: ") + hipGetErrorString(e));
+  if (flag) return fail(QTN_EDEVICE, "sub-sweep gave up waiting on a dependency");
+  if (ms_out) *ms_out = tot / reps;
+  return QTN_OK;
+}
+
 qtn_status qtn_time_persistent(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes, void* stream,
                                int32_t reps, double* ms_out) {
   qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
@@ -974,9 +1075,12 @@ qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* strea
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
-  hipError_t e = launch_copy(src, dst, n16, st);
+  // eight 256-thread workgroups per compute unit: 32 wavefronts per CU,
+  // each thread with four 16-byte loads in flight
+  const int grid = 8 * ctx->n_cu;
+  hipError_t e = launch_copy(src, dst, n16, grid, st);
   if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, n16, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, n16, grid, st);
   if (e == hipSuccess) e = hipEventRecord(e1, st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0;

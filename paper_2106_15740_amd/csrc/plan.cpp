@@ -1740,13 +1740,23 @@ std::string validate_plan(const Plan& P) {
 }
 
 void build_items(Plan& P, bool grad) {
+  Queue q;
+  build_queue(P, grad, nullptr, q);
+  (grad ? P.items_grad : P.items_fwd) = std::move(q.items);
+  (grad ? P.node_init_grad : P.node_init_fwd) = std::move(q.init);
+  (grad ? P.succ_grad : P.succ_fwd) = std::move(q.succ);
+}
+
+void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& keep, Queue& q) {
   const TuneParams& T = P.tune;
-  auto& items = grad ? P.items_grad : P.items_fwd;
-  auto& init = grad ? P.node_init_grad : P.node_init_fwd;
-  auto& succ = grad ? P.succ_grad : P.succ_fwd;
+  auto& items = q.items;
+  auto& init = q.init;
+  auto& succ = q.succ;
   items.clear();
   init.clear();
   succ.clear();
+  // a filtered queue runs a subset of ops from global memory (never LDS-resident)
+  const bool use_lds = !keep;
   // a segment is up to two physical op ranges run in sequence (a cone's
   // gradient program is its forward range followed by its adjoint range)
   struct Seg {
@@ -1776,6 +1786,11 @@ void build_items(Plan& P, bool grad) {
       bool open_here = false;
       for (int32_t o = rg.first; o < rg.second; ++o) {
         const OpDesc& d = P.ops[o];
+        if (keep && !keep(o)) {
+          // a skipped op ends the open narrow range here
+          open_here = false;
+          continue;
+        }
         const bool contract = d.kind == OP_CONTRACT || d.kind == OP_ADJOINT;
         const bool wide = contract && d.nbits > T.seq_max_bits;
         if (wide) {
@@ -1900,7 +1915,7 @@ void build_items(Plan& P, bool grad) {
       const int32_t wait_node = r.seg > 0 ? node : -1;
       if (!g.wide) {
         // a cone that runs LDS-resident is one narrow segment
-        const bool lds = !P.cone_lds.empty() && P.cone_lds[r.cone] && segs[r.cone].size() == 1;
+        const bool lds = use_lds && !P.cone_lds.empty() && P.cone_lds[r.cone] && segs[r.cone].size() == 1;
         const int32_t cp = lds ? P.cone_copyin[r.cone] : -1;
         items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, cp, {0, 0}});
       } else {

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -166,6 +167,14 @@ std::string build_programs(Plan& P, int elem_bytes);
 // Persistent-queue items for the forward (grad = false) or forward + adjoint
 // program; items are in topological order.
 void build_items(Plan& P, bool grad);
+// The same queue construction into q; with `keep`, only the ops it accepts
+// (chained per cone in program order, never LDS-resident): a sub-sweep for
+// measurement.
+struct Queue {
+  std::vector<QItem> items;
+  std::vector<int32_t> init, succ;
+};
+void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& keep, Queue& q);
 // Plan invariants; "" if all hold, else the first violation.
 std::string validate_plan(const Plan& P);
 

@@ -377,3 +377,38 @@ def test_variant_network_sizes_closed_form():
         assert variants.counts(n, edges, p, "diagonal") == (2 * n + p * (2 * m + 2 * n), 3 * n + p * (3 * m + 3 * n))
         assert variants.counts(n, edges, p, "zz") == (2 * n + p * (2 * m + n), 3 * n + p * (m + n))
         assert variants.counts(n, edges, p, "diagonal_zz") == (2 * n + p * n, 3 * n + p * (m + n))
+
+
+def test_full_size_golden_files_match_the_oracle():
+    """The stored full-size expected values (tests/golden/make_full_size.py)
+    are the oracle's: a few entries recomputed here, the radius-3 tree-like
+    edges of the p = 3 file share one value (their light cones are isomorphic
+    trees), and every stored <ZZ> is real and within [-1, 1]."""
+    import os
+
+    from oracle import tn
+    from workloads import workload
+
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+    def rows(name):
+        with open(os.path.join(golden, f"full_size_{name}.txt")) as fh:
+            return [l.split() for l in fh if not l.startswith("#")]
+
+    for name, picks in (("p3_n244", (0, 101, 365)), ("p4_n100", (7,)), ("p5_n1000", (3,))):
+        w = workload(name)
+        r = rows(name)
+        assert len(r) == len(w.edges)
+        for i in picks:
+            z = tn.zz_edge(w.n, w.edges, w.gamma, w.beta, *w.edges[i])
+            assert abs(z - (float(r[i][4]) + 1j * float(r[i][5]))) < 1e-12
+        vals = np.array([float(x[4]) for x in r])
+        assert np.all(np.abs(vals) <= 1) and max(abs(float(x[5])) for x in r) < 1e-12
+    r = rows("p3_n244")
+    w = workload("p3_n244")
+    gates = tn.circuit(w.n, w.edges, w.p)
+    nq = [len({q for _, _, qs in tn.prune(gates, j, k) for q in qs} | {j, k}) for j, k in w.edges]
+    tree = [i for i, q in enumerate(nq) if q == 2 * (2 ** (w.p + 1) - 1)]  # 30 distinct qubits: a tree
+    assert len(tree) > 10
+    vals = np.array([float(r[i][4]) for i in tree])
+    assert np.ptp(vals) < 1e-12
