@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+P5_TIMED_MAX_WIDTH = 23  # widest oracle contraction timed in the p = 5 CPU extrapolation
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_persistent_kernel_p3_n244.json")
 
 
@@ -139,20 +140,28 @@ def cpu_baseline(w, budget_s: float = 12.0):
     for j, k in w2.edges:
         ball.zz_edge(w2.n, w2.edges, w2.gamma, w2.beta, j, k)
     sv_times["p2_n60_ball_energy_s"] = time.perf_counter() - t
-    # p = 5, N = 1000: one forward contraction per worker on a seeded sample of
-    # edges, extrapolated to energy + gradient over all 1500 edges
-    w5 = wl("p5_n1000")
-    o5 = np.random.default_rng(1).permutation(len(w5.edges))[:cores]
-    a5 = [(w5.n, w5.edges, w5.gamma, w5.beta, w5.edges[int(e)]) for e in o5]
+    # p = 5, N = 1000: the oracle's own contraction width of every edge (its
+    # network and min-fill order, no contraction), one timed contraction of the
+    # first edge of each width up to P5_TIMED_MAX_WIDTH, twice the time per
+    # width above it (memory and work double per index), extrapolated to energy
+    # + gradient (4p + 1 contractions) over all 1500 edges on `cores` cores
     import concurrent.futures as cf
     import multiprocessing as mp
 
+    w5 = wl("p5_n1000")
+    a5 = [(w5.n, w5.edges, w5.gamma, w5.beta, e) for e in w5.edges]
     t = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
-        times = list(ex.map(_oracle_edge_fwd_timed, a5))
+        widths = list(ex.map(_oracle_edge_width, a5, chunksize=8))
+        classes = sorted(set(widths))
+        timed_w = [c for c in classes if c <= P5_TIMED_MAX_WIDTH]
+        picks = [a5[widths.index(c)] for c in timed_w]
+        times = dict(zip(timed_w, ex.map(_oracle_edge_fwd_timed, picks)))
     dt5 = time.perf_counter() - t
-    per_edge_fwd_s = float(np.mean(times))  # core-seconds per forward contraction
-    p5_sweep_s = per_edge_fwd_s * (4 * w5.p + 1) * len(w5.edges) / cores
+    top = max(timed_w)
+    per_w = {c: times[c] if c in times else times[top] * 2.0 ** (c - top) for c in classes}
+    core_s = sum(per_w[c] for c in widths) * (4 * w5.p + 1)
+    p5_sweep_s = core_s / cores
     return {"value": done / dt, "unit": "edge light-cones/s", "cores": cores, "kind": "oracle",
             "os_cpu_count": os.cpu_count(),
             "cores_note": "one worker process per CPU this process may use, capped at 16 (one GPU's share of the "
@@ -171,15 +180,25 @@ def cpu_baseline(w, budget_s: float = 12.0):
             "statevector_s": sv_times,
             "p5_n1000_extrapolated": {
                 "sweep_s": p5_sweep_s, "edge_light_cones_per_s": len(w5.edges) / p5_sweep_s,
-                "sample": f"{len(a5)} seeded edges contracted once each (complex128, {cores} processes, {dt5:.1f} s): "
-                          f"{per_edge_fwd_s:.2f} core-s per contraction, times {4 * w5.p + 1} contractions per edge "
-                          f"and {len(w5.edges)} edges over {cores} cores"}}
+                "seconds_per_contraction_by_oracle_width": {str(c): per_w[c] for c in classes},
+                "edges_by_oracle_width": {str(c): widths.count(c) for c in classes},
+                "sample": f"the oracle's width of all {len(w5.edges)} edges; one complex128 contraction timed per "
+                          f"width {min(timed_w)}..{top}, 2x per width above {top} (widths up to {max(classes)}); "
+                          f"times {4 * w5.p + 1} contractions per edge over {cores} cores ({dt5:.1f} s of "
+                          f"measurement): an extrapolation, not a run"}}
 
 
 def _oracle_edge_fwd(n, edges, gamma, beta, edge):
     from oracle import tn
 
     return tn.zz_edge(n, edges, gamma, beta, *edge)
+
+
+def _oracle_edge_width(a):
+    from oracle import tn
+
+    n, edges, gamma, beta, edge = a
+    return tn.min_fill_order(tn.network(n, edges, gamma, beta, *edge))[1]
 
 
 def _oracle_edge_fwd_timed(a):

@@ -303,8 +303,10 @@ qtn_status qtn_cost_model(int32_t n_vertices, int32_t n_edges, const int32_t* ed
 /* Achievable-bandwidth reference: the library's plain copy kernel copies the
  * first half of the caller's device buffer `buf` (`bytes` long, 16-byte
  * aligned) onto its second half, `reps` times on `stream` after one warm-up,
- * between HIP events.  *gbps_out = (bytes read + bytes written) per copy /
- * average device time.  The buffer's contents are overwritten.  QTN_EINVAL for
+ * between HIP events, for each of twelve launch shapes (1, 2 or 4 16-byte
+ * loads in flight per thread; 4, 8, 16 or 32 workgroups of 256 threads per
+ * compute unit).  *gbps_out = the best shape's (bytes read + bytes written)
+ * per copy / average device time.  The buffer's contents are overwritten.  QTN_EINVAL for
  * a null buffer, fewer than 32 bytes or reps < 1. */
 qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* stream, int32_t reps, double* gbps_out);
 

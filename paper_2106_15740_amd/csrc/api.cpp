@@ -1075,20 +1075,27 @@ qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* strea
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
-  // eight 256-thread workgroups per compute unit: 32 wavefronts per CU,
-  // each thread with four 16-byte loads in flight
-  const int grid = 8 * ctx->n_cu;
-  hipError_t e = launch_copy(src, dst, n16, grid, st);
-  if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, n16, grid, st);
-  if (e == hipSuccess) e = hipEventRecord(e1, st);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
-  float ms = 0;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  // the best of a few launch shapes: 1, 2 or 4 loads in flight per thread,
+  // 4 to 32 256-thread workgroups per compute unit
+  double best = 0;
+  hipError_t e = hipSuccess;
+  for (int unroll : {1, 2, 4})
+    for (int per_cu : {4, 8, 16, 32}) {
+      const int grid = per_cu * ctx->n_cu;
+      e = launch_copy(src, dst, n16, grid, unroll, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, n16, grid, unroll, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      best = std::max(best, 2.0 * (double)(n16 * 16) * reps / (ms * 1e-3) / 1e9);
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("copy kernel: ") + hipGetErrorString(e));
-  if (gbps_out) *gbps_out = 2.0 * (double)(n16 * 16) * reps / (ms * 1e-3) / 1e9;
+  if (gbps_out) *gbps_out = best;
   return QTN_OK;
 }
 

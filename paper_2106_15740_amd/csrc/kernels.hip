@@ -169,17 +169,18 @@ __global__ void __launch_bounds__(256) small_copy_kernel(const uint32_t* __restr
 
 // Plain device copy (16-byte words, grid-stride): the achievable-bandwidth
 // reference the contraction kernels are compared against.  Each thread keeps
-// four 16-byte loads in flight (issued before the first store); consecutive
+// U 16-byte loads in flight (issued before the first store); consecutive
 // threads touch consecutive words, so every load and store is coalesced.
+template <int U>
 __global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    uint4 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = src[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < U; ++k) dst[i + k * stride] = v[k];
   }
   for (; i < n; i += stride) dst[i] = src[i];
 }
@@ -285,10 +286,17 @@ hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const void* src, void* dst, size_t n16, int grid, hipStream_t st) {
+hipError_t launch_copy(const void* src, void* dst, size_t n16, int grid, int unroll, hipStream_t st) {
   if (n16 == 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_kernel, dim3(std::max(1, grid)), dim3(256), 0, st, reinterpret_cast<const uint4*>(src),
-                     reinterpret_cast<uint4*>(dst), n16);
+  const dim3 g(std::max(1, grid));
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  if (unroll >= 4)
+    hipLaunchKernelGGL(copy_kernel<4>, g, dim3(256), 0, st, s, d, n16);
+  else if (unroll == 2)
+    hipLaunchKernelGGL(copy_kernel<2>, g, dim3(256), 0, st, s, d, n16);
+  else
+    hipLaunchKernelGGL(copy_kernel<1>, g, dim3(256), 0, st, s, d, n16);
   return hipGetLastError();
 }
 

@@ -29,8 +29,8 @@ hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const En
 // either side may be mapped pinned host memory
 hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 // n16 16-byte words from src to dst (non-overlapping), `grid` workgroups of
-// 256 threads
-hipError_t launch_copy(const void* src, void* dst, size_t n16, int grid, hipStream_t st);
+// 256 threads, `unroll` (1, 2 or 4) loads in flight per thread
+hipError_t launch_copy(const void* src, void* dst, size_t n16, int grid, int unroll, hipStream_t st);
 hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStream_t st);
 // wide: some op carries F_WIDE; max_nin: the largest input count of any
 // contraction op in the items; lds_bytes: dynamic LDS window of LDS-resident
