@@ -61,7 +61,8 @@ typedef struct {
   int32_t tile_blocks;  /* blocks of a split bucket handled by one queue item (power of two) */
   int32_t loop_cap;     /* summed bits looped inside a thread before partial sums go to atomics */
   int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
-  int32_t lds_kb;       /* LDS window (KiB) for light cones that run LDS-resident in the batched sweep (0: none) */
+  int32_t lds_kb;       /* LDS window (KiB, <= 128) for light cones that run LDS-resident in the batched sweep: leaf
+                           tables, intermediates and adjoints of such a cone never leave LDS (0: none) */
   int32_t par_bits;     /* a split bucket aims at >= 2^par_bits threads before summing in per-thread loops (8..24) */
   int32_t merge_bits;   /* a bucket is merged into its consumer while the merged step's union has <= merge_bits
                            bits (0: one step per bucket; at most 16) */
@@ -72,6 +73,8 @@ typedef struct {
                            union (output adjoint and inputs read once) where the loop bits can be chosen so
                            that no output needs atomics per step; 2: also the other buckets, summed tile by tile
                            in LDS (slower on MI355X: LDS atomics); 0: one pass per input adjoint */
+  int32_t lds_threads;  /* workgroup size (64, 128 or 256) of the kernel that runs the light cones whose whole
+                           program fits the LDS window (lds_kb), one workgroup per cone */
 } qtn_tuning;
 
 typedef struct {
@@ -82,7 +85,8 @@ typedef struct {
   int64_t n_buckets;        /* total buckets over all cones (one per index) */
   int64_t n_ops_fwd;        /* device ops of the forward program */
   int64_t n_ops_grad;       /* device ops of the forward + adjoint program */
-  int64_t n_items_fwd, n_items_grad;  /* persistent-queue items */
+  int64_t n_items_fwd, n_items_grad;  /* work items of the batched sweep: persistent-queue items plus one per
+                                         LDS-resident light cone */
   double fwd_bytes;         /* algorithmic bytes of one forward sweep (each input read once, output written once) */
   double bwd_bytes;         /* algorithmic bytes of the adjoint sweep */
   double fwd_flops;         /* complex multiply = 6, add = 2 */
@@ -209,9 +213,10 @@ qtn_status qtn_get_tuning(const qtn_net* net, qtn_tuning* out);
 qtn_status qtn_set_tuning(qtn_net* net, const qtn_tuning* t);
 
 /* Project-written autotuner: times the batched sweep (with_grad as given) on
- * `stream` by coordinate descent over three groups (workgroup size and lane
+ * `stream` by coordinate descent over four groups (workgroup size and lane
  * cap; split thresholds seq_max_bits and tile_blocks; merge_bits and
- * merge_lam_bits), keeps the fastest setting and returns it in *best
+ * merge_lam_bits; lds_threads and lds_kb), keeps the fastest setting and
+ * returns it in *best
  * (nullable).  Needs qtn_set_params first and a workspace as for the sweep;
  * settings whose workspace would not fit in ws_bytes are skipped. */
 qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
@@ -234,8 +239,10 @@ qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width,
                              void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out);
 
 /* In-sweep rate of the wide buckets: the contraction ops of buckets whose
- * output rank is >= min_width (forward and, with with_grad, adjoint ops) as a
- * queue of their own -- chained per light cone in program order, split into
+ * output rank is in [min_width, max_width] (max_width <= 0: no upper bound)
+ * and whose kind is in `kinds` (bit 0: forward contractions, bit 1: adjoint
+ * ops that compute one input's adjoint, bit 2: fused adjoint ops; 0: all),
+ * forward and, with with_grad, adjoint ops, as a queue of their own -- chained per light cone in program order, split into
  * the same tiles and list-scheduled as in the batched sweep -- run by one
  * launch of the persistent kernel, `reps` times (after one warm-up) between
  * HIP events on `stream`.  Reads the tensors left in `workspace` by the last
@@ -244,9 +251,9 @@ qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width,
  * (each input read once, output written once), the average device time, and
  * the op and queue-item counts.  Allocates (and frees) the sub-queue's device
  * copy.  QTN_EDEVICE if a dependency wait gave up. */
-qtn_status qtn_time_wide_sweep(qtn_net* net, int32_t with_grad, int32_t min_width, void* workspace,
-                               size_t ws_bytes, void* stream, int32_t reps, double* bytes_out, double* ms_out,
-                               int64_t* n_ops_out, int64_t* n_items_out);
+qtn_status qtn_time_wide_sweep(qtn_net* net, int32_t with_grad, int32_t min_width, int32_t max_width, int32_t kinds,
+                               void* workspace, size_t ws_bytes, void* stream, int32_t reps, double* bytes_out,
+                               double* ms_out, int64_t* n_ops_out, int64_t* n_items_out);
 
 /* Device time of the persistent kernel alone: `reps` batched sweeps (after
  * one warm-up) are enqueued on `stream` without graph capture, each with HIP

@@ -40,7 +40,7 @@ class Tuning(C.Structure):
                 ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32), ("grid", C.c_int32),
                 ("lds_kb", C.c_int32), ("par_bits", C.c_int32), ("merge_bits", C.c_int32),
                 ("merge_lam_bits", C.c_int32), ("lane_low", C.c_int32),
-                ("fuse_adjoint", C.c_int32)]
+                ("fuse_adjoint", C.c_int32), ("lds_threads", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -107,8 +107,8 @@ def lib() -> C.CDLL:
         "qtn_amplitude": (I32, [P, I32, P, SZ, P, P, P]),
         "qtn_cost_model": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost)]),
         "qtn_energy_grad_noalloc": (I32, [P, I32, P, P, P, P, P]),
-        "qtn_time_wide_sweep": (I32, [P, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64),
-                                      C.POINTER(I64)]),
+        "qtn_time_wide_sweep": (I32, [P, I32, I32, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D),
+                                      C.POINTER(I64), C.POINTER(I64)]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

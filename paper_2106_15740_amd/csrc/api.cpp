@@ -53,7 +53,8 @@ struct DevProg {
   QItem* items = nullptr;
   int32_t* succ = nullptr;
   int32_t* init = nullptr;
-  int32_t n_items = 0, n_nodes = 0;
+  int32_t* small_items = nullptr;  // (lo, hi) per LDS-resident cone
+  int32_t n_items = 0, n_nodes = 0, n_small = 0;
 };
 
 struct GraphCache {
@@ -71,6 +72,7 @@ struct qtn_net {
   // device plan
   OpDesc* d_ops = nullptr;
   LeafRef* d_leafrefs = nullptr;
+  SmallOp* d_small = nullptr;  // LDS-resident programs
   DevProg prog[2];
   void* d_leafvals = nullptr;  // vals then dvals, element type
   // host staging (pinned)
@@ -127,10 +129,13 @@ size_t fin_copy_bytes(const qtn_net* n) {
 void free_device_plan(qtn_net* n) {
   (void)hipFree(n->d_ops);
   (void)hipFree(n->d_leafrefs);
+  (void)hipFree(n->d_small);
+  n->d_small = nullptr;
   for (auto& pg : n->prog) {
     (void)hipFree(pg.items);
     (void)hipFree(pg.succ);
     (void)hipFree(pg.init);
+    (void)hipFree(pg.small_items);
     pg = DevProg();
   }
   n->d_ops = nullptr;
@@ -174,16 +179,20 @@ qtn_status rebuild_programs(qtn_net* n) {
   free_device_plan(n);
   HIPCHECK(upload(&n->d_ops, n->P.ops));
   HIPCHECK(upload(&n->d_leafrefs, n->P.leafrefs));
+  HIPCHECK(upload(&n->d_small, n->P.small));
   for (int g = 0; g < 2; ++g) {
     DevProg& pg = n->prog[g];
     const auto& items = g ? n->P.items_grad : n->P.items_fwd;
     const auto& succ = g ? n->P.succ_grad : n->P.succ_fwd;
     const auto& init = g ? n->P.node_init_grad : n->P.node_init_fwd;
+    const auto& small_items = g ? n->P.small_items_grad : n->P.small_items_fwd;
     HIPCHECK(upload(&pg.items, items));
     HIPCHECK(upload(&pg.succ, succ));
     HIPCHECK(upload(&pg.init, init));
+    HIPCHECK(upload(&pg.small_items, small_items));
     pg.n_items = (int32_t)items.size();
     pg.n_nodes = (int32_t)init.size();
+    pg.n_small = (int32_t)(small_items.size() / 2);
   }
   return QTN_OK;
 }
@@ -213,13 +222,20 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
   // kernel launches report through hipGetLastError: drop any error left
   // behind by unrelated earlier calls on this thread
   (void)hipGetLastError();
-  HIPCHECK(launch_small_copy(n->dh_leafvals, n->d_leafvals, n->leaf_bytes, st));
   const TuneParams& T = n->P.tune;
   DevProg& pg = n->prog[grad ? 1 : 0];
   int32_t* ctl = reinterpret_cast<int32_t*>(w + L.ctl_off);
-  // leaf-product tables; in the batched form the same launch resets the queue
-  HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, n->P.leaf_hi, env, st, mode == QTN_BATCHED ? ctl : nullptr,
-                        pg.init, pg.n_nodes));
+  const bool batched = mode == QTN_BATCHED;
+  // leaf-product tables; the batched form also resets the queue, in the leaf
+  // launch or, without one, in the copy of the leaf values
+  const int32_t leaf_hi = n->P.leaf_hi;
+  const int32_t lgrad_hi = n->P.lgrad_hi;
+  const bool leaf_launch = leaf_hi > n->P.leaf_lo;
+  HIPCHECK(launch_small_copy(n->dh_leafvals, n->d_leafvals, n->leaf_bytes, st,
+                             batched && !leaf_launch ? ctl : nullptr, pg.init, pg.n_nodes));
+  if (leaf_launch)
+    HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, leaf_hi, env, st, batched ? ctl : nullptr, pg.init,
+                          pg.n_nodes));
   if (mode == QTN_PLAIN) {
     for (size_t c = 0; c < n->P.cones.size(); ++c) {
       auto run = [&](int32_t lo, int32_t hi) -> qtn_status {
@@ -238,14 +254,19 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
       }
     }
   } else {
+    // the LDS-resident cones (one workgroup each), then the work queue of
+    // the others; the two are independent
     const int grid = std::max(1, std::min<int>(n->grid, std::max(1, pg.n_items)));
     const size_t lds_bytes = (size_t)n->P.lds_elems * n->elem;
     if (pk0) HIPCHECK(hipEventRecord(pk0, st));
-    HIPCHECK(launch_persistent(n->c128, n->has_wide, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env,
-                               T.threads, grid, lds_bytes, kSpinLimit, st));
+    HIPCHECK(launch_small(n->c128, n->d_small, pg.small_items, pg.n_small, env, T.lds_threads, lds_bytes, st));
+    if (pg.n_items > 0)
+      HIPCHECK(launch_persistent(n->c128, n->has_wide, n->max_nin, n->d_ops, pg.items, pg.n_items, pg.succ, ctl, env,
+                                 T.threads, grid, lds_bytes, kSpinLimit, st));
     if (pk1) HIPCHECK(hipEventRecord(pk1, st));
   }
-  if (grad) HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, n->P.lgrad_hi, env, st));
+  if (grad && lgrad_hi > n->P.lgrad_lo)
+    HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, lgrad_hi, env, st));
   // E, dE/dtheta straight into the mapped host buffer, followed (at the
   // workspace's ctl offset) by the queue head and the persistent kernel's
   // error flag
@@ -699,8 +720,8 @@ qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
     out->n_ops_fwd += n->P.cone_fwd_hi[c] + 1 - n->P.cone_fwd_lo[c];
     out->n_ops_grad += (n->P.cone_fwd_hi[c] - n->P.cone_fwd_lo[c]) + (n->P.cone_adj_hi[c] - n->P.cone_adj_lo[c]);
   }
-  out->n_items_fwd = (int64_t)n->P.items_fwd.size();
-  out->n_items_grad = (int64_t)n->P.items_grad.size();
+  out->n_items_fwd = (int64_t)(n->P.items_fwd.size() + n->P.small_items_fwd.size() / 2);
+  out->n_items_grad = (int64_t)(n->P.items_grad.size() + n->P.small_items_grad.size() / 2);
   out->ws_fwd = ws_layout(n, false).total;
   out->ws_grad = ws_layout(n, true).total;
   for (char l : n->P.cone_lds) out->n_lds_cones += l ? 1 : 0;
@@ -743,6 +764,7 @@ qtn_status qtn_get_tuning(const qtn_net* n, qtn_tuning* out) {
   out->merge_lam_bits = n->P.tune.merge_lam_bits;
   out->lane_low = n->P.tune.lane_low;
   out->fuse_adjoint = n->P.tune.fuse_adjoint;
+  out->lds_threads = n->P.tune.lds_threads;
   return QTN_OK;
 }
 
@@ -762,9 +784,12 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->merge_lam_bits < 0 || t->merge_lam_bits > 16) return fail(QTN_EINVAL, "merge_lam_bits must be in 0..16");
   if (t->lane_low != 0 && t->lane_low != 1) return fail(QTN_EINVAL, "lane_low must be 0 or 1");
   if (t->fuse_adjoint < 0 || t->fuse_adjoint > 2) return fail(QTN_EINVAL, "fuse_adjoint must be 0, 1 or 2");
+  if (t->lds_threads != 64 && t->lds_threads != 128 && t->lds_threads != 256)
+    return fail(QTN_EINVAL, "lds_threads must be 64, 128 or 256");
   n->P.tune.threads = th;
   n->P.tune.lane_low = t->lane_low;
   n->P.tune.fuse_adjoint = t->fuse_adjoint;
+  n->P.tune.lds_threads = t->lds_threads;
   n->P.tune.par_bits = t->par_bits;
   n->P.tune.merge_bits = t->merge_bits;
   n->P.tune.merge_lam_bits = t->merge_lam_bits;
@@ -810,11 +835,12 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
     *ms_out = ms;
     return QTN_OK;
   };
-  // coordinate descent over three groups of parameters: workgroup shape,
-  // split thresholds of wide buckets, merging of small buckets
+  // coordinate descent over four groups of parameters: workgroup shape,
+  // split thresholds of wide buckets, merging of small buckets, the kernel of
+  // the LDS-resident cones
   double best_ms = 1e300;
   qtn_tuning best = base;
-  for (int stage = 0; stage < 3 && s == QTN_OK; ++stage) {
+  for (int stage = 0; stage < 4 && s == QTN_OK; ++stage) {
     std::vector<qtn_tuning> cand;
     const qtn_tuning b0 = best;
     if (stage == 0) {
@@ -833,6 +859,15 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
           qtn_tuning t = b0;
           t.seq_max_bits = sq;
           t.tile_blocks = tb;
+          cand.push_back(t);
+        }
+    } else if (stage == 3) {
+      // LDS-resident cones: workgroup size and LDS window cap
+      for (int lt : {128, 256})
+        for (int kb : {64, 96}) {
+          qtn_tuning t = b0;
+          t.lds_threads = lt;
+          t.lds_kb = kb;
           cand.push_back(t);
         }
     } else {
@@ -908,9 +943,9 @@ qtn_status qtn_time_wide_ops(qtn_net* n, int32_t with_grad, int32_t min_width, v
   return QTN_OK;
 }
 
-qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width, void* ws, size_t ws_bytes,
-                               void* stream, int32_t reps, double* bytes_out, double* ms_out, int64_t* n_ops_out,
-                               int64_t* n_items_out) {
+qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width, int32_t max_width, int32_t kinds,
+                               void* ws, size_t ws_bytes, void* stream, int32_t reps, double* bytes_out, double* ms_out,
+                               int64_t* n_ops_out, int64_t* n_items_out) {
   qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
   if (s != QTN_OK) return s;
   if (reps < 1) return fail(QTN_EINVAL, "reps must be >= 1");
@@ -925,9 +960,16 @@ qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width,
   }
   double bytes = 0;
   int64_t cnt = 0;
+  if (max_width <= 0) max_width = MAXBITS;
+  if (kinds == 0) kinds = 7;
   auto keep = [&](int32_t o) {
     const OpDesc& d = n->P.ops[o];
-    return in_prog[o] && (d.kind == OP_CONTRACT || d.kind == OP_ADJOINT) && d.nbits - 1 >= min_width;
+    if (!in_prog[o] || (d.kind != OP_CONTRACT && d.kind != OP_ADJOINT)) return false;
+    if (d.nbits - 1 < min_width || d.nbits - 1 > max_width) return false;
+    // forward op: input 0 holds the eliminated index; adjoint op: input 0 is
+    // the output adjoint, which lacks it
+    const int kind = d.kind == OP_ADJOINT ? 4 : ((d.in_mask[0] & 1u) ? 1 : 2);
+    return (kinds & kind) != 0;
   };
   for (size_t o = 0; o < n->P.ops.size(); ++o) {
     if (!keep((int32_t)o)) continue;

@@ -70,6 +70,19 @@ __device__ __forceinline__ double2 shfl_xor_c(double2 v, int m) {
   return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
 }
 
+// Parameter slot of a leaf kind inside a cone's result record: gamma_l at
+// 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+>, Z and <0|.
+__device__ __forceinline__ int theta_slot(int kind, int p) {
+  if (kind < 2 || kind >= 2 + 4 * p) return -1;
+  const int l = (kind - 2) >> 2, t = (kind - 2) & 3;
+  return t < 2 ? 2 + 2 * l : 2 + 2 * p + 2 * l;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
 // Element stride of union bit u inside a tensor whose union-bit mask is m.
 __device__ __forceinline__ uint32_t bit_stride(uint32_t m, uint32_t u) {
   return ((m >> u) & 1u) ? (1u << __popc(m & ((1u << u) - 1u))) : 0u;
@@ -96,10 +109,10 @@ struct RedBuf {
   E v[512 * 2];
 };
 
-template <typename R, int NIN, bool USE_LDS = false>
+template <typename R, int NIN>
 __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
                               int64_t blk_end, int64_t wg_rank, int64_t wg_count,
-                              RedBuf<typename CT<R>::E>* __restrict__ red, typename CT<R>::E* lds = nullptr) {
+                              RedBuf<typename CT<R>::E>* __restrict__ red) {
   using E = typename CT<R>::E;
   constexpr int MAXU = MaxU<R, NIN>::value;
   const int tid = threadIdx.x;
@@ -120,10 +133,7 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
 #pragma unroll
   for (int i = 0; i < NIN; ++i) {
     mask[i] = d.in_mask[i];
-    if constexpr (USE_LDS)
-      inp[i] = ((d.lds_mask >> i) & 1u) ? lds + d.lds_off[i] : arena + d.in_off[i];
-    else
-      inp[i] = arena + d.in_off[i];
+    inp[i] = arena + d.in_off[i];
     // lane offset: the strides of the lane bits are distinct powers of two
     uint32_t o = 0;
 #pragma unroll
@@ -143,11 +153,7 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
 #pragma unroll
   for (int i = 0; i < NIN; ++i) us0[i] = (MAXU > 1 && nu > 0) ? bit_stride(mask[i], d.zbit[nl]) : 0u;
   const uint32_t uo0 = (MAXU > 1 && nu > 0) ? bit_stride(out_mask, d.zbit[nl]) : 0u;
-  E* outp;
-  if constexpr (USE_LDS)
-    outp = ((d.lds_mask >> MAXIN) & 1u) ? lds + d.lds_off[MAXIN] : arena + d.out_off;
-  else
-    outp = arena + d.out_off;
+  E* outp = arena + d.out_off;
   const uint32_t lane_sum = d.lane_sum;
   const int zk0 = nl + nu;
   const int zb0 = nl + nu + nk;
@@ -935,19 +941,18 @@ __device__ __forceinline__ void exec_adjoint_any(const OpDesc& d, typename CT<R>
   }
 }
 
-template <typename R, int MAXNIN, bool USE_LDS>
+template <typename R, int MAXNIN>
 __device__ __forceinline__ void exec_contract_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
-                                                  int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red,
-                                                  typename CT<R>::E* lds) {
+                                                  int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
   switch (d.n_in) {
-    case 1: exec_contract<R, 1, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    case 2: exec_contract<R, 2, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    case 3: exec_contract<R, 3, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    case 4: if constexpr (MAXNIN >= 4) exec_contract<R, 4, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    case 5: if constexpr (MAXNIN >= 5) exec_contract<R, 5, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    case 6: if constexpr (MAXNIN >= 6) exec_contract<R, 6, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    case 7: if constexpr (MAXNIN >= 7) exec_contract<R, 7, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
-    default: if constexpr (MAXNIN >= 8) exec_contract<R, 8, USE_LDS>(d, arena, b0, b1, r, c, red, lds); break;
+    case 1: exec_contract<R, 1>(d, arena, b0, b1, r, c, red); break;
+    case 2: exec_contract<R, 2>(d, arena, b0, b1, r, c, red); break;
+    case 3: exec_contract<R, 3>(d, arena, b0, b1, r, c, red); break;
+    case 4: if constexpr (MAXNIN >= 4) exec_contract<R, 4>(d, arena, b0, b1, r, c, red); break;
+    case 5: if constexpr (MAXNIN >= 5) exec_contract<R, 5>(d, arena, b0, b1, r, c, red); break;
+    case 6: if constexpr (MAXNIN >= 6) exec_contract<R, 6>(d, arena, b0, b1, r, c, red); break;
+    case 7: if constexpr (MAXNIN >= 7) exec_contract<R, 7>(d, arena, b0, b1, r, c, red); break;
+    default: if constexpr (MAXNIN >= 8) exec_contract<R, 8>(d, arena, b0, b1, r, c, red); break;
   }
 }
 
@@ -971,14 +976,6 @@ __device__ __forceinline__ void exec_leaf(const OpDesc& d, typename CT<R>::E* ar
     }
     out[e] = p;
   }
-}
-
-// Parameter slot of a leaf kind inside a cone's result record: gamma_l at
-// 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+>, Z and <0|.
-__device__ __forceinline__ int theta_slot(int kind, int p) {
-  if (kind < 2 || kind >= 2 + 4 * p) return -1;
-  const int l = (kind - 2) >> 2, t = (kind - 2) & 3;
-  return t < 2 ? 2 + 2 * l : 2 + 2 * p + 2 * l;
 }
 
 template <typename R>
@@ -1038,14 +1035,11 @@ __device__ __forceinline__ void exec_leafgrad(const OpDesc& d, typename CT<R>::E
 // Cone value R = product of the scalar outputs; with F_GRAD also the seed
 // dR/dO_s = product of the other scalars, and zeroed gradient accumulators.
 template <typename R>
-__device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env,
-                                            typename CT<R>::E* lds = nullptr) {
+__device__ __forceinline__ void exec_result(const OpDesc& d, typename CT<R>::E* arena, const Env& env) {
   using E = typename CT<R>::E;
   double* res = env.res + (int64_t)d.cone * env.res_stride;
   const int ns = d.n_in;
-  auto at = [&](int i) -> E* {
-    return (lds && ((d.lds_mask >> i) & 1u)) ? lds + d.lds_off[i] : arena + d.in_off[i];
-  };
+  auto at = [&](int i) -> E* { return arena + d.in_off[i]; };
   if (threadIdx.x == 0) {
     double2 prod = make_double2(1, 0);
     for (int s = 0; s < ns; ++s) {
@@ -1083,7 +1077,8 @@ __device__ __forceinline__ void exec_zero(const OpDesc& d, typename CT<R>::E* ar
 
 // MAXNIN < 0: contraction ops have exactly -MAXNIN inputs (plain launches are
 // specialised per input count on the host); else up to MAXNIN inputs.
-template <typename R, int MAXNIN, bool USE_LDS = false, bool WIDE = false>
+// lds: LDS space for the tile sums of LDS-tiled adjoints.
+template <typename R, int MAXNIN, bool WIDE = false>
 __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t b0, int64_t b1, int64_t wg_rank,
                                         int64_t wg_count, RedBuf<typename CT<R>::E>* red,
                                         typename CT<R>::E* lds = nullptr) {
@@ -1091,7 +1086,7 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
   E* arena = reinterpret_cast<E*>(env.arena);
   switch (d.kind) {
     case OP_CONTRACT:
-      if constexpr (WIDE && !USE_LDS) {
+      if constexpr (WIDE) {
         if (d.flags & F_WIDE) {
           exec_wide_any<R>(d, arena, b0, b1, wg_rank, wg_count, red);
           break;
@@ -1100,20 +1095,395 @@ __device__ __forceinline__ void exec_op(const OpDesc& d, const Env& env, int64_t
       if constexpr (MAXNIN < 0)
         exec_contract<R, -MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
       else
-        exec_contract_any<R, MAXNIN, USE_LDS>(d, arena, b0, b1, wg_rank, wg_count, red, lds);
+        exec_contract_any<R, MAXNIN>(d, arena, b0, b1, wg_rank, wg_count, red);
       break;
     case OP_ADJOINT:
-      if constexpr (WIDE && !USE_LDS) exec_adjoint_any<R>(d, arena, b0, b1, wg_rank, wg_count, lds);
+      if constexpr (WIDE) exec_adjoint_any<R>(d, arena, b0, b1, wg_rank, wg_count, lds);
       break;
     case OP_LEAF: exec_leaf<R>(d, arena, env, wg_rank, wg_count); break;
     case OP_RESULT:
-      if (wg_rank == 0) exec_result<R>(d, arena, env, USE_LDS ? lds : nullptr);
+      if (wg_rank == 0) exec_result<R>(d, arena, env);
       break;
     case OP_ZERO: exec_zero<R>(d, arena, wg_rank, wg_count); break;
     case OP_LEAFGRAD:
       if (wg_rank == 0) exec_leafgrad<R>(d, arena, env);
       break;
     default: break;
+  }
+}
+
+// ------------------------------------------------------------------ LDS-resident programs
+// A light cone whose whole program fits the LDS window runs in one workgroup
+// from compact SmallOps.  The ops are read through the scalar cache (uniform
+// address, constant address space), so every descriptor field is a scalar
+// register and the per-op setup costs a few instructions.
+#define QTN_CONST __attribute__((address_space(4)))
+
+// A record loaded through the scalar cache: word by word from the constant
+// address space (the address must be uniform across the wavefront).
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "records are loaded in 32-bit words");
+  const QTN_CONST uint32_t* q = (const QTN_CONST uint32_t*)p;
+  T v;
+  uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+  return v;
+}
+
+__device__ __forceinline__ uint32_t nib(uint64_t v, int j) { return (uint32_t)(v >> (4 * j)) & 0xfu; }
+
+// Contraction on one wavefront.  Virtual lane v covers the first nv = n_out +
+// ls dimensions (the output element and, when the output has fewer than 64
+// elements, the lowest summed dimensions, which are then reduced across the
+// wavefront); lane bits are the first min(nv, 6) dimensions, the rest of v is
+// a per-lane loop.  Each lane walks the summed dimensions nv.. in Gray-code
+// order, two at a time (both values of the first), so its loads are
+// independent.  Offsets move by XOR: every dimension an input holds is one
+// bit of its element index.
+template <typename R, int NIN>
+__device__ __forceinline__ void small_contract(const SmallOp& d, typename CT<R>::E* __restrict__ lds,
+                                               typename CT<R>::E* __restrict__ arena, int lane) {
+  using E = typename CT<R>::E;
+  const int nb = d.nbits, no = d.n_out, ns = nb - no;
+  const int ls = min(ns, max(0, 6 - no));
+  const int nv = no + ls, nk = ns - ls;
+  const int nl = min(nv, 6);
+  const E* in[NIN];
+  uint32_t st0[NIN], off[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    in[i] = lds + d.in_off[i];
+    const uint32_t s = nk > 0 ? nib(d.shift[i], nv) : 0xfu;
+    st0[i] = s == 0xfu ? 0u : (1u << s);
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t sj = nib(d.shift[i], j);
+      if (j < nl && sj != 0xfu) o |= ((uint32_t)(lane >> j) & 1u) << sj;
+    }
+    off[i] = o;
+  }
+  const bool active = lane < (1 << nl);
+  const int nouter = 1 << (nv - nl);
+  uint32_t g = 0;  // Gray code of the outer loop (dimensions 6 .. nv - 1)
+  for (int h = 0; h < nouter; ++h) {
+    if (h) {
+      const int t = __ffs(h) - 1;
+      g ^= 1u << t;
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) {
+        const uint32_t s = nib(d.shift[i], 6 + t);
+        off[i] ^= s == 0xfu ? 0u : (1u << s);
+      }
+    }
+    E acc0 = {0, 0}, acc1 = {0, 0};
+    if (active) {
+      uint32_t o2[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) o2[i] = off[i];
+      if (nk == 0) {
+        E p = in[0][o2[0]];
+#pragma unroll
+        for (int i = 1; i < NIN; ++i) p = cmul(p, in[i][o2[i]]);
+        acc0 = p;
+      } else {
+        const int nit = 1 << (nk - 1);
+        for (int it = 0; it < nit; ++it) {
+          if (it) {
+            const int j = nv + __ffs(it);  // Gray code over dimensions nv + 1 ..
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+              const uint32_t s = nib(d.shift[i], j);
+              o2[i] ^= s == 0xfu ? 0u : (1u << s);
+            }
+          }
+          E a[NIN], b[NIN];
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            a[i] = in[i][o2[i]];
+            b[i] = in[i][o2[i] ^ st0[i]];
+          }
+          E p = a[0], q = b[0];
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) {
+            p = cmul(p, a[i]);
+            q = cmul(q, b[i]);
+          }
+          acc0 = cadd(acc0, p);
+          acc1 = cadd(acc1, q);
+        }
+      }
+    }
+    acc0 = cadd(acc0, acc1);
+    // summed lane dimensions no .. nv - 1 (then nv <= 6)
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j >= no && j < nv) acc0 = cadd(acc0, shfl_xor_c(acc0, 1 << j));
+    const uint32_t v = (uint32_t)lane | (g << 6);
+    if (active && ((v >> no) & ((1u << ls) - 1u)) == 0) {
+      const uint32_t o = v & ((1u << no) - 1u);
+      if (d.flags & SF_GOUT)
+        arena[d.gout + o] = acc0;  // a leaf-table adjoint, for the leaf-gradient launch
+      else
+        lds[d.out_off + o] = acc0;
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void small_contract_any(const SmallOp& d, typename CT<R>::E* lds,
+                                                   typename CT<R>::E* arena, int lane) {
+  switch (d.n_in) {
+    case 1: small_contract<R, 1>(d, lds, arena, lane); break;
+    case 2: small_contract<R, 2>(d, lds, arena, lane); break;
+    case 3: small_contract<R, 3>(d, lds, arena, lane); break;
+    case 4: small_contract<R, 4>(d, lds, arena, lane); break;
+    case 5: small_contract<R, 5>(d, lds, arena, lane); break;
+    case 6: small_contract<R, 6>(d, lds, arena, lane); break;
+    case 7: small_contract<R, 7>(d, lds, arena, lane); break;
+    default: small_contract<R, 8>(d, lds, arena, lane); break;
+  }
+}
+
+// Leaf-product table on one wavefront (lane 0..63): entry e of out = product
+// over the table's L leaves of leaf[e restricted to the leaf's two indices].
+// LM >= L: the body is branch-free (missing leaves multiply by one), so every
+// value load of an entry is in flight at once; references read once.
+template <typename R, int LM>
+__device__ __forceinline__ void leaf_table_wave_m(typename CT<R>::E* out, int n, const LeafRef* refs, int L,
+                                                  const typename CT<R>::E* vals, int lane) {
+  using E = typename CT<R>::E;
+  LeafRef lr[LM];
+#pragma unroll
+  for (int q = 0; q < LM; ++q) lr[q] = q < L ? refs[q] : LeafRef{0, 0, 0};
+  for (int e = lane; e < n; e += 64) {
+    E v[LM];
+#pragma unroll
+    for (int q = 0; q < LM; ++q) {
+      const int hi = lr[q].pb >= 0 ? ((e >> (lr[q].pb & 31)) & 1) << 1 : 0;
+      v[q] = vals[lr[q].kind * 4 + (((e >> lr[q].pa) & 1) | hi)];
+    }
+    E p = {1, 0};
+#pragma unroll
+    for (int q = 0; q < LM; ++q)
+      if (q < L) p = cmul(p, v[q]);
+    out[e] = p;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void leaf_table_wave(typename CT<R>::E* out, int n, const LeafRef* refs, int L,
+                                                const typename CT<R>::E* vals, int lane) {
+  using E = typename CT<R>::E;
+  if (L <= 4) {
+    leaf_table_wave_m<R, 4>(out, n, refs, L, vals, lane);
+  } else if (L <= 8) {
+    leaf_table_wave_m<R, 8>(out, n, refs, L, vals, lane);
+  } else if (L <= 16) {
+    leaf_table_wave_m<R, 16>(out, n, refs, L, vals, lane);
+  } else {
+    for (int e = lane; e < n; e += 64) {
+      E p = {1, 0};
+      for (int r = 0; r < L; ++r) {
+        const LeafRef Lr = refs[r];
+        int idx = (e >> Lr.pa) & 1;
+        if (Lr.pb >= 0) idx |= ((e >> Lr.pb) & 1) << 1;
+        p = cmul(p, vals[Lr.kind * 4 + idx]);
+      }
+      out[e] = p;
+    }
+  }
+}
+
+// dR/dtheta += sum_e Lbar[e] * (derivative of one leaf) * (the other leaves),
+// by one wavefront (lane 0..63) over the n entries of one leaf-product table
+// with L <= LM leaves.  Per entry: every leaf value and derivative loaded at
+// once, suffix products of the leaves, then one pass with the running prefix
+// (3L complex multiplies instead of L^2), branch-free; leaves come sorted by
+// kind, so one wavefront sum and one atomic per angle.
+template <typename R, int LM>
+__device__ __forceinline__ void leafgrad_wave_m(const typename CT<R>::E* lbar, int n, const LeafRef* refs, int L,
+                                                const typename CT<R>::E* vals, const typename CT<R>::E* dvals,
+                                                double* res, int p, int lane) {
+  using E = typename CT<R>::E;
+  LeafRef lr[LM];
+  int slot[LM];
+#pragma unroll
+  for (int q = 0; q < LM; ++q) {
+    lr[q] = q < L ? refs[q] : LeafRef{0, 0, 0};
+    slot[q] = q < L ? theta_slot(lr[q].kind, p) : -1;
+  }
+  double sxd[LM], syd[LM];
+#pragma unroll
+  for (int q = 0; q < LM; ++q) sxd[q] = syd[q] = 0.0;
+  for (int e = lane; e < n; e += 64) {
+    E v[LM], dv[LM];
+#pragma unroll
+    for (int q = 0; q < LM; ++q) {
+      const int hi = lr[q].pb >= 0 ? ((e >> (lr[q].pb & 31)) & 1) << 1 : 0;
+      const int k = lr[q].kind * 4 + (((e >> lr[q].pa) & 1) | hi);
+      v[q] = q < L ? vals[k] : E{1, 0};
+      dv[q] = dvals[k];
+    }
+    E suf[LM + 1];
+    suf[LM] = E{1, 0};
+#pragma unroll
+    for (int q = LM - 1; q >= 0; --q) suf[q] = cmul(v[q], suf[q + 1]);
+    E pre = lbar[e];
+#pragma unroll
+    for (int q = 0; q < LM; ++q) {
+      const E t = cmul(cmul(pre, dv[q]), suf[q + 1]);
+      sxd[q] += (double)t.x;
+      syd[q] += (double)t.y;
+      pre = cmul(pre, v[q]);
+    }
+  }
+  int cur = -1;
+  double sx = 0, sy = 0;
+#pragma unroll
+  for (int q = 0; q <= LM; ++q) {
+    const int sl = q < LM ? slot[q] : -2;  // uniform across the wavefront
+    if (sl == -1) continue;
+    if (sl != cur && cur >= 0) {
+      const double wx = wave_sum(sx), wy = wave_sum(sy);
+      if (lane == 0) {
+        atomicAdd(res + cur, wx);
+        atomicAdd(res + cur + 1, wy);
+      }
+    }
+    if (sl == -2) break;
+    if (sl != cur) {
+      cur = sl;
+      sx = sy = 0;
+    }
+    sx += sxd[q];
+    sy += syd[q];
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void leafgrad_wave(const typename CT<R>::E* lbar, int n, const LeafRef* refs, int L,
+                                              const typename CT<R>::E* vals, const typename CT<R>::E* dvals,
+                                              double* res, int p, int lane) {
+  using E = typename CT<R>::E;
+  if (L <= 4) {
+    leafgrad_wave_m<R, 4>(lbar, n, refs, L, vals, dvals, res, p, lane);
+  } else if (L <= 8) {
+    leafgrad_wave_m<R, 8>(lbar, n, refs, L, vals, dvals, res, p, lane);
+  } else if (L <= 16) {
+    leafgrad_wave_m<R, 16>(lbar, n, refs, L, vals, dvals, res, p, lane);
+  } else {
+    // many leaves (rare): one pass over the entries per leaf with an angle
+    for (int r = 0; r < L; ++r) {
+      const int slot = theta_slot(refs[r].kind, p);
+      if (slot < 0) continue;  // uniform across the wavefront
+      double ax = 0, ay = 0;
+      for (int e = lane; e < n; e += 64) {
+        E t = lbar[e];
+        for (int q = 0; q < L; ++q) {
+          const LeafRef Ls = refs[q];
+          int idx = (e >> Ls.pa) & 1;
+          if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
+          t = cmul(t, q == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
+        }
+        ax += (double)t.x;
+        ay += (double)t.y;
+      }
+      ax = wave_sum(ax);
+      ay = wave_sum(ay);
+      if (lane == 0) {
+        atomicAdd(res + slot, ax);
+        atomicAdd(res + slot + 1, ay);
+      }
+    }
+  }
+}
+
+// Cone value R = product of the scalars; with SF_GRAD also the seed of each
+// scalar (product of the others) and zeroed gradient accumulators.  One
+// wavefront.
+template <typename R>
+__device__ __forceinline__ void small_result(const SmallOp& d, typename CT<R>::E* lds, const Env& env, int lane) {
+  using E = typename CT<R>::E;
+  double* res = env.res + (int64_t)d.cone * env.res_stride;
+  const int ns = d.n_in;  // <= 4 scalars (one per connected component)
+  double2 x[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const E v = s < ns ? lds[d.in_off[s]] : E{1, 0};
+    x[s] = make_double2(v.x, v.y);
+  }
+  if (lane == 0) {
+    const double2 prod = cmul(cmul(x[0], x[1]), cmul(x[2], x[3]));
+    res[0] = prod.x;
+    res[1] = prod.y;
+  }
+  if (d.flags & SF_GRAD) {
+    // seed of scalar s: product of the other scalars (lane s)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (s < ns && lane == s) {
+        double2 seed = make_double2(1, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t != s) seed = cmul(seed, x[t]);
+        E o;
+        o.x = (R)seed.x;
+        o.y = (R)seed.y;
+        lds[d.in_off[4 + s]] = o;
+      }
+    for (int i = lane; i < 4 * env.p; i += 64) res[2 + i] = 0.0;
+  }
+}
+
+// One cone's LDS-resident program small[lo, hi) on the whole workgroup.  The
+// ops come through `sprog` in chunks of SMALL_CHUNK (one bulk load per
+// chunk, every thread a 16-byte word, instead of a dependent load per op) and
+// are read from there into scalar registers.  The leaf-block copy runs on all
+// threads; every other op on its wavefront (ops between two barriers are
+// independent, so the wavefronts run them side by side).
+constexpr int SMALL_CHUNK = 16;
+
+template <typename R>
+__device__ __forceinline__ void run_small(const SmallOp* small, int lo, int hi, typename CT<R>::E* lds, SmallOp* sprog,
+                                          const Env& env) {
+  using E = typename CT<R>::E;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  for (int k0 = lo; k0 < hi; k0 += SMALL_CHUNK) {
+    const int nk = min(SMALL_CHUNK, hi - k0);
+    constexpr int W = sizeof(SmallOp) / sizeof(uint4);
+    __syncthreads();  // the previous chunk's ops are done with sprog
+    for (int t = threadIdx.x; t < nk * W; t += blockDim.x)
+      reinterpret_cast<uint4*>(sprog)[t] = reinterpret_cast<const uint4*>(small + k0)[t];
+    __syncthreads();
+    for (int j = 0; j < nk; ++j) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(sprog + j);
+      // kind, flags and wavefront first: the other wavefronts skip the op here
+      const uint32_t w0 = __builtin_amdgcn_readfirstlane(src[0]), w1 = __builtin_amdgcn_readfirstlane(src[1]);
+      const uint32_t kind = w0 & 0xffu, flags = w1 & 0xffu, owner = (w1 >> 8) & 0xffu;
+      if (j > 0 && (flags & SF_SYNC)) __syncthreads();
+      if (kind != S_COPYIN && (int)(owner % nw) != wave) continue;
+      // every field into a scalar register: uniform control flow, no private copy
+      SmallOp d;
+      {
+        uint32_t* dw = reinterpret_cast<uint32_t*>(&d);
+#pragma unroll
+        for (int q = 0; q < (int)(sizeof(SmallOp) / 4); ++q) dw[q] = __builtin_amdgcn_readfirstlane(src[q]);
+      }
+      if (d.kind == S_COPYIN) {
+        const E* src = reinterpret_cast<const E*>(env.arena) + d.gout;
+        for (int t = threadIdx.x; t < d.aux1; t += blockDim.x) lds[t] = src[t];
+        continue;
+      }
+      if (d.kind == S_CONTRACT)
+        small_contract_any<R>(d, lds, reinterpret_cast<E*>(env.arena), lane);
+      else if (d.kind == S_RESULT)
+        small_result<R>(d, lds, env, lane);
+    }
   }
 }
 

@@ -13,9 +13,9 @@ constexpr int DESC_CHUNK = 16;
 // WIDE: the plan has F_WIDE ops (a separate instantiation keeps the register
 // budget of narrow-only sweeps unchanged).
 template <typename R, int MAXNIN, bool WIDE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, 8))) persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items,
-                                                          int n_items, const int32_t* __restrict__ succ, int32_t* ctl,
-                                                          Env env, long long spin_limit) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, 8)))
+persistent_kernel(const OpDesc* __restrict__ ops, const QItem* __restrict__ items, int n_items,
+                  const int32_t* __restrict__ succ, int32_t* ctl, Env env, long long spin_limit) {
   __shared__ RedBuf<typename CT<R>::E> red;
   __shared__ OpDesc sdesc[DESC_CHUNK];
   extern __shared__ __align__(16) char dyn_lds[];
@@ -52,15 +52,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
     __syncthreads();
     if (!s_abort) {
       using E = typename CT<R>::E;
-      E* lds = nullptr;
-      if (I.copyin >= 0) {
-        // LDS-resident cone: bring its leaf-product block into the LDS window
-        const OpDesc& cp = ops[I.copyin];
-        const E* src = reinterpret_cast<const E*>(env.arena) + cp.in_off[0];
-        lds = reinterpret_cast<E*>(dyn_lds);
-        for (int64_t t = threadIdx.x; t < cp.in_off[1]; t += blockDim.x) lds[t] = src[t];
-        __syncthreads();
-      }
       // descriptors are staged through LDS in chunks: one bulk copy instead of
       // a dependent global load per op
       for (int r = 0; r < 2; ++r) {
@@ -79,10 +70,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
             const int64_t nblocks = (d.kind == OP_CONTRACT || d.kind == OP_ADJOINT) ? (int64_t(1) << d.nb) : 1;
             const int64_t b0 = I.blk_hi < 0 ? 0 : I.blk_lo;
             const int64_t b1 = I.blk_hi < 0 ? nblocks : I.blk_hi;
-            if (lds)
-              exec_op<R, MAXNIN, true>(d, env, b0, b1, 0, 1, &red, lds);
-            else
-              exec_op<R, MAXNIN, false, WIDE>(d, env, b0, b1, 0, 1, &red, reinterpret_cast<E*>(dyn_lds));
+            exec_op<R, MAXNIN, WIDE>(d, env, b0, b1, 0, 1, &red, reinterpret_cast<E*>(dyn_lds));
           }
           __syncthreads();
         }
@@ -112,9 +100,9 @@ static hipError_t launch_persistent_m(const OpDesc* ops, const QItem* items, int
 }
 
 template <typename R, bool W>
-hipError_t launch_persistent_t(int max_nin, const OpDesc* ops, const QItem* items, int n_items,
-                                      const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
-                                      size_t lds_bytes, long long spin_limit, hipStream_t st) {
+hipError_t launch_persistent_t(int max_nin, const OpDesc* ops, const QItem* items, int n_items, const int32_t* succ,
+                               int32_t* ctl, const Env& env, int threads, int grid, size_t lds_bytes,
+                               long long spin_limit, hipStream_t st) {
   if (max_nin <= 3)
     return launch_persistent_m<R, 3, W>(ops, items, n_items, succ, ctl, env, threads, grid, lds_bytes, spin_limit, st);
   if (max_nin <= 5)

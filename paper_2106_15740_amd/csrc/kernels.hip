@@ -17,13 +17,6 @@ namespace qtn {
 // Leaf-product tables (OP_LEAF) and leaf gradients (OP_LEAFGRAD) of every
 // cone, one wavefront per op: the tables have a few to a few hundred entries,
 // so a whole workgroup per op would idle.
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-  return v;
-}
-
-constexpr int LG_MAXL = 16;  // leaves per table handled by the linear-time leaf gradient
-
 template <typename R>
 __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env,
                                                          int32_t* ctl, const int32_t* __restrict__ ctl_init,
@@ -54,117 +47,36 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
     const OpDesc& d = ops[op];
     const int64_t n = int64_t(1) << d.nbits;
     const LeafRef* refs = env.leafrefs + d.aux0;
-    if (d.kind == OP_LEAF) {
-      E* out = arena + d.out_off;
-      for (int64_t e = lane; e < n; e += 64) {
-        E pr = {1, 0};
-        for (int r = 0; r < d.aux1; ++r) {
-          const LeafRef L = refs[r];
-          int idx = (e >> L.pa) & 1;
-          if (L.pb >= 0) idx |= ((e >> L.pb) & 1) << 1;
-          pr = cmul(pr, vals[L.kind * 4 + idx]);
-        }
-        out[e] = pr;
-      }
-    } else if (d.kind == OP_LEAFGRAD) {
-      // dR/dtheta += sum_e Lbar[e] * (derivative of one leaf) * (the other
-      // leaves).  Up to LG_MAXL leaves: per entry, suffix products of the
-      // leaves, then one forward pass with the running prefix (3L complex
-      // multiplies instead of L^2); leaves come sorted by angle, so one
-      // atomic per angle.
-      const E* lbar = arena + d.in_off[0];
-      double* res = env.res + (int64_t)d.cone * env.res_stride;
-      const int L = d.aux1;
-      if (L <= LG_MAXL) {
-        double ax[LG_MAXL], ay[LG_MAXL];
-#pragma unroll
-        for (int q = 0; q < LG_MAXL; ++q) ax[q] = ay[q] = 0.0;
-        for (int64_t e = lane; e < n; e += 64) {
-          E suf[LG_MAXL + 1];
-          suf[LG_MAXL] = E{1, 0};
-#pragma unroll
-          for (int q = LG_MAXL - 1; q >= 0; --q) {
-            if (q < L) {
-              const LeafRef Lq = refs[q];
-              int idx = (e >> Lq.pa) & 1;
-              if (Lq.pb >= 0) idx |= ((e >> Lq.pb) & 1) << 1;
-              suf[q] = cmul(vals[Lq.kind * 4 + idx], suf[q + 1]);
-            } else {
-              suf[q] = E{1, 0};
-            }
-          }
-          E pre = lbar[e];
-#pragma unroll
-          for (int q = 0; q < LG_MAXL; ++q) {
-            if (q < L) {
-              const LeafRef Lq = refs[q];
-              int idx = (e >> Lq.pa) & 1;
-              if (Lq.pb >= 0) idx |= ((e >> Lq.pb) & 1) << 1;
-              const E t = cmul(cmul(pre, dvals[Lq.kind * 4 + idx]), suf[q + 1]);
-              ax[q] += (double)t.x;
-              ay[q] += (double)t.y;
-              pre = cmul(pre, vals[Lq.kind * 4 + idx]);
-            }
-          }
-        }
-        // per angle: sum the leaves in the lane, then across the wavefront
-        int cur = -1;
-        double sx = 0, sy = 0;
-#pragma unroll
-        for (int q = 0; q <= LG_MAXL; ++q) {
-          const int slot = q < L ? theta_slot(refs[q].kind, env.p) : -2;  // uniform across the wavefront
-          if (slot == -1) continue;
-          if (slot != cur && cur >= 0) {
-            const double wx = wave_sum(sx), wy = wave_sum(sy);
-            if (lane == 0) {
-              atomicAdd(res + cur, wx);
-              atomicAdd(res + cur + 1, wy);
-            }
-          }
-          if (slot == -2) break;
-          if (slot != cur) {
-            cur = slot;
-            sx = sy = 0;
-          }
-          if (q < LG_MAXL) {
-            sx += ax[q];
-            sy += ay[q];
-          }
-        }
-      } else {
-        for (int r = 0; r < L; ++r) {
-          const int slot = theta_slot(refs[r].kind, env.p);
-          if (slot < 0) continue;  // uniform across the wavefront
-          double ax = 0, ay = 0;
-          for (int64_t e = lane; e < n; e += 64) {
-            E t = lbar[e];
-            for (int q = 0; q < L; ++q) {
-              const LeafRef Ls = refs[q];
-              int idx = (e >> Ls.pa) & 1;
-              if (Ls.pb >= 0) idx |= ((e >> Ls.pb) & 1) << 1;
-              t = cmul(t, q == r ? dvals[Ls.kind * 4 + idx] : vals[Ls.kind * 4 + idx]);
-            }
-            ax += (double)t.x;
-            ay += (double)t.y;
-          }
-          ax = wave_sum(ax);
-          ay = wave_sum(ay);
-          if (lane == 0) {
-            atomicAdd(res + slot, ax);
-            atomicAdd(res + slot + 1, ay);
-          }
-        }
-      }
-    }
+    if (d.kind == OP_LEAF)
+      leaf_table_wave<R>(arena + d.out_off, (int)n, refs, d.aux1, vals, lane);
+    else if (d.kind == OP_LEAFGRAD)
+      leafgrad_wave<R>(arena + d.in_off[0], (int)n, refs, d.aux1, vals, dvals,
+                       env.res + (int64_t)d.cone * env.res_stride, env.p, lane);
   }
+}
+
+// LDS-resident light cones: workgroup k runs the whole program
+// small[items[2k], items[2k + 1]) of one cone with every tensor in its LDS
+// window (items are ordered longest first).
+template <typename R>
+__global__ void __launch_bounds__(256) small_kernel(const SmallOp* __restrict__ small, const int32_t* __restrict__ items,
+                                                    Env env) {
+  using E = typename CT<R>::E;
+  extern __shared__ __align__(16) char dyn_lds[];
+  __shared__ SmallOp sprog[SMALL_CHUNK];
+  const int2 r = load_const(reinterpret_cast<const int2*>(items) + blockIdx.x);
+  run_small<R>(small, r.x, r.y, reinterpret_cast<E*>(dyn_lds), sprog, env);
 }
 
 // Copy of a few hundred bytes between device memory and mapped pinned host
 // memory (leaf values in, results out): a kernel node keeps the sweep's
 // graph free of copy-engine transfers and their start-up latency.
 __global__ void __launch_bounds__(256) small_copy_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
-                                                         int n) {
+                                                         int n, int32_t* ctl, const int32_t* __restrict__ ctl_init,
+                                                         int n_nodes) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  if (ctl)
+    for (int i = threadIdx.x; i < n_nodes + 2; i += blockDim.x) ctl[i] = i < 2 ? 0 : ctl_init[i - 2];
 }
 
 // Plain device copy (16-byte words, grid-stride): the achievable-bandwidth
@@ -278,11 +190,12 @@ hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const En
   return hipGetLastError();
 }
 
-hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
-  if (bytes == 0) return hipSuccess;
+hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st, int32_t* ctl,
+                             const int32_t* ctl_init, int n_nodes) {
+  if (bytes == 0 && !ctl) return hipSuccess;
   if (bytes % 4 || bytes > (size_t(1) << 20)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(small_copy_kernel, dim3(1), dim3(256), 0, st, reinterpret_cast<const uint32_t*>(src),
-                     reinterpret_cast<uint32_t*>(dst), (int)(bytes / 4));
+                     reinterpret_cast<uint32_t*>(dst), (int)(bytes / 4), ctl, ctl_init, n_nodes);
   return hipGetLastError();
 }
 
@@ -319,6 +232,25 @@ hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* op
                                                  spin_limit, st)
               : launch_persistent_t<float, false>(max_nin, ops, items, n_items, succ, ctl, env, threads, grid,
                                                   lds_bytes, spin_limit, st);
+}
+
+template <typename R>
+static hipError_t launch_small_t(const SmallOp* small, const int32_t* items, int n_items, const Env& env, int threads,
+                                 size_t lds_bytes, hipStream_t st) {
+  if (lds_bytes > 0) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&small_kernel<R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(small_kernel<R>, dim3(n_items), dim3(threads), lds_bytes, st, small, items, env);
+  return hipGetLastError();
+}
+
+hipError_t launch_small(bool c128, const SmallOp* small, const int32_t* items, int n_items, const Env& env,
+                        int threads, size_t lds_bytes, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  return c128 ? launch_small_t<double>(small, items, n_items, env, threads, lds_bytes, st)
+              : launch_small_t<float>(small, items, n_items, env, threads, lds_bytes, st);
 }
 
 hipError_t launch_final(bool c128, const double* res, int res_stride, int n_cones, int p, int with_grad, void* zz_out,

@@ -26,8 +26,10 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
 hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, hipStream_t st,
                         int32_t* ctl = nullptr, const int32_t* ctl_init = nullptr, int n_nodes = 0);
 // bytes (a multiple of 4, <= 1 MiB) from src to dst with one workgroup;
-// either side may be mapped pinned host memory
-hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+// either side may be mapped pinned host memory.  With ctl, the same launch
+// resets the persistent sweep's queue head, error flag and node counters.
+hipError_t launch_small_copy(const void* src, void* dst, size_t bytes, hipStream_t st, int32_t* ctl = nullptr,
+                             const int32_t* ctl_init = nullptr, int n_nodes = 0);
 // n16 16-byte words from src to dst (non-overlapping), `grid` workgroups of
 // 256 threads, `unroll` (1, 2 or 4) loads in flight per thread
 hipError_t launch_copy(const void* src, void* dst, size_t n16, int grid, int unroll, hipStream_t st);
@@ -38,6 +40,10 @@ hipError_t launch_reset(int32_t* ctl, const int32_t* init, int n_nodes, hipStrea
 hipError_t launch_persistent(bool c128, bool wide, int max_nin, const OpDesc* ops, const QItem* items, int n_items,
                              const int32_t* succ, int32_t* ctl, const Env& env, int threads, int grid,
                              size_t lds_bytes, long long spin_limit, hipStream_t st);
+// LDS-resident light cones: one workgroup per program small[items[2k],
+// items[2k + 1]), the LDS window lds_bytes
+hipError_t launch_small(bool c128, const SmallOp* small, const int32_t* items, int n_items, const Env& env,
+                        int threads, size_t lds_bytes, hipStream_t st);
 // Per-element-type launchers, each instantiated in its own translation unit
 // (kern_ops.hip, kern_persist.hip) so the kernels compile in parallel.
 template <typename R>

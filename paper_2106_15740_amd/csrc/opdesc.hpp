@@ -16,7 +16,6 @@ enum OpKind : int32_t {
   OP_RESULT = 2,    // cone value R = prod of scalar outputs; optional adjoint seeds
   OP_ZERO = 3,      // zero a range of the arena
   OP_LEAFGRAD = 4,  // dR/dtheta from the adjoint of one leaf-product table
-  OP_COPYIN = 5,    // copy a cone's leaf-product block into its LDS window (persistent sweep only)
   OP_ADJOINT = 6,   // every input adjoint of one wide bucket in one pass over its union (see adj_off)
 };
 
@@ -53,15 +52,11 @@ struct alignas(16) OpDesc {
   int64_t in_off[MAXIN];
   uint32_t in_mask[MAXIN];
   uint8_t zbit[32];
-  // LDS-resident execution (persistent sweep): operand i (output: MAXIN) is
-  // at LDS element offset lds_off[i] when bit i of lds_mask is set
-  uint32_t lds_mask;
-  int32_t lds_off[MAXIN + 1];
   // lane offsets without bit arithmetic on the device: for operand i (output:
   // MAXIN) and lane bit j < nl, the element stride is 1 << lsh[i][j], or 0
   // when lsh[i][j] == LSH_NONE
   uint8_t lsh[MAXIN + 1][MAXLANE];
-  uint8_t pad_[14];
+  uint8_t pad_[6];
   // OP_ADJOINT: input 0 is the output adjoint (without the eliminated index,
   // bit 0), inputs 1.. hold bit 0; for every i with bit i of adj_sel set, the
   // adjoint of input i (same index set in_mask[i]) is written at adj_off[i]:
@@ -72,11 +67,48 @@ struct alignas(16) OpDesc {
   uint32_t pad2_[3];
 };
 static_assert(sizeof(OpDesc) % 16 == 0, "OpDesc is copied in 16-byte words");
+static_assert(sizeof(OpDesc) == 368, "OpDesc layout");
 
 struct LeafRef {
   int16_t kind;
   int8_t pa, pb;  // bit positions inside the leaf-product table (pb < 0: rank 1)
 };
+
+// Compact op of an LDS-resident light-cone program (the batched sweep runs
+// such a cone's whole program in one workgroup, every tensor in LDS).  The
+// union bits of a contraction are renumbered as "dimensions": the output's
+// bits first (in union order, so output element o is the first n_out
+// dimensions read as a number), then the summed bits.  Input i reads element
+// sum over set dimensions j of 2^shift_i[j], where shift_i[j] is nibble j of
+// shift[i] (0xf: input i lacks dimension j).
+enum SmallKind : uint8_t {
+  S_CONTRACT = 0,  // out[o] = sum over summed dims of prod_i in_i[...]
+  S_COPYIN = 1,    // copy aux1 elements of the arena from gout (the cone's leaf-product block) to LDS offset 0
+  S_RESULT = 2,    // cone value R = prod of the n_in (<= 4) scalars at in_off[]; SF_GRAD: seeds at in_off[4 + s]
+};
+enum SmallFlags : uint8_t {
+  SF_SYNC = 1,  // barrier before the op (it reads or overwrites data of an op since the last barrier)
+  SF_GOUT = 2,  // the output goes to global memory at element offset gout (not LDS)
+  SF_GRAD = 4,  // S_RESULT also writes the adjoint seeds and zeroes the gradient accumulators
+};
+struct alignas(16) SmallOp {  // the executor reads byte 0 (kind), 4 (flags) and 5 (wave) first
+  uint8_t kind;
+  uint8_t n_in;
+  uint8_t nbits;   // contraction: union bits (<= 15)
+  uint8_t n_out;   // contraction: output bits
+  uint8_t flags;
+  uint8_t wave;         // wavefront of the workgroup that runs the op (modulo the wavefronts present)
+  uint8_t pad0[2];
+  uint16_t out_off;     // LDS element offset of the output
+  uint16_t in_off[8];   // LDS element offsets of the inputs (S_RESULT: scalars, then seeds)
+  uint16_t pad1[3];
+  uint64_t shift[8];    // per input: 16 nibbles, the element stride (log2) of each dimension
+  int64_t gout;         // global element offset (SF_GOUT output; S_COPYIN source)
+  int32_t aux0, aux1;   // S_COPYIN: aux1 = elements
+  int32_t cone;
+  int32_t pad2[3];
+};
+static_assert(sizeof(SmallOp) == 128, "SmallOp is copied in 16-byte words");
 
 // Persistent-queue work item: ops [op_lo, op_hi) then [op2_lo, op2_hi) run
 // in sequence by one workgroup over all their blocks (blk_hi < 0), or blocks
@@ -89,8 +121,7 @@ struct QItem {
   int32_t blk_lo, blk_hi;
   int32_t node;
   int32_t succ_lo, succ_hi;
-  int32_t copyin;  // >= 0: the item runs LDS-resident; this op fills the LDS window first
-  int32_t pad[2];
+  int32_t pad[3];
 };
 
 }  // namespace qtn

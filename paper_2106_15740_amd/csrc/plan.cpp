@@ -18,6 +18,7 @@
 #include <numeric>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <set>
 
 namespace qtn {
@@ -909,123 +910,10 @@ OpDesc blank(int kind, int cone) {
 
 }  // namespace
 
-// LDS-resident cones: when every op of a cone's program fits one workgroup,
-// its tensors can live in LDS for the whole persistent sweep.  Works on the
-// programs while their operands still hold buffer codes: lifetimes are taken
-// over the gradient program (which covers the forward-only program too) and
-// buffers are placed first-fit by definition time.  The leaf-product block
-// sits at LDS offset 0, laid out as in the arena.  The adjoints of the leaf
-// tables stay in global memory (the leaf gradients are batched after the
-// sweep).  Ops keep their global offsets for the plain per-op path;
-// lds_off/lds_mask are used only by the persistent kernel in items flagged as
-// LDS-resident.
-static void lds_layout(Plan& P) {
-  const TuneParams& T = P.tune;
-  const int64_t budget = (int64_t)T.lds_kb * 1024 / std::max(1, T.elem_bytes);
-  P.cone_lds.assign(P.cones.size(), 0);
-  P.lds_elems = 0;
-  if (budget <= 0) return;
-  for (size_t c = 0; c < P.cones.size(); ++c) {
-    Cone& C = P.cones[c];
-    std::vector<int32_t> prog;
-    for (int32_t o = P.cone_fwd_lo[c]; o <= P.cone_fwd_hi[c]; ++o) prog.push_back(o);  // includes forward result
-    for (int32_t o = P.cone_adj_lo[c]; o < P.cone_adj_hi[c]; ++o) prog.push_back(o);
-    bool ok = C.lam_size <= budget;
-    for (int32_t o : prog) {
-      const OpDesc& d = P.ops[o];
-      if (d.kind == OP_ZERO || d.kind == OP_ADJOINT || (d.kind == OP_CONTRACT && d.nbits > T.seq_max_bits))
-        ok = false;
-    }
-    if (!ok) continue;
-    std::unordered_map<int64_t, int64_t> lam_local;  // leaf tables: offset inside the block
-    std::unordered_map<int64_t, size_t> idx;
-    struct L {
-      int64_t code, size;
-      int def = -1, last = -1;
-      int64_t loff = -1;
-    };
-    std::vector<L> bufs;
-    for (const BufLife& B : C.bufs) {
-      if (code_kind(B.code) == BK_LAM) lam_local[B.code] = B.off;
-      if (code_kind(B.code) == BK_LAM || code_kind(B.code) == BK_LAMADJ) continue;
-      idx[B.code] = bufs.size();
-      bufs.push_back({B.code, B.size});
-    }
-    auto touch = [&](int64_t code, int t) {
-      auto it = idx.find(code);
-      if (it == idx.end()) return;
-      L& B = bufs[it->second];
-      if (B.def < 0) B.def = t;
-      B.last = std::max(B.last, t);
-    };
-    for (size_t t = 0; t < prog.size(); ++t) {
-      const OpDesc& d = P.ops[prog[t]];
-      if (d.kind == OP_CONTRACT) {
-        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t);
-        touch(d.out_off, (int)t);
-      } else if (d.kind == OP_RESULT) {
-        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t);
-        if (d.flags & F_GRAD)
-          for (int i = 0; i < d.n_in; ++i) touch(d.in_off[d.n_in + i], (int)t);
-      }
-    }
-    std::vector<size_t> order;
-    for (size_t i = 0; i < bufs.size(); ++i)
-      if (bufs[i].def >= 0) order.push_back(i);
-    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bufs[a].def < bufs[b].def; });
-    const int64_t base0 = (C.lam_size + 63) / 64 * 64;
-    int64_t peak = base0;
-    std::vector<size_t> live;
-    for (size_t bi : order) {
-      L& B = bufs[bi];
-      live.erase(std::remove_if(live.begin(), live.end(), [&](size_t x) { return bufs[x].last < B.def; }), live.end());
-      std::vector<std::pair<int64_t, int64_t>> used;
-      for (size_t x : live) used.push_back({bufs[x].loff, bufs[x].loff + bufs[x].size});
-      std::sort(used.begin(), used.end());
-      const int64_t al = B.size >= 64 ? 64 : 2;
-      int64_t cand = base0;
-      for (auto& u : used) {
-        if (cand + B.size <= u.first) break;
-        cand = std::max(cand, (u.second + al - 1) / al * al);
-      }
-      B.loff = cand;
-      peak = std::max(peak, cand + B.size);
-      live.push_back(bi);
-    }
-    if (peak > budget) continue;
-    P.cone_lds[c] = 1;
-    P.lds_elems = std::max(P.lds_elems, peak);
-    auto lds_of = [&](int64_t code, int32_t& out) -> bool {
-      if (!is_code(code)) return false;
-      auto lt = lam_local.find(code);
-      if (lt != lam_local.end()) {
-        out = (int32_t)lt->second;
-        return true;
-      }
-      auto it = idx.find(code);
-      if (it == idx.end() || bufs[it->second].loff < 0) return false;
-      out = (int32_t)bufs[it->second].loff;
-      return true;
-    };
-    for (int32_t o : prog) {
-      OpDesc& d = P.ops[o];
-      d.lds_mask = 0;
-      if (d.kind == OP_CONTRACT) {
-        for (int i = 0; i < d.n_in; ++i)
-          if (lds_of(d.in_off[i], d.lds_off[i])) d.lds_mask |= 1u << i;
-        if (lds_of(d.out_off, d.lds_off[MAXIN])) d.lds_mask |= 1u << MAXIN;
-      } else if (d.kind == OP_RESULT) {
-        for (int i = 0; i < 2 * d.n_in; ++i)
-          if (lds_of(d.in_off[i], d.lds_off[i])) d.lds_mask |= 1u << i;
-      }
-    }
-  }
-}
-
 // F_SYNC marks the ops of a cone program that must wait for the whole
 // workgroup before they start, because they read or overwrite data written by
-// an op since the previous barrier, or (LDS-resident cones, where dead buffers
-// are reused) overwrite data read since then.  Independent consecutive ops
+// an op since the previous barrier, or overwrite data read since then (dead
+// buffers are reused).  Independent consecutive ops
 // (e.g. the buckets of unrelated branches of the elimination tree) run
 // without one.
 static void mark_barriers(Plan& P) {
@@ -1038,14 +926,11 @@ static void mark_barriers(Plan& P) {
       if (r.space == x.space && x.lo < r.hi && r.lo < x.hi) return true;
     return false;
   };
-  auto run = [&](int32_t lo, int32_t hi, bool lds, std::vector<Rng>& dirty, std::vector<Rng>& rdset) {
+  auto run = [&](int32_t lo, int32_t hi, std::vector<Rng>& dirty, std::vector<Rng>& rdset) {
     for (int32_t o = lo; o < hi; ++o) {
       OpDesc& d = P.ops[o];
       std::vector<Rng> rd, wr;
-      auto opnd = [&](int slot, int64_t goff, int64_t size) -> Rng {
-        if (lds && ((d.lds_mask >> slot) & 1)) return {1, d.lds_off[slot], d.lds_off[slot] + size};
-        return {0, goff, goff + size};
-      };
+      auto opnd = [&](int, int64_t goff, int64_t size) -> Rng { return {0, goff, goff + size}; };
       if (d.kind == OP_CONTRACT) {
         for (int i = 0; i < d.n_in; ++i)
           rd.push_back(opnd(i, d.in_off[i], int64_t(1) << __builtin_popcount(d.in_mask[i])));
@@ -1078,13 +963,12 @@ static void mark_barriers(Plan& P) {
     }
   };
   for (size_t c = 0; c < P.cones.size(); ++c) {
-    const bool lds = !P.cone_lds.empty() && P.cone_lds[c];
     std::vector<Rng> dirty, rdset;
-    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1, lds, dirty, rdset);  // forward program ends with its result op
+    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c] + 1, dirty, rdset);  // forward program ends with its result op
     dirty.clear();
     rdset.clear();
-    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c], lds, dirty, rdset);  // gradient program: forward ops, then the adjoint range
-    run(P.cone_adj_lo[c], P.cone_adj_hi[c], lds, dirty, rdset);
+    run(P.cone_fwd_lo[c], P.cone_fwd_hi[c], dirty, rdset);  // gradient program: forward ops, then the adjoint range
+    run(P.cone_adj_lo[c], P.cone_adj_hi[c], dirty, rdset);
   }
 }
 
@@ -1416,6 +1300,236 @@ int64_t resolve_off(const Cone& C, const std::unordered_map<int64_t, int64_t>& w
 
 }  // namespace
 
+// LDS-resident light cones.  When every step of a cone's gradient program is
+// narrow and its tensors fit the LDS window, the batched sweep runs the whole
+// program in one workgroup with every intermediate in LDS, from compact
+// SmallOps: the cone's leaf-product block (built by the leaf launch) is copied
+// in first, the adjoints of the leaf tables go straight to global memory (the
+// leaf-gradient launch reads them there), and every other tensor stays in LDS.
+// Buffers are placed first-fit by lifetime over that program, after the leaf
+// block (the forward-only program is its prefix with a plain result, so the
+// same placement serves it).  Ops between two barriers are independent of each
+// other: each is given to one wavefront of the workgroup (balanced by size),
+// so a workgroup of several wavefronts runs them side by side.  The per-op
+// programs stay in P.ops for the plain per-op path.
+static void small_programs(Plan& P, const std::vector<ConeProg>& progs) {
+  const TuneParams& T = P.tune;
+  const size_t nc = P.cones.size();
+  const int64_t budget = (int64_t)T.lds_kb * 1024 / std::max(1, T.elem_bytes);
+  const int nwaves = std::max(1, T.lds_threads / 64);
+  P.cone_lds.assign(nc, 0);
+  P.small.clear();
+  P.small_fwd_lo.assign(nc, 0);
+  P.small_fwd_hi.assign(nc, 0);
+  P.small_grad_lo.assign(nc, 0);
+  P.small_grad_hi.assign(nc, 0);
+  P.lds_elems = 0;
+  if (budget <= 0) return;
+  for (size_t c = 0; c < nc; ++c) {
+    const Cone& C = P.cones[c];
+    const ConeProg& G = progs[c];
+    std::unordered_map<int64_t, int64_t> goff;  // arena offsets (relative to the cone) of its buffers
+    for (const BufLife& B : C.bufs) goff[B.code] = B.off;
+    // gradient program: forward steps, the seeding result, adjoint steps
+    std::vector<const OpDesc*> prog;
+    bool ok = C.lam_size <= budget;
+    for (const OpDesc& d : G.fwd) prog.push_back(&d);
+    const size_t fwd_end = prog.size();
+    for (const OpDesc& d : G.adj) prog.push_back(&d);
+    for (const OpDesc* d : prog) {
+      if (d->kind == OP_CONTRACT) {
+        ok = ok && d->nbits <= 15 && d->nbits <= T.seq_max_bits && d->n_in <= 8 && !(d->flags & F_ATOMIC);
+        for (int i = 0; i < d->n_in; ++i) ok = ok && is_code(d->in_off[i]) && code_kind(d->in_off[i]) != BK_LAMADJ;
+        ok = ok && is_code(d->out_off) && code_kind(d->out_off) != BK_LAM;
+      } else if (d->kind != OP_RESULT) {
+        ok = false;  // zeroing, fused adjoints: wide steps
+      }
+    }
+    if (!ok) continue;
+    auto gout = [&](int64_t code) { return code_kind(code) == BK_LAMADJ; };
+    // lifetimes over the program; the leaf block sits at LDS offset 0 as in the arena
+    struct L {
+      int64_t size;
+      int def = -1, last = -1;
+      int64_t off = -1;
+    };
+    std::unordered_map<int64_t, L> bufs;
+    auto touch = [&](int64_t code, int t) {
+      if (code_kind(code) == BK_LAM || gout(code)) return;
+      L& B = bufs[code];
+      if (B.def < 0) {
+        B.def = t;
+        B.size = int64_t(1) << C.buckets[code_bucket(code)].out_rank();
+      }
+      B.last = std::max(B.last, t);
+    };
+    for (size_t t = 0; t < prog.size(); ++t) {
+      const OpDesc& d = *prog[t];
+      if (d.kind == OP_CONTRACT) {
+        for (int i = 0; i < d.n_in; ++i) touch(d.in_off[i], (int)t);
+        touch(d.out_off, (int)t);
+      } else if (d.kind == OP_RESULT) {
+        for (int i = 0; i < 2 * d.n_in; ++i) touch(d.in_off[i], (int)t);
+      }
+    }
+    std::vector<int64_t> order;
+    for (auto& kv : bufs) order.push_back(kv.first);
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return bufs[a].def != bufs[b].def ? bufs[a].def < bufs[b].def : a < b;
+    });
+    const int64_t base0 = C.lam_size;
+    int64_t peak = base0;
+    std::vector<int64_t> live;
+    for (int64_t code : order) {
+      L& B = bufs[code];
+      live.erase(std::remove_if(live.begin(), live.end(), [&](int64_t x) { return bufs[x].last < B.def; }),
+                 live.end());
+      std::vector<std::pair<int64_t, int64_t>> used;
+      for (int64_t x : live) used.push_back({bufs[x].off, bufs[x].off + bufs[x].size});
+      std::sort(used.begin(), used.end());
+      int64_t cand = base0;
+      for (auto& u : used) {
+        if (cand + B.size <= u.first) break;
+        cand = std::max(cand, u.second);
+      }
+      B.off = cand;
+      peak = std::max(peak, cand + B.size);
+      live.push_back(code);
+    }
+    if (peak > budget || peak > 65535) continue;
+    auto lds = [&](int64_t code) -> uint16_t {
+      return (uint16_t)(code_kind(code) == BK_LAM ? goff.at(code) : bufs.at(code).off);
+    };
+    struct Rng {
+      int64_t lo, hi;
+    };
+    auto range = [&](int64_t code) -> Rng {
+      if (code_kind(code) == BK_LAM) {
+        const int64_t o = goff.at(code);
+        return {o, o + (int64_t(1) << C.buckets[code_bucket(code)].lam_rank())};
+      }
+      return {bufs.at(code).off, bufs.at(code).off + bufs.at(code).size};
+    };
+    auto emit = [&](const OpDesc& d, bool grad_result) {
+      SmallOp s;
+      std::memset(&s, 0, sizeof(s));
+      s.cone = (int32_t)c;
+      if (d.kind == OP_CONTRACT) {
+        s.kind = S_CONTRACT;
+        s.n_in = (uint8_t)d.n_in;
+        s.nbits = (uint8_t)d.nbits;
+        s.n_out = (uint8_t)__builtin_popcount(d.out_mask);
+        // dimensions: output bits, then summed bits, each in union order
+        int dims[16], nd = 0;
+        for (int u = 0; u < d.nbits; ++u)
+          if ((d.out_mask >> u) & 1u) dims[nd++] = u;
+        for (int u = 0; u < d.nbits; ++u)
+          if (!((d.out_mask >> u) & 1u)) dims[nd++] = u;
+        for (int i = 0; i < d.n_in; ++i) {
+          uint64_t sh = ~uint64_t(0);
+          for (int j = 0; j < nd; ++j)
+            if ((d.in_mask[i] >> dims[j]) & 1u) {
+              const uint64_t r = (uint64_t)__builtin_popcount(d.in_mask[i] & ((1u << dims[j]) - 1u));
+              sh &= ~(uint64_t(0xf) << (4 * j));
+              sh |= r << (4 * j);
+            }
+          s.shift[i] = sh;
+          s.in_off[i] = lds(d.in_off[i]);
+        }
+        if (gout(d.out_off)) {
+          s.flags |= SF_GOUT;
+          s.gout = C.base + goff.at(d.out_off);
+        } else {
+          s.out_off = lds(d.out_off);
+        }
+      } else {  // OP_RESULT
+        s.kind = S_RESULT;
+        s.n_in = (uint8_t)d.n_in;
+        for (int i = 0; i < d.n_in; ++i) s.in_off[i] = lds(d.in_off[i]);
+        if (grad_result) {
+          s.flags |= SF_GRAD;
+          for (int i = 0; i < d.n_in; ++i) s.in_off[4 + i] = lds(d.in_off[d.n_in + i]);
+        }
+      }
+      return s;
+    };
+    // one program: the leaf-block copy, then the ops; barriers from the LDS
+    // read / write sets since the last one; the ops of one stage (between
+    // barriers) spread over the wavefronts, largest first onto the least loaded
+    auto emit_range = [&](const std::vector<std::pair<const OpDesc*, bool>>& ops) {
+      SmallOp cp;
+      std::memset(&cp, 0, sizeof(cp));
+      cp.kind = S_COPYIN;
+      cp.cone = (int32_t)c;
+      cp.gout = C.lam_base;
+      cp.aux1 = (int32_t)C.lam_size;
+      P.small.push_back(cp);
+      std::vector<Rng> dirty, rdset;
+      auto hit = [](const std::vector<Rng>& v, const Rng& x) {
+        for (const Rng& r : v)
+          if (x.lo < r.hi && r.lo < x.hi) return true;
+        return false;
+      };
+      dirty.push_back({0, C.lam_size});  // the copy-in
+      std::vector<size_t> stage;         // indices into P.small of the open stage
+      auto close_stage = [&]() {
+        std::vector<double> load(nwaves, 0.0);
+        std::vector<size_t> by_size(stage);
+        auto cost = [&](size_t k) {
+          const SmallOp& o = P.small[k];
+          return o.kind == S_CONTRACT ? std::ldexp(1.0, o.nbits) * o.n_in + 256.0 : 64.0;
+        };
+        std::stable_sort(by_size.begin(), by_size.end(), [&](size_t a, size_t b) { return cost(a) > cost(b); });
+        for (size_t k : by_size) {
+          const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          P.small[k].wave = (uint8_t)w;
+          load[w] += cost(k);
+        }
+        stage.clear();
+      };
+      for (auto& pr : ops) {
+        const OpDesc& d = *pr.first;
+        std::vector<Rng> rd, wr;
+        if (d.kind == OP_CONTRACT) {
+          for (int i = 0; i < d.n_in; ++i) rd.push_back(range(d.in_off[i]));
+          if (!gout(d.out_off)) wr.push_back(range(d.out_off));
+        } else {
+          for (int i = 0; i < d.n_in; ++i) rd.push_back(range(d.in_off[i]));
+          if (pr.second)
+            for (int i = 0; i < d.n_in; ++i) wr.push_back(range(d.in_off[d.n_in + i]));
+        }
+        bool need = false;
+        for (const Rng& r : rd) need |= hit(dirty, r);
+        for (const Rng& r : wr) need |= hit(dirty, r) || hit(rdset, r);
+        SmallOp so = emit(d, pr.second);
+        if (need) {
+          close_stage();
+          so.flags |= SF_SYNC;
+          dirty.clear();
+          rdset.clear();
+        }
+        dirty.insert(dirty.end(), wr.begin(), wr.end());
+        rdset.insert(rdset.end(), rd.begin(), rd.end());
+        stage.push_back(P.small.size());
+        P.small.push_back(so);
+      }
+      close_stage();
+    };
+    std::vector<std::pair<const OpDesc*, bool>> fwd, grad;
+    for (size_t t = 0; t < fwd_end; ++t) fwd.push_back({prog[t], false});
+    fwd.push_back({&G.result, false});
+    for (size_t t = 0; t < prog.size(); ++t) grad.push_back({prog[t], prog[t]->kind == OP_RESULT});
+    P.small_fwd_lo[c] = (int32_t)P.small.size();
+    emit_range(fwd);
+    P.small_fwd_hi[c] = (int32_t)P.small.size();
+    P.small_grad_lo[c] = (int32_t)P.small.size();
+    emit_range(grad);
+    P.small_grad_hi[c] = (int32_t)P.small.size();
+    P.cone_lds[c] = 1;
+    P.lds_elems = std::max(P.lds_elems, peak);
+  }
+}
+
 std::string build_programs(Plan& P, int elem_bytes) {
   P.tune.elem_bytes = elem_bytes;
   P.ops.clear();
@@ -1484,7 +1598,7 @@ std::string build_programs(Plan& P, int elem_bytes) {
     off += C.arena_elems;
   }
   P.arena_grad = P.arena_fwd = align_elems(off, 64);
-  lds_layout(P);
+  small_programs(P, progs);
   // the LDS window also holds the tile sums of LDS-tiled adjoints
   for (const OpDesc& d : P.ops)
     if (d.kind == OP_ADJOINT && (d.flags & F_TILE)) P.lds_elems = std::max<int64_t>(P.lds_elems, d.aux0);
@@ -1517,16 +1631,6 @@ std::string build_programs(Plan& P, int elem_bytes) {
     }
   }
   mark_barriers(P);
-  // copy-in ops of the LDS-resident cones (leaf-product block -> LDS)
-  P.cone_copyin.assign(nc, -1);
-  for (size_t c = 0; c < nc; ++c)
-    if (P.cone_lds[c]) {
-      OpDesc d = blank(OP_COPYIN, (int)c);
-      d.in_off[0] = P.cones[c].lam_base;
-      d.in_off[1] = P.cones[c].lam_size;
-      P.cone_copyin[c] = (int32_t)P.ops.size();
-      P.ops.push_back(d);
-    }
   return "";
 }
 
@@ -1534,7 +1638,7 @@ std::string build_programs(Plan& P, int elem_bytes) {
 static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
   const uint32_t all = (uint32_t)((uint64_t(1) << d.nbits) - 1);
   if (d.nbits <= P.tune.seq_max_bits || !(d.flags & F_WIDE)) return "adjoint op not wide";
-  if (d.n_in < 3 || d.n_in > 4 || d.lds_mask) return "adjoint op with a bad input count or LDS operands";
+  if (d.n_in < 3 || d.n_in > 4) return "adjoint op with a bad input count";
   const bool tiled = d.flags & F_TILE;
   if (d.nu != 0 || d.nl < 1 || d.nl + d.nk + d.nb != d.nbits - 1) return "adjoint op bit partition";
   if (tiled ? (1 << d.nl) != P.tune.threads : d.nl > 6) return "adjoint op lane count";
@@ -1688,7 +1792,7 @@ std::string validate_plan(const Plan& P) {
     if (d.nl + d.nu + d.nk + d.nb != d.nbits - 1) return "op " + S(o) + "bit partition does not cover the union";
     if (d.flags & F_WIDE) {
       if (d.nu > (P.tune.elem_bytes == 8 ? 2 : 1)) return "op " + S(o) + "too many unroll bits";
-      if (d.n_in > 4 || d.lds_mask) return "op " + S(o) + "wide op with more than 4 inputs or LDS operands";
+      if (d.n_in > 4) return "op " + S(o) + "wide op with more than 4 inputs";
       for (int i = 1; i < d.n_in; ++i)
         if (!(d.in_mask[i] & 1u)) return "op " + S(o) + "wide op input without the eliminated index";
       const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
@@ -1728,13 +1832,54 @@ std::string validate_plan(const Plan& P) {
         if (st != got) return "op " + S(o) + "lane shift table mismatch";
       }
     }
-    for (int i = 0; i <= MAXIN; ++i)
-      if ((d.lds_mask >> i) & 1) {
-        const int64_t sz = int64_t(1) << __builtin_popcount(i == MAXIN ? d.out_mask : d.in_mask[i]);
-        if (i != MAXIN && i >= d.n_in) return "op " + S(o) + "LDS bit of a missing input";
-        if (d.lds_off[i] < 0 || d.lds_off[i] + sz > P.lds_elems) return "op " + S(o) + "LDS operand out of the window";
-        if ((d.lds_off[i] & 1) && ((i == MAXIN ? d.out_mask : d.in_mask[i]) & 1)) return "op " + S(o) + "odd LDS pair";
+  }
+  // LDS-resident programs: every operand inside the window; each input's
+  // dimensions map one to one onto its element bits
+  for (size_t c = 0; c < P.cones.size(); ++c) {
+    if (!P.cone_lds[c]) continue;
+    for (int r = 0; r < 2; ++r) {
+      const int32_t lo = r ? P.small_grad_lo[c] : P.small_fwd_lo[c], hi = r ? P.small_grad_hi[c] : P.small_fwd_hi[c];
+      if (lo >= hi || hi > (int32_t)P.small.size()) return "cone " + S(c) + "empty LDS program";
+      for (int32_t k = lo; k < hi; ++k) {
+        const SmallOp& d = P.small[k];
+        auto in_window = [&](int64_t off, int64_t n) { return off >= 0 && off + n <= P.lds_elems; };
+        if (d.cone != (int32_t)c) return "LDS op " + S(k) + "of another cone";
+        if (d.kind == S_CONTRACT) {
+          if (d.nbits > 15 || d.n_out > d.nbits || d.n_in < 1 || d.n_in > 8) return "LDS op " + S(k) + "shape";
+          if (d.flags & SF_GOUT) {
+            if (d.gout < 0 || d.gout + (int64_t(1) << d.n_out) > P.arena_grad)
+              return "LDS op " + S(k) + "global output out of the arena";
+          } else if (!in_window(d.out_off, int64_t(1) << d.n_out)) {
+            return "LDS op " + S(k) + "output out of the window";
+          }
+          for (int i = 0; i < d.n_in; ++i) {
+            uint32_t seen = 0;
+            int rank = 0;
+            for (int j = 0; j < d.nbits; ++j) {
+              const int sh = (int)((d.shift[i] >> (4 * j)) & 0xf);
+              if (sh == 0xf) continue;
+              if (sh >= d.nbits || ((seen >> sh) & 1u)) return "LDS op " + S(k) + "input dimension map";
+              seen |= 1u << sh;
+              ++rank;
+            }
+            for (int j = d.nbits; j < 16; ++j)
+              if (((d.shift[i] >> (4 * j)) & 0xf) != 0xf) return "LDS op " + S(k) + "dimension beyond the union";
+            if (seen != (1u << rank) - 1u) return "LDS op " + S(k) + "input element bits not contiguous";
+            if (!in_window(d.in_off[i], int64_t(1) << rank)) return "LDS op " + S(k) + "input out of the window";
+          }
+        } else if (d.kind == S_COPYIN) {
+          if (k != lo || !in_window(0, d.aux1) || d.gout != P.cones[c].lam_base || d.aux1 != P.cones[c].lam_size)
+            return "LDS op " + S(k) + "leaf-block copy";
+        } else if (d.kind == S_RESULT) {
+          if (d.n_in > 4) return "LDS op " + S(k) + "more than 4 scalars";
+          for (int i = 0; i < d.n_in; ++i)
+            if (!in_window(d.in_off[i], 1) || ((d.flags & SF_GRAD) && !in_window(d.in_off[4 + i], 1)))
+              return "LDS op " + S(k) + "scalar out of the window";
+        } else {
+          return "LDS op " + S(k) + "unknown kind";
+        }
       }
+    }
   }
   return "";
 }
@@ -1745,6 +1890,21 @@ void build_items(Plan& P, bool grad) {
   (grad ? P.items_grad : P.items_fwd) = std::move(q.items);
   (grad ? P.node_init_grad : P.node_init_fwd) = std::move(q.init);
   (grad ? P.succ_grad : P.succ_fwd) = std::move(q.succ);
+  // LDS-resident cones: one workgroup each, the longest programs first
+  auto& sm = grad ? P.small_items_grad : P.small_items_fwd;
+  sm.clear();
+  std::vector<std::pair<int32_t, int32_t>> r;
+  for (size_t c = 0; c < P.cones.size(); ++c)
+    if (!P.cone_lds.empty() && P.cone_lds[c])
+      r.push_back(grad ? std::make_pair(P.small_grad_lo[c], P.small_grad_hi[c])
+                       : std::make_pair(P.small_fwd_lo[c], P.small_fwd_hi[c]));
+  std::stable_sort(r.begin(), r.end(), [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+    return a.second - a.first > b.second - b.first;
+  });
+  for (auto& x : r) {
+    sm.push_back(x.first);
+    sm.push_back(x.second);
+  }
 }
 
 void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& keep, Queue& q) {
@@ -1755,8 +1915,8 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
   items.clear();
   init.clear();
   succ.clear();
-  // a filtered queue runs a subset of ops from global memory (never LDS-resident)
-  const bool use_lds = !keep;
+  // LDS-resident cones run in their own kernel, not from this queue
+  auto in_queue = [&](size_t c) { return P.cone_lds.empty() || !P.cone_lds[c]; };
   // a segment is up to two physical op ranges run in sequence (a cone's
   // gradient program is its forward range followed by its adjoint range)
   struct Seg {
@@ -1768,6 +1928,7 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
   const size_t nc = P.cones.size();
   std::vector<std::vector<Seg>> segs(nc);
   for (size_t c = 0; c < nc; ++c) {
+    if (!in_queue(c)) continue;
     std::vector<std::pair<int32_t, int32_t>> ranges;
     if (grad) {
       ranges.push_back({P.cone_fwd_lo[c], P.cone_fwd_hi[c]});
@@ -1914,15 +2075,12 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
       }
       const int32_t wait_node = r.seg > 0 ? node : -1;
       if (!g.wide) {
-        // a cone that runs LDS-resident is one narrow segment
-        const bool lds = use_lds && !P.cone_lds.empty() && P.cone_lds[r.cone] && segs[r.cone].size() == 1;
-        const int32_t cp = lds ? P.cone_copyin[r.cone] : -1;
-        items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, cp, {0, 0}});
+        items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, {0, 0, 0}});
       } else {
         const int64_t tb = g.per_item;
         const int64_t b = (int64_t)r.item * tb;
         items.push_back({g.r[0], g.r[1], -1, -1, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node,
-                         slo, shi, -1, {0, 0}});
+                         slo, shi, {0, 0, 0}});
       }
       running.push({now + item_us[r.cone][r.seg], r.cone, r.seg});
       --free_w;

@@ -102,12 +102,13 @@ struct TuneParams {
   int unroll_cap = 1;       // output bits handled inside one thread of a wide op (<= 1)
   int par_bits = 21;        // a wide op aims at >= 2^par_bits threads
   int elem_bytes = 8;       // 8: complex64, 16: complex128 (set by build_programs)
-  int lds_kb = 64;          // LDS window for LDS-resident cones (0: never)
+  int lds_kb = 96;          // LDS window cap for LDS-resident cones (0: never)
   int merge_bits = 12;       // merge a bucket into its consumer while the merged union has <= this many bits (0: off)
   int merge_lam_bits = 7;   // ... and its leaf-product table has <= this many bits
   int lane_low = 1;         // wide ops: lanes on the lowest union bits (1) or the lowest output bits (0)
   int fuse_adjoint = 1;     // wide buckets: every input adjoint in one pass where a loop-bit group fits (1), also
                             // LDS tiles for the others (2), or one op per input (0)
+  int lds_threads = 256;    // workgroup size of the kernel that runs the LDS-resident cones
 };
 
 struct Plan {
@@ -123,8 +124,10 @@ struct Plan {
   std::vector<LeafRef> leafrefs;
   int32_t leaf_lo = 0, leaf_hi = 0;    // all OP_LEAF ops (run before the sweep)
   int32_t lgrad_lo = 0, lgrad_hi = 0;  // all OP_LEAFGRAD ops (run after the adjoint sweep)
-  std::vector<char> cone_lds;          // cone runs LDS-resident in the persistent sweep
-  std::vector<int32_t> cone_copyin;    // its OP_COPYIN op (-1: none)
+  std::vector<char> cone_lds;          // cone runs LDS-resident in the persistent sweep (as a SmallOp program)
+  std::vector<SmallOp> small;          // LDS-resident programs of those cones
+  std::vector<int32_t> small_fwd_lo, small_fwd_hi;    // per cone: forward-only program in `small`
+  std::vector<int32_t> small_grad_lo, small_grad_hi;  // per cone: forward + adjoint program
   int64_t lds_elems = 0;               // largest LDS window needed (elements)
   int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
   int64_t mem_budget = 0;           // arena budget in elements (0: unlimited)
@@ -133,6 +136,8 @@ struct Plan {
   std::vector<QItem> items_fwd, items_grad;
   std::vector<int32_t> node_init_fwd, node_init_grad;   // initial dependency counts
   std::vector<int32_t> succ_fwd, succ_grad;             // successor node lists (CSR payload)
+  // LDS-resident cones: (lo, hi) ranges into `small`, one per cone, longest first
+  std::vector<int32_t> small_items_fwd, small_items_grad;
   int32_t max_width = 0;
 };
 
@@ -165,7 +170,8 @@ CostEstimate cost_model(int n, const std::vector<std::pair<int32_t, int32_t>>& e
 // budget requires it) and resolves all operand offsets.
 std::string build_programs(Plan& P, int elem_bytes);
 // Persistent-queue items for the forward (grad = false) or forward + adjoint
-// program; items are in topological order.
+// program; items are in topological order.  Cones that run LDS-resident are
+// not in the queue: they get one (lo, hi) range each in small_items_*.
 void build_items(Plan& P, bool grad);
 // The same queue construction into q; with `keep`, only the ops it accepts
 // (chained per cone in program order, never LDS-resident): a sub-sweep for

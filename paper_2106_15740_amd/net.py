@@ -244,12 +244,16 @@ class QaoaNet:
                                             C.byref(b), C.byref(ms), C.byref(n)))
         return b.value, ms.value, n.value
 
-    def time_wide_sweep(self, min_width: int = 20, with_grad: bool = True, reps: int = 3) -> dict:
-        """In-sweep rate of the buckets of output rank >= min_width: their ops
-        as one persistent launch of their own (after a sweep)."""
+    def time_wide_sweep(self, min_width: int = 20, with_grad: bool = True, reps: int = 3, max_width: int = 0,
+                        kinds: int = 0) -> dict:
+        """In-sweep rate of the buckets of output rank in [min_width,
+        max_width] (0: unbounded): their ops (kinds: bit 0 forward, bit 1
+        single-input adjoints, bit 2 fused adjoints; 0 all) as one persistent
+        launch of their own (after a sweep)."""
         ws = self._workspace(with_grad)
         b, ms, n, it = C.c_double(), C.c_double(), C.c_int64(), C.c_int64()
-        L.check(self._lib.qtn_time_wide_sweep(self.handle, int(bool(with_grad)), int(min_width),
+        L.check(self._lib.qtn_time_wide_sweep(self.handle, int(bool(with_grad)), int(min_width), int(max_width),
+                                              int(kinds),
                                               C.c_void_p(ws.data_ptr()), ws.numel(), self._stream(), int(reps),
                                               C.byref(b), C.byref(ms), C.byref(n), C.byref(it)))
         return {"alg_bytes": b.value, "ms": ms.value, "ops": n.value, "items": it.value}
