@@ -102,6 +102,9 @@ typedef struct {
                                inputs t (rank <= 2 leaves left out); adjoint s * sum_b (2^rank(out_b) + 2 sum_t
                                2^rank(t)) (read the output adjoint and the stored inputs, write the input adjoints) */
   double bwd_bytes_bucket;
+  size_t pinned_bytes;      /* arena bytes of every cone's leaf tables and their adjoints (never shared) */
+  size_t max_cone_dynamic;  /* largest arena bytes one cone needs beyond them, keeping every output; a memory
+                               budget below pinned_bytes + this makes the planner recompute */
 } qtn_info;
 
 /* Context bound to HIP device `device` (hipSetDevice is called on it).  Owns a
@@ -199,13 +202,18 @@ qtn_status qtn_cone_stats(const qtn_net* net, int32_t* width, int32_t* n_qubits,
  * QTN_OK or QTN_EINVAL with the first violation in qtn_last_error(). */
 qtn_status qtn_validate_plan(const qtn_net* net);
 
-/* Checkpointed adjoint: limit the workspace to about `bytes` (0: no limit).
- * While the arena does not fit, the largest bucket output of the largest light
- * cone whose producer reads only kept outputs is dropped after the forward
- * sweep and recomputed by the adjoint sweep right before it is needed
- * (results are unchanged; qtn_info reports the extra traffic).  QTN_ENOMEM
- * (and no limit) when even full recomputation cannot meet it.  Rebuilds and
- * re-uploads the device program. */
+/* Memory admission and checkpointed adjoint: limit the workspace to about
+ * `bytes` (0: no limit).  Every cone's leaf tables and their adjoints keep
+ * their own place; the rest of each cone's working set (its dynamic region)
+ * goes into a shared area: the batched sweep admits cones into it in queue
+ * order, a cone waiting for the cones that last held its region.  A cone
+ * whose dynamic region alone exceeds the area drops bucket outputs after the
+ * forward sweep (largest first, where that shrinks the region) and the
+ * adjoint sweep recomputes them right before their first use, after the
+ * dropped outputs they read (results are unchanged; qtn_info reports the
+ * recomputed outputs and their extra traffic).  QTN_ENOMEM (and no limit)
+ * when even that cannot meet the budget.  Rebuilds and re-uploads the
+ * device program. */
 qtn_status qtn_set_memory_budget(qtn_net* net, size_t bytes);
 
 /* Tile parameters; changing them rebuilds and re-uploads the device program. */

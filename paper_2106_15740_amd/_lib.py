@@ -61,7 +61,8 @@ class Info(C.Structure):
                 ("bwd_bytes", C.c_double), ("fwd_flops", C.c_double), ("ws_fwd", C.c_size_t),
                 ("ws_grad", C.c_size_t), ("n_lds_cones", C.c_int32), ("lds_window", C.c_int32),
                 ("n_recomputed", C.c_int64), ("rec_bytes", C.c_double), ("arena_keep_all", C.c_size_t),
-                ("n_steps", C.c_int64), ("fwd_bytes_bucket", C.c_double), ("bwd_bytes_bucket", C.c_double)]
+                ("n_steps", C.c_int64), ("fwd_bytes_bucket", C.c_double), ("bwd_bytes_bucket", C.c_double),
+                ("pinned_bytes", C.c_size_t), ("max_cone_dynamic", C.c_size_t)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

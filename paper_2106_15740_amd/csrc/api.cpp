@@ -156,12 +156,12 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 }
 
 qtn_status rebuild_programs(qtn_net* n) {
-  std::string err = build_programs(n->P, n->elem);
-  if (!err.empty()) return fail(QTN_EUNSUPPORTED, err);
   // workgroups resident at once: 16 wavefronts per compute unit (the
   // persistent kernel's register budget), at most the launched grid
   const int waves_per_wg = std::max(1, n->P.tune.threads / 64);
   n->P.sched_workers = std::max(1, std::min(n->grid, n->ctx->n_cu * std::max(1, 16 / waves_per_wg)));
+  std::string err = build_programs(n->P, n->elem);
+  if (!err.empty()) return fail(QTN_EUNSUPPORTED, err);
   build_items(n->P, false);
   build_items(n->P, true);
   n->max_nin = 1;
@@ -730,6 +730,8 @@ qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
     for (char r : C.recompute) out->n_recomputed += r ? 1 : 0;
     out->rec_bytes += C.rec_bytes;
     out->arena_keep_all += (size_t)C.keep_all_elems * n->elem;
+    out->pinned_bytes += (size_t)((C.dyn_start + 63) / 64 * 64) * n->elem;
+    out->max_cone_dynamic = std::max(out->max_cone_dynamic, (size_t)(C.keep_all_elems - C.dyn_start) * n->elem);
   }
   return QTN_OK;
 }

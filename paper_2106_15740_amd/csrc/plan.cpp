@@ -1035,16 +1035,20 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
     ref_n[b] = d.aux1;
     G.leaf.push_back(d);
   }
-  // forward contraction of bucket b, writing `out` (its output or a recomputation)
+  // forward contraction of bucket b, writing `out` (its output or a
+  // recomputation, which reads the recomputed values of inputs that were
+  // dropped too)
   auto fwd_op = [&](size_t b, int64_t out, double* bytes, double* flops) -> OpDesc {
     const Bucket& Bk = C.buckets[b];
     const int nbits = Bk.nbits();
+    const bool rec = code_kind(out) == BK_REC;
     OpDesc d = blank(OP_CONTRACT, (int)c);
     d.nbits = nbits;
     int ni = 0;
     double in_elems = 0;
     for (size_t t = 0; t < Bk.in_bkt.size(); ++t) {
-      d.in_off[ni] = buf_code(BK_OUT, Bk.in_bkt[t]);
+      const int pb = Bk.in_bkt[t];
+      d.in_off[ni] = buf_code(rec && C.recompute[pb] ? BK_REC : BK_OUT, pb);
       d.in_mask[ni] = Bk.in_mask[t];
       in_elems += std::ldexp(1.0, __builtin_popcount(Bk.in_mask[t]));
       ++ni;
@@ -1088,6 +1092,16 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
   OpDesc rg = G.result;
   rg.flags = F_GRAD;
   G.adj.push_back(rg);
+  // a dropped output is recomputed once, right before its first use in the
+  // adjoint sweep, after the dropped outputs it reads (recursively); the
+  // recomputed value then lives until its last use
+  std::vector<char> made(nb, 0);
+  std::function<void(int)> ensure = [&](int b) {
+    if (!C.recompute[b] || made[b]) return;
+    for (int pb : C.buckets[b].in_bkt) ensure(pb);
+    push_zeroed(G.adj, fwd_op(b, buf_code(BK_REC, b), &C.rec_bytes, nullptr));
+    made[b] = 1;
+  };
   for (size_t bb = nb; bb-- > 0;) {
     const Bucket& Bk = C.buckets[bb];
     const int nbits = Bk.nbits();
@@ -1095,10 +1109,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
     const uint32_t all = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u);
     const int nin = (int)Bk.in_bkt.size();
     // inputs dropped after the forward sweep are recomputed before their use
-    for (int t = 0; t < nin; ++t) {
-      const int pb = Bk.in_bkt[t];
-      if (C.recompute[pb]) push_zeroed(G.adj, fwd_op(pb, buf_code(BK_REC, pb), &C.rec_bytes, nullptr));
-    }
+    for (int t = 0; t < nin; ++t) ensure(Bk.in_bkt[t]);
     auto in_code = [&](int t) {
       const int pb = Bk.in_bkt[t];
       return buf_code(C.recompute[pb] ? BK_REC : BK_OUT, pb);
@@ -1246,6 +1257,7 @@ int64_t alloc_cone(Cone& C, const ConeProg& G) {
       off += B.size;
     }
   const int64_t base0 = align_elems(off, 64);
+  C.dyn_start = base0;
   std::vector<size_t> order;
   for (size_t i = 0; i < C.bufs.size(); ++i) {
     const int k = code_kind(C.bufs[i].code);
@@ -1276,26 +1288,14 @@ int64_t alloc_cone(Cone& C, const ConeProg& G) {
   return C.arena_elems;
 }
 
-// The largest kept bucket output whose producer reads only kept outputs, so
-// that its recomputation is one contraction deep; -1 if none.
-int recompute_candidate(const Cone& C) {
-  int best = -1;
-  for (size_t b = 0; b < C.buckets.size(); ++b) {
-    const Bucket& Bk = C.buckets[b];
-    if (C.recompute[b] || Bk.consumer < 0 || Bk.out_rank() < 4) continue;
-    bool ok = true;
-    for (int pb : Bk.in_bkt) ok &= !C.recompute[pb];
-    for (size_t x = 0; x < C.buckets.size() && ok; ++x)  // nothing recomputed may read it
-      if (C.recompute[x])
-        for (int pb : C.buckets[x].in_bkt) ok &= pb != (int)b;
-    if (ok && (best < 0 || Bk.out_rank() > C.buckets[best].out_rank())) best = (int)b;
-  }
-  return best;
-}
-
-int64_t resolve_off(const Cone& C, const std::unordered_map<int64_t, int64_t>& where, int64_t v) {
+// Absolute arena offset of a coded operand: a leaf table or its adjoint in
+// the cone's pinned part, anything else in its dynamic region.
+int64_t resolve_off(const Plan& P, const Cone& C, const std::unordered_map<int64_t, int64_t>& where, int64_t v) {
   if (!is_code(v)) return v;
-  return C.base + where.at(v);
+  const int64_t off = where.at(v);
+  const int k = code_kind(v);
+  if (k == BK_LAM || k == BK_LAMADJ) return C.base + off;
+  return P.dyn_off + C.dyn_base + (off - C.dyn_start);
 }
 
 }  // namespace
@@ -1530,6 +1530,8 @@ static void small_programs(Plan& P, const std::vector<ConeProg>& progs) {
   }
 }
 
+static bool admit_cones(Plan& P, int64_t area);
+
 std::string build_programs(Plan& P, int elem_bytes) {
   P.tune.elem_bytes = elem_bytes;
   P.ops.clear();
@@ -1549,25 +1551,42 @@ std::string build_programs(Plan& P, int elem_bytes) {
     total += alloc_cone(P.cones[c], progs[c]);
     P.cones[c].keep_all_elems = P.cones[c].arena_elems;
   }
-  // memory budget: drop the largest recomputable outputs of the largest
-  // cones until the arena fits
-  while (P.mem_budget > 0 && total > P.mem_budget) {
-    size_t worst = nc;
-    int cand = -1;
+  // memory budget: every cone's pinned part (leaf tables and their
+  // adjoints, written before and read after the sweep) side by side, the
+  // dynamic regions in a shared area that the batched sweep admits cones
+  // into; a cone whose dynamic region alone exceeds the area drops bucket
+  // outputs after the forward sweep (largest first, kept when the region
+  // shrinks) and recomputes them in the adjoint sweep
+  int64_t pinned = 0;
+  for (size_t c = 0; c < nc; ++c) pinned += align_elems(P.cones[c].dyn_start, 64);
+  const int64_t area = P.mem_budget > 0 ? P.mem_budget - align_elems(pinned, 64) : 0;
+  if (P.mem_budget > 0) {
+    if (area <= 0) return "the memory budget does not hold the leaf tables";
     for (size_t c = 0; c < nc; ++c) {
-      const int b = recompute_candidate(P.cones[c]);
-      if (b >= 0 && (worst == nc || P.cones[c].arena_elems > P.cones[worst].arena_elems)) {
-        worst = c;
-        cand = b;
+      Cone& C = P.cones[c];
+      if (C.arena_elems - C.dyn_start <= area) continue;
+      std::vector<int> cand;
+      for (size_t b = 0; b < C.buckets.size(); ++b)
+        if (C.buckets[b].consumer >= 0 && C.buckets[b].out_rank() >= 4) cand.push_back((int)b);
+      std::stable_sort(cand.begin(), cand.end(),
+                       [&](int a, int b) { return C.buckets[a].out_rank() > C.buckets[b].out_rank(); });
+      for (int b : cand) {
+        if (C.arena_elems - C.dyn_start <= area) break;
+        const int64_t before = C.arena_elems;
+        C.recompute[b] = 1;
+        std::string err = emit_cone(P, c, progs[c]);
+        if (!err.empty()) return err;
+        alloc_cone(C, progs[c]);
+        if (C.arena_elems >= before) {  // no gain: keep the output
+          C.recompute[b] = 0;
+          err = emit_cone(P, c, progs[c]);
+          if (!err.empty()) return err;
+          alloc_cone(C, progs[c]);
+        }
       }
+      if (C.arena_elems - C.dyn_start > area)
+        return "the gradient sweep does not fit the memory budget even with recomputation";
     }
-    if (worst == nc) return "the gradient sweep does not fit the memory budget even with recomputation";
-    Cone& C = P.cones[worst];
-    const int64_t before = C.arena_elems;
-    C.recompute[cand] = 1;
-    std::string err = emit_cone(P, worst, progs[worst]);
-    if (!err.empty()) return err;
-    total += alloc_cone(C, progs[worst]) - before;
   }
   // assemble the op list (operands still coded)
   std::vector<OpDesc> leaf_ops, lgrad_ops;
@@ -1589,16 +1608,36 @@ std::string build_programs(Plan& P, int elem_bytes) {
   P.lgrad_lo = P.leaf_hi;
   P.ops.insert(P.ops.end(), lgrad_ops.begin(), lgrad_ops.end());
   P.lgrad_hi = (int32_t)P.ops.size();
-  // cone bases, LDS windows (on codes), then absolute offsets
+  // pinned parts side by side, then the dynamic area
   int64_t off = 0;
   for (size_t c = 0; c < nc; ++c) {
     Cone& C = P.cones[c];
     C.base = off;
     C.lam_base = off;
-    off += C.arena_elems;
+    off += align_elems(C.dyn_start, 64);
   }
-  P.arena_grad = P.arena_fwd = align_elems(off, 64);
+  P.dyn_off = align_elems(off, 64);
   small_programs(P, progs);
+  // dynamic regions: under a budget, placed by the admission schedule of the
+  // batched sweep; else side by side.  LDS-resident cones use none in the
+  // batched sweep (the plain path runs one cone at a time): offset 0.
+  P.cone_pred.clear();
+  int64_t dyn_end = 0;
+  if (P.mem_budget > 0) {
+    P.sched_workers = std::max(1, P.sched_workers);
+    if (!admit_cones(P, area)) return "the gradient sweep does not fit the memory budget even with recomputation";
+    for (size_t c = 0; c < nc; ++c)
+      dyn_end = std::max(dyn_end, P.cones[c].dyn_base + P.cones[c].arena_elems - P.cones[c].dyn_start);
+  } else {
+    for (size_t c = 0; c < nc; ++c) {
+      Cone& C = P.cones[c];
+      const int64_t n = C.arena_elems - C.dyn_start;
+      C.dyn_base = P.cone_lds[c] ? 0 : dyn_end;
+      dyn_end = std::max(dyn_end, C.dyn_base + n);
+      if (!P.cone_lds[c]) dyn_end = align_elems(dyn_end, 64);
+    }
+  }
+  P.arena_grad = P.arena_fwd = align_elems(P.dyn_off + dyn_end, 64);
   // the LDS window also holds the tile sums of LDS-tiled adjoints
   for (const OpDesc& d : P.ops)
     if (d.kind == OP_ADJOINT && (d.flags & F_TILE)) P.lds_elems = std::max<int64_t>(P.lds_elems, d.aux0);
@@ -1611,21 +1650,21 @@ std::string build_programs(Plan& P, int elem_bytes) {
       const auto& W = where[d.cone];
       switch (d.kind) {
         case OP_CONTRACT:
-          for (int i = 0; i < d.n_in; ++i) d.in_off[i] = resolve_off(C, W, d.in_off[i]);
-          d.out_off = resolve_off(C, W, d.out_off);
+          for (int i = 0; i < d.n_in; ++i) d.in_off[i] = resolve_off(P, C, W, d.in_off[i]);
+          d.out_off = resolve_off(P, C, W, d.out_off);
           break;
         case OP_ADJOINT:
           for (int i = 0; i < d.n_in; ++i) {
-            d.in_off[i] = resolve_off(C, W, d.in_off[i]);
-            if ((d.adj_sel >> i) & 1u) d.adj_off[i] = resolve_off(C, W, d.adj_off[i]);
+            d.in_off[i] = resolve_off(P, C, W, d.in_off[i]);
+            if ((d.adj_sel >> i) & 1u) d.adj_off[i] = resolve_off(P, C, W, d.adj_off[i]);
           }
           break;
         case OP_RESULT:
-          for (int i = 0; i < 2 * d.n_in; ++i) d.in_off[i] = resolve_off(C, W, d.in_off[i]);
+          for (int i = 0; i < 2 * d.n_in; ++i) d.in_off[i] = resolve_off(P, C, W, d.in_off[i]);
           break;
         case OP_ZERO:
-        case OP_LEAF: d.out_off = resolve_off(C, W, d.out_off); break;
-        case OP_LEAFGRAD: d.in_off[0] = resolve_off(C, W, d.in_off[0]); break;
+        case OP_LEAF: d.out_off = resolve_off(P, C, W, d.out_off); break;
+        case OP_LEAFGRAD: d.in_off[0] = resolve_off(P, C, W, d.in_off[0]); break;
         default: break;
       }
     }
@@ -1685,6 +1724,68 @@ static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
       const uint32_t st = j < d.nl && ((m >> d.zbit[j]) & 1) ? (1u << __builtin_popcount(m & ((1u << d.zbit[j]) - 1))) : 0u;
       const uint32_t got = d.lsh[i][j] == LSH_NONE ? 0u : (1u << d.lsh[i][j]);
       if (st != got) return "adjoint op lane shift table mismatch";
+    }
+  }
+  return "";
+}
+
+// The wait structure of a stored work queue.  A cone's items, in queue
+// order, form runs of equal op ranges (its segments; a wide op's items share
+// one run).  Every run after a cone's first, and the first run of a cone that
+// waits for other cones' memory, waits on one node; the items that release
+// that node are exactly the preceding run (and the last runs of the cones it
+// waits for), all earlier in the queue, and the node's initial count is their
+// number.  Runs that wait on nothing have no releasing items.
+static std::string validate_queue(const Plan& P, bool grad) {
+  const auto& items = grad ? P.items_grad : P.items_fwd;
+  const auto& init = grad ? P.node_init_grad : P.node_init_fwd;
+  const auto& succ = grad ? P.succ_grad : P.succ_fwd;
+  const std::string q = grad ? "gradient queue: " : "forward queue: ";
+  const size_t nc = P.cones.size(), ni = items.size(), nn = init.size();
+  std::vector<std::vector<int32_t>> rel(nn);  // items that release each node
+  for (size_t i = 0; i < ni; ++i) {
+    const QItem& I = items[i];
+    if (I.op_lo < 0 || I.op_hi > (int32_t)P.ops.size() || I.op_lo >= I.op_hi) return q + "bad op range";
+    if (I.succ_lo < 0 || I.succ_hi < I.succ_lo || I.succ_hi > (int32_t)succ.size()) return q + "bad successor range";
+    for (int32_t s = I.succ_lo; s < I.succ_hi; ++s) {
+      if (succ[s] < 0 || succ[s] >= (int32_t)nn) return q + "successor node out of range";
+      rel[succ[s]].push_back((int32_t)i);
+    }
+    if (I.node < -1 || I.node >= (int32_t)nn) return q + "wait node out of range";
+  }
+  for (size_t n = 0; n < nn; ++n)
+    if ((int32_t)rel[n].size() != init[n]) return q + "node " + std::to_string(n) + " count != releasing items";
+  // runs per cone
+  auto same_run = [](const QItem& a, const QItem& b) {
+    return a.op_lo == b.op_lo && a.op_hi == b.op_hi && a.op2_lo == b.op2_lo && a.op2_hi == b.op2_hi;
+  };
+  std::vector<std::vector<std::vector<int32_t>>> runs(nc);
+  for (size_t i = 0; i < ni; ++i) {
+    auto& r = runs[P.ops[items[i].op_lo].cone];
+    if (r.empty() || !same_run(items[r.back().back()], items[i])) r.emplace_back();
+    r.back().push_back((int32_t)i);
+  }
+  const bool gated = P.cone_pred.size() == nc;
+  for (size_t c = 0; c < nc; ++c) {
+    for (size_t k = 0; k < runs[c].size(); ++k) {
+      std::vector<int32_t> need;
+      if (k > 0) need = runs[c][k - 1];
+      if (k == 0 && gated)
+        for (int a : P.cone_pred[c])
+          if (!runs[a].empty()) need.insert(need.end(), runs[a].back().begin(), runs[a].back().end());
+      const int32_t node = items[runs[c][k][0]].node;
+      for (int32_t i : runs[c][k])
+        if (items[i].node != node) return q + "items of one segment wait on different nodes";
+      if (need.empty()) {
+        if (node >= 0 && init[node] != 0) return q + "cone " + std::to_string(c) + " waits on unrelated items";
+        continue;
+      }
+      if (node < 0) return q + "cone " + std::to_string(c) + " segment " + std::to_string(k) + " does not wait";
+      std::vector<int32_t> got = rel[node];
+      std::sort(got.begin(), got.end());
+      std::sort(need.begin(), need.end());
+      if (got != need) return q + "cone " + std::to_string(c) + " segment " + std::to_string(k) + " waits on the wrong items";
+      if (need.back() >= runs[c][k][0]) return q + "an item waits on a later item";
     }
   }
   return "";
@@ -1778,9 +1879,52 @@ std::string validate_plan(const Plan& P) {
         if (A.off < B.off + B.size && B.off < A.off + A.size)
           return "cone " + S(c) + "buffers with overlapping lifetimes share memory";
       }
-    if (C.base < 0 || C.base + C.arena_elems > P.arena_grad) return "cone " + S(c) + "arena out of bounds";
+    if (C.base < 0 || C.base + C.dyn_start > P.dyn_off) return "cone " + S(c) + "pinned part out of bounds";
+    if (C.dyn_base < 0 || P.dyn_off + C.dyn_base + (C.arena_elems - C.dyn_start) > P.arena_grad)
+      return "cone " + S(c) + "dynamic region out of bounds";
+    iv.push_back({C.base, C.base + C.dyn_start});
   }
-  (void)iv;
+  // pinned parts never overlap; dynamic regions of cones run from the work
+  // queue overlap only when one cone waits (through its predecessors) for the
+  // other
+  std::sort(iv.begin(), iv.end(), [](const Iv& a, const Iv& b) { return a.lo < b.lo; });
+  for (size_t i = 1; i < iv.size(); ++i)
+    if (iv[i].lo < iv[i - 1].hi) return "pinned parts of two cones overlap";
+  {
+    const size_t nc = P.cones.size();
+    const bool gated = P.cone_pred.size() == nc;
+    std::vector<std::vector<char>> anc;  // anc[c][a]: c waits for a, directly or not
+    if (gated) {
+      anc.assign(nc, std::vector<char>(nc, 0));
+      std::vector<int> done(nc, 0);
+      std::function<void(int)> visit = [&](int c) {
+        if (done[c]) return;
+        done[c] = 1;
+        for (int a : P.cone_pred[c]) {
+          if (a < 0 || a >= (int)nc || a == c) return;
+          visit(a);
+          anc[c][a] = 1;
+          for (size_t x = 0; x < nc; ++x) anc[c][x] |= anc[a][x];
+        }
+      };
+      for (size_t c = 0; c < nc; ++c) visit((int)c);
+    }
+    std::vector<std::pair<Iv, int>> dv;
+    for (size_t c = 0; c < nc; ++c) {
+      const Cone& C = P.cones[c];
+      if (!P.cone_lds.empty() && P.cone_lds[c]) continue;
+      if (C.arena_elems > C.dyn_start) dv.push_back({{C.dyn_base, C.dyn_base + C.arena_elems - C.dyn_start}, (int)c});
+    }
+    std::sort(dv.begin(), dv.end(), [](const std::pair<Iv, int>& a, const std::pair<Iv, int>& b) {
+      return a.first.lo < b.first.lo;
+    });
+    for (size_t i = 0; i < dv.size(); ++i)
+      for (size_t j = i + 1; j < dv.size() && dv[j].first.lo < dv[i].first.hi; ++j) {
+        const int a = dv[i].second, b = dv[j].second;
+        if (!gated || !(anc[a][b] || anc[b][a]))
+          return "dynamic regions of cones " + S(a, b) + "overlap without an order between them";
+      }
+  }
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const OpDesc& d = P.ops[o];
     if (d.kind == OP_ADJOINT) {
@@ -1881,6 +2025,10 @@ std::string validate_plan(const Plan& P) {
       }
     }
   }
+  for (int g = 0; g < 2; ++g) {
+    const std::string e = validate_queue(P, g == 1);
+    if (!e.empty()) return e;
+  }
   return "";
 }
 
@@ -1907,26 +2055,32 @@ void build_items(Plan& P, bool grad) {
   }
 }
 
-void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& keep, Queue& q) {
+// A cone's program as a chain of segments: a segment is up to two physical op
+// ranges run in sequence by one workgroup (a cone's gradient program is its
+// forward range followed by its adjoint range), or one wide op split into
+// items of per_item blocks.  Durations are estimates for the list schedule: a
+// fixed cost per item and per op plus bytes at a nominal per-workgroup rate.
+struct Seg {
+  int32_t r[4];
+  bool wide;
+  int64_t nblocks;
+  int64_t per_item;  // blocks per item of a wide op
+  int32_t n_items() const { return wide ? (int32_t)((nblocks + per_item - 1) / per_item) : 1; }
+};
+struct Chains {
+  std::vector<std::vector<Seg>> segs;
+  std::vector<std::vector<double>> item_us, span;  // per segment: one item's duration; remaining chain length
+};
+
+static void cone_chains(const Plan& P, bool grad, const std::function<bool(int32_t)>& keep, Chains& ch) {
   const TuneParams& T = P.tune;
-  auto& items = q.items;
-  auto& init = q.init;
-  auto& succ = q.succ;
-  items.clear();
-  init.clear();
-  succ.clear();
-  // LDS-resident cones run in their own kernel, not from this queue
-  auto in_queue = [&](size_t c) { return P.cone_lds.empty() || !P.cone_lds[c]; };
-  // a segment is up to two physical op ranges run in sequence (a cone's
-  // gradient program is its forward range followed by its adjoint range)
-  struct Seg {
-    int32_t r[4];
-    bool wide;
-    int64_t nblocks;
-    int64_t per_item;  // blocks per item of a wide op
-  };
   const size_t nc = P.cones.size();
-  std::vector<std::vector<Seg>> segs(nc);
+  // LDS-resident cones run in their own kernel, not from the queue
+  auto in_queue = [&](size_t c) { return P.cone_lds.empty() || !P.cone_lds[c]; };
+  ch.segs.assign(nc, {});
+  ch.item_us.assign(nc, {});
+  ch.span.assign(nc, {});
+  auto& segs = ch.segs;
   for (size_t c = 0; c < nc; ++c) {
     if (!in_queue(c)) continue;
     std::vector<std::pair<int32_t, int32_t>> ranges;
@@ -1977,22 +2131,6 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
     }
     close();
   }
-  std::vector<std::vector<int32_t>> node_of(nc);
-  int32_t nn = 0;
-  for (size_t c = 0; c < nc; ++c)
-    for (size_t s = 0; s < segs[c].size(); ++s) node_of[c].push_back(nn++);
-  init.assign(nn, 0);
-  auto n_items = [&](const Seg& g) -> int32_t {
-    if (!g.wide) return 1;
-    return (int32_t)((g.nblocks + g.per_item - 1) / g.per_item);
-  };
-  for (size_t c = 0; c < nc; ++c)
-    for (size_t s = 1; s < segs[c].size(); ++s) init[node_of[c][s]] = n_items(segs[c][s - 1]);
-  // Queue order: a list schedule of the segments on the resident workgroups,
-  // longest remaining chain first.  Durations are estimates (a fixed cost per
-  // item and per op plus bytes at a nominal per-workgroup rate); an item
-  // enters the queue only when its predecessor segment has finished in the
-  // schedule, so every item waits only on items earlier in the queue.
   auto op_bytes = [&](const OpDesc& d) -> double {
     double b = 0;
     if (d.kind == OP_CONTRACT) {
@@ -2015,23 +2153,188 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
     const bool red = __builtin_popcount(d.out_mask) < d.nbits - (adj ? 0 : 1);
     return adj ? (red ? 2.6e3 : 6.2e3) : 3.7e3;
   };
-  std::vector<std::vector<double>> item_us(nc), span(nc);  // per segment: one item's duration
   for (size_t c = 0; c < nc; ++c) {
     for (const Seg& g : segs[c]) {
       double t = 2.0;
       if (g.wide) {
         const OpDesc& d = P.ops[g.r[0]];
-        t += op_bytes(d) / (double)n_items(g) / rate(d);
+        t += op_bytes(d) / (double)g.n_items() / rate(d);
       } else {
         for (int r = 0; r < 2; ++r)
           if (g.r[2 * r] >= 0)
             for (int32_t o = g.r[2 * r]; o < g.r[2 * r + 1]; ++o) t += 4.0 + op_bytes(P.ops[o]) / 1.7e3;
       }
-      item_us[c].push_back(t);
+      ch.item_us[c].push_back(t);
     }
-    span[c].assign(segs[c].size() + 1, 0.0);  // remaining chain length from each segment
-    for (size_t s = segs[c].size(); s-- > 0;) span[c][s] = span[c][s + 1] + item_us[c][s];
+    ch.span[c].assign(segs[c].size() + 1, 0.0);
+    for (size_t s = segs[c].size(); s-- > 0;) ch.span[c][s] = ch.span[c][s + 1] + ch.item_us[c][s];
   }
+}
+
+// Memory admission under a workspace budget.  Cones run from the work queue
+// share a dynamic area of `area` elements: the list schedule of the gradient
+// program is simulated with a first-fit allocator, a cone is admitted (its
+// first segment released) once its dynamic region fits, and its region is
+// freed when its last segment ends.  Sets every queued cone's dyn_base and
+// its predecessors: the cones that last held any part of its region (the
+// queue makes it wait for them).  LDS-resident cones keep no region in the
+// batched sweep; they get offset 0 (the plain per-op path runs one cone at a
+// time).  Returns false if some cone's region exceeds the area.
+static bool admit_cones(Plan& P, int64_t area) {
+  const size_t nc = P.cones.size();
+  Chains ch;
+  cone_chains(P, true, nullptr, ch);
+  P.cone_pred.assign(nc, {});
+  struct Piece {
+    int64_t lo, hi;
+    int owner, last;  // owner -1: free
+  };
+  std::vector<Piece> mem{{0, area, -1, -1}};
+  auto dyn = [&](size_t c) { return P.cones[c].arena_elems - P.cones[c].dyn_start; };
+  for (size_t c = 0; c < nc; ++c) {
+    P.cones[c].dyn_base = 0;
+    if (dyn(c) > area) return false;
+  }
+  auto alloc = [&](int c, int64_t size) -> bool {
+    for (size_t i = 0; i < mem.size(); ++i) {
+      if (mem[i].owner >= 0) continue;
+      // a run of free pieces from i covering size (64-element aligned start)
+      const int64_t lo = (mem[i].lo + 63) / 64 * 64;
+      if (lo >= mem[i].hi) continue;
+      size_t j = i;
+      while (j < mem.size() && mem[j].owner < 0 && mem[j].hi < lo + size) ++j;
+      if (j == mem.size() || mem[j].owner >= 0) {
+        i = j;
+        continue;
+      }
+      const int64_t hi = lo + size;
+      // split the first and last pieces, mark the covered ones
+      std::vector<Piece> out(mem.begin(), mem.begin() + i);
+      if (mem[i].lo < lo) out.push_back({mem[i].lo, lo, -1, mem[i].last});
+      std::vector<int> pred;
+      for (size_t k = i; k <= j; ++k) {
+        const int64_t a = std::max(mem[k].lo, lo), b = std::min(mem[k].hi, hi);
+        if (a < b && mem[k].last >= 0) pred.push_back(mem[k].last);
+      }
+      out.push_back({lo, hi, c, c});
+      if (mem[j].hi > hi) out.push_back({hi, mem[j].hi, -1, mem[j].last});
+      out.insert(out.end(), mem.begin() + j + 1, mem.end());
+      mem.swap(out);
+      std::sort(pred.begin(), pred.end());
+      pred.erase(std::unique(pred.begin(), pred.end()), pred.end());
+      P.cone_pred[c] = pred;
+      P.cones[c].dyn_base = lo;
+      return true;
+    }
+    return false;
+  };
+  auto release = [&](int c) {
+    for (Piece& m : mem)
+      if (m.owner == c) m.owner = -1;
+  };
+  struct Ready {
+    double prio;
+    int32_t cone, seg, item;
+    bool operator<(const Ready& o) const {
+      if (prio != o.prio) return prio < o.prio;
+      if (cone != o.cone) return cone > o.cone;
+      return item > o.item;
+    }
+  };
+  struct Done {
+    double t;
+    int32_t cone, seg;
+    bool operator<(const Done& o) const { return t > o.t; }
+  };
+  std::priority_queue<Ready> ready;
+  std::priority_queue<Done> running;
+  std::vector<std::vector<int32_t>> left(nc);
+  auto release_seg = [&](size_t c, size_t s) {
+    const int32_t k = ch.segs[c][s].n_items();
+    left[c][s] = k;
+    for (int32_t it = 0; it < k; ++it) ready.push({ch.span[c][s], (int32_t)c, (int32_t)s, it});
+  };
+  std::vector<int> pending;  // queued cones not yet admitted, longest chain first
+  for (size_t c = 0; c < nc; ++c) {
+    left[c].assign(ch.segs[c].size(), 0);
+    if (!ch.segs[c].empty()) pending.push_back((int)c);
+  }
+  std::stable_sort(pending.begin(), pending.end(), [&](int a, int b) { return ch.span[a][0] > ch.span[b][0]; });
+  auto admit = [&]() {
+    std::vector<int> rest;
+    for (int c : pending) {
+      if (alloc(c, dyn(c)))
+        release_seg(c, 0);
+      else
+        rest.push_back(c);
+    }
+    pending.swap(rest);
+  };
+  admit();
+  double now = 0;
+  int free_w = std::max(1, P.sched_workers);
+  for (;;) {
+    while (free_w > 0 && !ready.empty()) {
+      const Ready r = ready.top();
+      ready.pop();
+      running.push({now + ch.item_us[r.cone][r.seg], r.cone, r.seg});
+      --free_w;
+    }
+    if (running.empty()) break;
+    const Done d = running.top();
+    running.pop();
+    now = d.t;
+    ++free_w;
+    if (--left[d.cone][d.seg] == 0) {
+      if ((size_t)d.seg + 1 < ch.segs[d.cone].size()) {
+        release_seg(d.cone, d.seg + 1);
+      } else {
+        release(d.cone);
+        admit();
+      }
+    }
+  }
+  return pending.empty();
+}
+
+void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& keep, Queue& q) {
+  auto& items = q.items;
+  auto& init = q.init;
+  auto& succ = q.succ;
+  items.clear();
+  init.clear();
+  succ.clear();
+  const size_t nc = P.cones.size();
+  Chains ch;
+  cone_chains(P, grad, keep, ch);
+  const auto& segs = ch.segs;
+  // memory admission (unfiltered queues): cone c starts after its predecessors end
+  const bool gated = !keep && P.cone_pred.size() == nc;
+  std::vector<std::vector<int32_t>> after(nc);  // cones that wait for this one
+  if (gated)
+    for (size_t c = 0; c < nc; ++c)
+      for (int a : P.cone_pred[c]) after[a].push_back((int32_t)c);
+  std::vector<std::vector<int32_t>> node_of(nc);
+  int32_t nn = 0;
+  for (size_t c = 0; c < nc; ++c)
+    for (size_t s = 0; s < segs[c].size(); ++s) node_of[c].push_back(nn++);
+  init.assign(nn, 0);
+  for (size_t c = 0; c < nc; ++c)
+    for (size_t s = 1; s < segs[c].size(); ++s) init[node_of[c][s]] = segs[c][s - 1].n_items();
+  // a gated cone's first node also counts its predecessors' last items
+  std::vector<int32_t> waits(nc, 0);
+  if (gated)
+    for (size_t c = 0; c < nc; ++c)
+      for (int a : P.cone_pred[c])
+        if (!segs[c].empty() && !segs[a].empty()) {
+          init[node_of[c][0]] += segs[a].back().n_items();
+          ++waits[c];
+        }
+  // Queue order: a list schedule of the segments on the resident workgroups,
+  // longest remaining chain first; an item enters the queue only when its
+  // predecessor segment (and, for a cone's first segment, its predecessor
+  // cones) has finished in the schedule, so every item waits only on items
+  // earlier in the queue.
   const int workers = std::max(1, P.sched_workers);
   struct Ready {
     double prio;
@@ -2051,13 +2354,16 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
   std::priority_queue<Done> running;
   std::vector<std::vector<int32_t>> left(nc);  // unfinished items per segment
   auto release = [&](size_t c, size_t s) {
-    const int32_t k = n_items(segs[c][s]);
+    const int32_t k = segs[c][s].n_items();
     left[c][s] = k;
-    for (int32_t it = 0; it < k; ++it) ready.push({span[c][s], (int32_t)c, (int32_t)s, it});
+    for (int32_t it = 0; it < k; ++it) ready.push({ch.span[c][s], (int32_t)c, (int32_t)s, it});
   };
+  // the simulation counts waits down: whether a cone's first node waits is
+  // fixed before it starts
+  const std::vector<int32_t> gate_of = waits;
   for (size_t c = 0; c < nc; ++c) {
     left[c].assign(segs[c].size(), 0);
-    if (!segs[c].empty()) release(c, 0);
+    if (!segs[c].empty() && waits[c] == 0) release(c, 0);
   }
   double now = 0;
   int free_w = workers;
@@ -2068,12 +2374,13 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
       const Seg& g = segs[r.cone][r.seg];
       const int32_t node = node_of[r.cone][r.seg];
       const bool has_next = (size_t)r.seg + 1 < segs[r.cone].size();
-      int32_t slo = (int32_t)succ.size(), shi = slo;
-      if (has_next) {
-        succ.push_back(node_of[r.cone][r.seg + 1]);
-        shi = slo + 1;
-      }
-      const int32_t wait_node = r.seg > 0 ? node : -1;
+      int32_t slo = (int32_t)succ.size();
+      if (has_next) succ.push_back(node_of[r.cone][r.seg + 1]);
+      if (!has_next)
+        for (int32_t c2 : after[r.cone])
+          if (!segs[c2].empty()) succ.push_back(node_of[c2][0]);
+      const int32_t shi = (int32_t)succ.size();
+      const int32_t wait_node = (r.seg > 0 || gate_of[r.cone] > 0) ? node : -1;
       if (!g.wide) {
         items.push_back({g.r[0], g.r[1], g.r[2], g.r[3], 0, -1, wait_node, slo, shi, {0, 0, 0}});
       } else {
@@ -2082,7 +2389,7 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
         items.push_back({g.r[0], g.r[1], -1, -1, (int32_t)b, (int32_t)std::min<int64_t>(g.nblocks, b + tb), wait_node,
                          slo, shi, {0, 0, 0}});
       }
-      running.push({now + item_us[r.cone][r.seg], r.cone, r.seg});
+      running.push({now + ch.item_us[r.cone][r.seg], r.cone, r.seg});
       --free_w;
     }
     if (running.empty()) break;
@@ -2090,7 +2397,14 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
     running.pop();
     now = d.t;
     ++free_w;
-    if (--left[d.cone][d.seg] == 0 && (size_t)d.seg + 1 < segs[d.cone].size()) release(d.cone, d.seg + 1);
+    if (--left[d.cone][d.seg] == 0) {
+      if ((size_t)d.seg + 1 < segs[d.cone].size()) {
+        release(d.cone, d.seg + 1);
+      } else {
+        for (int32_t c2 : after[d.cone])
+          if (--waits[c2] == 0 && !segs[c2].empty()) release(c2, 0);
+      }
+    }
   }
 }
 

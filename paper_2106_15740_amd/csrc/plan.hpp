@@ -86,8 +86,10 @@ struct Cone {
   // arena: [leaf tables][their adjoints][buffers placed by lifetime]
   std::vector<char> recompute;    // bucket outputs not kept for the adjoint sweep (recomputed there)
   std::vector<BufLife> bufs;      // placement of every logical buffer
-  int64_t base = 0;               // element offset of the cone in the arena
-  int64_t arena_elems = 0;        // elements the cone occupies
+  int64_t base = 0;               // element offset of the cone's pinned part (leaf tables, their adjoints)
+  int64_t arena_elems = 0;        // elements the cone occupies (pinned part, then its dynamic region)
+  int64_t dyn_start = 0;          // cone-relative offset where the dynamic region starts (= pinned elements)
+  int64_t dyn_base = 0;           // offset of the dynamic region inside the plan's dynamic area
   int64_t keep_all_elems = 0;     // elements without any recomputation
   int64_t lam_base = 0, lam_size = 0;  // contiguous block of the leaf-product tables (absolute)
   double fwd_bytes_alg = 0, bwd_bytes_alg = 0, fwd_flops = 0, rec_bytes = 0;
@@ -131,6 +133,10 @@ struct Plan {
   int64_t lds_elems = 0;               // largest LDS window needed (elements)
   int64_t arena_fwd = 0, arena_grad = 0;  // elements needed without / with gradient
   int64_t mem_budget = 0;           // arena budget in elements (0: unlimited)
+  int64_t dyn_off = 0;              // arena offset of the dynamic area (after every cone's pinned part)
+  // under a budget: the cones each queued cone waits for (they last held part
+  // of its dynamic region); empty without a budget
+  std::vector<std::vector<int32_t>> cone_pred;
   int sched_workers = 1024;  // resident workgroups the queue order is scheduled for
   // persistent-queue items (forward-only and forward+gradient programs)
   std::vector<QItem> items_fwd, items_grad;

@@ -151,6 +151,28 @@ def test_p5_n1000_every_edge_vs_oracle_and_symmetries():
     np.testing.assert_allclose(db2, -db, rtol=0, atol=1e-4 * scale)
 
 
+@pytest.mark.parametrize("share", [0.25, 0.0])
+def test_p5_n1000_under_a_memory_budget(share):
+    """The p = 5 workload of the benchmark under a workspace budget: a quarter
+    of the keep-everything arena (cones admitted into a shared area), and
+    (share 0) just below the largest cone's own working set, so that cone
+    recomputes dropped outputs in its adjoint sweep.  Every edge term and the
+    sampled derivatives against the oracle, as without a budget."""
+    w, net = net_for("p5_n1000", "min_degree", repeats=10, seq_max_bits=16, tile_blocks=128, par_bits=21)
+    full = net.info()
+    if share > 0:
+        budget = int(share * full["arena_keep_all"])
+    else:
+        budget = full["pinned_bytes"] + int(0.95 * full["max_cone_dynamic"])
+    net.set_memory_budget(budget)
+    info = net.info()
+    print(f"[budget] {budget / 1e9:.2f} GB of {full['arena_keep_all'] / 1e9:.2f} GB keep-all: workspace "
+          f"{info['ws_grad'] / 1e9:.2f} GB, {info['n_recomputed']} outputs recomputed", flush=True)
+    assert info["ws_grad"] <= budget + (1 << 20) and info["ws_grad"] <= 0.5 * full["arena_keep_all"]
+    assert (info["n_recomputed"] > 0) == (share == 0)
+    check_against_golden("p5_n1000", net, "batched")
+
+
 @pytest.mark.parametrize("order", ["min_fill", "min_degree"])
 def test_amplitude_n22_p4_wide_vs_statevector(order):
     """The single amplitude <0...0|gamma beta> of a 22-vertex graph at p = 4

@@ -260,25 +260,32 @@ def test_lds_resident_and_global_sweeps_agree(lds_kb):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_checkpointed_adjoint_under_memory_budget(mode):
-    """With a workspace budget the adjoint sweep recomputes dropped bucket
-    outputs; energy and gradient must still match the state-vector adjoint
-    (p = 3 on a 12-vertex 3-regular graph, min-degree order, width 17)."""
+    """Under a workspace budget the cones share their dynamic regions
+    (admission in queue order) and, below one cone's own region, the adjoint
+    sweep recomputes dropped bucket outputs; energy, gradient and edge terms
+    must still match the state vector (p = 3 on a 12-vertex 3-regular graph,
+    min-degree order, width 17, LDS-resident programs off)."""
     n, edges = 12, random_regular_graph(12, 3, 3)
     rng = np.random.default_rng(3)
     g, b = rng.uniform(0, np.pi, 3), rng.uniform(0, np.pi, 3)
     e_ref, dg_ref, db_ref = sv.energy_grad_adjoint(n, edges, g, b)
-    net = make(n, edges, 3, "c128", "min_degree", g, b)
-    keep = net.info()["arena_keep_all"]
-    net.set_memory_budget(int(0.9 * keep))
-    info = net.info()
-    assert info["n_recomputed"] > 0
-    print(f"[case] budget {int(0.9 * keep)} recomputed {info['n_recomputed']}", flush=True)
-    for _ in range(2):
-        e, dg, db = net.energy_grad(mode)
-        assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
-        np.testing.assert_allclose(dg, dg_ref, atol=1e-9)
-        np.testing.assert_allclose(db, db_ref, atol=1e-9)
-    np.testing.assert_allclose(net.edge_results(), sv.zz_expectations(n, edges, g, b), atol=1e-10)
+    zz_ref = sv.zz_expectations(n, edges, g, b)
+    net = make(n, edges, 3, "c128", "min_degree", g, b, lds_kb=0)
+    full = net.info()
+    budgets = [max(int(0.5 * full["arena_keep_all"]), full["pinned_bytes"] + full["max_cone_dynamic"]),
+               full["pinned_bytes"] + int(0.9 * full["max_cone_dynamic"])]
+    for k, budget in enumerate(budgets):
+        net.set_memory_budget(budget)
+        info = net.info()
+        assert info["ws_grad"] <= budget + (1 << 16)
+        assert (info["n_recomputed"] > 0) == (k == 1)
+        print(f"[case] budget {budget} recomputed {info['n_recomputed']}", flush=True)
+        for _ in range(2):
+            e, dg, db = net.energy_grad(mode)
+            assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
+            np.testing.assert_allclose(dg, dg_ref, atol=1e-9)
+            np.testing.assert_allclose(db, db_ref, atol=1e-9)
+        np.testing.assert_allclose(net.edge_results(), zz_ref, atol=1e-10)
 
 
 @pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-10)])

@@ -157,22 +157,33 @@ def test_empty_and_degenerate_graphs_plan():
 
 
 def test_memory_budget_checkpointing_plan():
-    """A workspace budget below the keep-everything arena makes the planner
-    drop bucket outputs after the forward sweep and recompute them in the
-    adjoint sweep; the plan stays valid, fits, and the budget is released by 0.
-    An unreachable budget is refused and leaves no limit behind."""
-    w = workload("p3_n244")
-    net = QaoaNet(w.n, w.edges[:60], w.p, dtype="c64", order="min_fill", device=None)
-    net.set_tuning(merge_bits=0)  # one step per bucket: merged steps of these small cones leave little to drop
+    """A workspace budget makes the cones share their dynamic regions (the
+    batched sweep admits them in queue order, each waiting for the cones that
+    last held its region: checked by the plan validator); below one cone's
+    own region the planner also drops bucket outputs after the forward sweep
+    and recomputes them (recursively) in the adjoint sweep.  The plan stays
+    valid and fits, the algorithmic bytes are unchanged, 0 releases the
+    budget, and an unreachable budget is refused without leaving a limit."""
+    w = workload("p4_n100")
+    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=None)
     full = net.info()
     assert full["n_recomputed"] == 0 and full["rec_bytes"] == 0
     keep = full["ws_grad"]
-    budget = int(0.95 * full["arena_keep_all"])
+    extra = keep - full["pinned_bytes"]
+    # admission only: half the keep-everything arena, above every cone's own region
+    budget = max(int(0.5 * full["arena_keep_all"]), full["pinned_bytes"] + full["max_cone_dynamic"] + (1 << 20))
+    assert budget < full["arena_keep_all"]
+    net.set_memory_budget(budget)
+    net.validate()
+    adm = net.info()
+    assert adm["n_recomputed"] == 0 and adm["ws_grad"] <= budget + (1 << 16)
+    # below the largest cone's own region: recomputation, one level or deeper
+    budget = full["pinned_bytes"] + int(0.8 * full["max_cone_dynamic"])
     net.set_memory_budget(budget)
     net.validate()
     cut = net.info()
     assert cut["n_recomputed"] > 0 and cut["rec_bytes"] > 0
-    assert cut["ws_grad"] - (keep - full["arena_keep_all"]) <= budget
+    assert cut["ws_grad"] <= budget + (1 << 16)
     assert cut["fwd_bytes"] == full["fwd_bytes"] and cut["bwd_bytes"] == full["bwd_bytes"]
     net.set_memory_budget(0)
     assert net.info()["n_recomputed"] == 0 and net.info()["ws_grad"] == keep
@@ -181,6 +192,7 @@ def test_memory_budget_checkpointing_plan():
     assert ei.value.status == L.QTN_ENOMEM
     assert net.info()["n_recomputed"] == 0 and net.info()["ws_grad"] == keep
     net.validate()
+    assert extra > 0
 
 
 @pytest.mark.parametrize("merge_bits", [0, 4, 8, 12])
