@@ -286,6 +286,23 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
         bands.append({"widths": f"{lo}-{hi - 1}" if hi else f">={lo}", "ops": k, "alg_bytes": b, "ms": ms,
                       "achieved_GBps": b / (ms * 1e-3) / 1e9 if ms > 0 else None})
     tuning = net.tuning()
+    # the same sweep under workspace budgets: a quarter of the keep-everything
+    # arena (cones admitted into a shared area as regions free up), and just
+    # below the largest cone's own working set (that cone drops outputs after
+    # its forward sweep and recomputes them in its adjoint sweep)
+    budgets = []
+    for label, nbytes in (("quarter_of_keep_all", int(0.25 * info["arena_keep_all"])),
+                          ("below_largest_cone", info["pinned_bytes"] + int(0.95 * info["max_cone_dynamic"]))):
+        net.set_memory_budget(nbytes)
+        ib = net.info()
+        dtb, eb, _, _ = time_sweeps(net, steps, 1)
+        pkb = net.time_persistent(with_grad=True, reps=2)
+        budgets.append({"budget": label, "budget_GB": nbytes / 1e9, "workspace_GB": ib["ws_grad"] / 1e9,
+                        "n_recomputed": ib["n_recomputed"], "recompute_bytes": ib["rec_bytes"],
+                        "persistent_kernel_ms": pkb, "overhead_vs_keep_all": pkb / pk_ms - 1.0,
+                        "edge_light_cones_per_s": len(w.edges) * steps / dtb,
+                        "energy_rel_diff": abs(eb - e) / abs(e)})
+    net.set_memory_budget(0)
     del net
     torch.cuda.empty_cache()
     # the other greedy order (min-fill: narrower, widths up to 25 on this graph)
@@ -316,6 +333,8 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
         "frac_of_peak": achieved_b / HBM_PEAK_GBS,
         "frac_of_copy": achieved_b / copy_gbps if copy_gbps else None,
         "workspace_GB": info["ws_grad"] / 1e9,
+        "keep_all_GB": info["arena_keep_all"] / 1e9,
+        "memory_budgets": budgets,
         "width_ge_20_standalone_bands": bands,
         "energy": e,
         "plan_s": plan_s,

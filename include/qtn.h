@@ -60,7 +60,8 @@ typedef struct {
   int32_t seq_max_bits; /* buckets with more union bits than this are split across workgroups */
   int32_t tile_blocks;  /* blocks of a split bucket handled by one queue item (power of two) */
   int32_t loop_cap;     /* summed bits looped inside a thread before partial sums go to atomics */
-  int32_t grid;         /* persistent workgroups (0: 8 per compute unit) */
+  int32_t grid;         /* persistent workgroups (0: 8 per compute unit; 1: one workgroup takes the queue's
+                           items in order, a deterministic schedule in which no item waits) */
   int32_t lds_kb;       /* LDS window (KiB, <= 128) for light cones that run LDS-resident in the batched sweep: leaf
                            tables, intermediates and adjoints of such a cone never leave LDS (0: none) */
   int32_t par_bits;     /* a split bucket aims at >= 2^par_bits threads before summing in per-thread loops (8..24) */

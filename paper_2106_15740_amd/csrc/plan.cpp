@@ -2308,12 +2308,34 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
   Chains ch;
   cone_chains(P, grad, keep, ch);
   const auto& segs = ch.segs;
-  // memory admission (unfiltered queues): cone c starts after its predecessors end
-  const bool gated = !keep && P.cone_pred.size() == nc;
+  // memory admission: cone c starts after its predecessors end.  A filtered
+  // queue may leave a predecessor without items: c then waits for that
+  // cone's own predecessors, transitively.
+  const bool gated = P.cone_pred.size() == nc;
+  std::vector<std::vector<int>> pred(nc);
+  if (gated) {
+    std::vector<char> done(nc, 0);
+    std::function<void(int)> eff = [&](int c) {
+      if (done[c]) return;
+      done[c] = 1;
+      std::vector<int> r;
+      for (int a : P.cone_pred[c]) {
+        if (!segs[a].empty()) {
+          r.push_back(a);
+        } else {
+          eff(a);
+          r.insert(r.end(), pred[a].begin(), pred[a].end());
+        }
+      }
+      std::sort(r.begin(), r.end());
+      r.erase(std::unique(r.begin(), r.end()), r.end());
+      pred[c] = r;
+    };
+    for (size_t c = 0; c < nc; ++c) eff((int)c);
+  }
   std::vector<std::vector<int32_t>> after(nc);  // cones that wait for this one
-  if (gated)
-    for (size_t c = 0; c < nc; ++c)
-      for (int a : P.cone_pred[c]) after[a].push_back((int32_t)c);
+  for (size_t c = 0; c < nc; ++c)
+    for (int a : pred[c]) after[a].push_back((int32_t)c);
   std::vector<std::vector<int32_t>> node_of(nc);
   int32_t nn = 0;
   for (size_t c = 0; c < nc; ++c)
@@ -2323,13 +2345,12 @@ void build_queue(const Plan& P, bool grad, const std::function<bool(int32_t)>& k
     for (size_t s = 1; s < segs[c].size(); ++s) init[node_of[c][s]] = segs[c][s - 1].n_items();
   // a gated cone's first node also counts its predecessors' last items
   std::vector<int32_t> waits(nc, 0);
-  if (gated)
-    for (size_t c = 0; c < nc; ++c)
-      for (int a : P.cone_pred[c])
-        if (!segs[c].empty() && !segs[a].empty()) {
-          init[node_of[c][0]] += segs[a].back().n_items();
-          ++waits[c];
-        }
+  for (size_t c = 0; c < nc; ++c)
+    for (int a : pred[c])
+      if (!segs[c].empty()) {
+        init[node_of[c][0]] += segs[a].back().n_items();
+        ++waits[c];
+      }
   // Queue order: a list schedule of the segments on the resident workgroups,
   // longest remaining chain first; an item enters the queue only when its
   // predecessor segment (and, for a cone's first segment, its predecessor

@@ -288,6 +288,39 @@ def test_checkpointed_adjoint_under_memory_budget(mode):
         np.testing.assert_allclose(net.edge_results(), zz_ref, atol=1e-10)
 
 
+@pytest.mark.parametrize("case", ["p3_edges", "p4_wide", "p4_wide_budget"])
+def test_one_workgroup_fifo_sweep_matches_plain(case):
+    """grid = 1: a single persistent workgroup takes the queue's items in
+    order, so no item ever waits and the queue's order alone must be a valid
+    schedule (every dependency earlier in the queue).  Its energy, gradient and
+    edge terms must equal the plain per-op loop's (complex128, 1e-12), also for
+    split buckets with atomics (p = 4, seq_max_bits 9) and under a memory
+    budget whose cones share regions; a second run agrees to rounding."""
+    w = workload("p3_n244" if case == "p3_edges" else "p4_n100")
+    edges = w.edges[:100] if case == "p3_edges" else w.edges
+    tune = dict(lds_kb=0) if case == "p3_edges" else dict(lds_kb=0, seq_max_bits=9, lane_cap=6, tile_blocks=64)
+    net = make(w.n, edges, w.p, "c128", "min_degree", w.gamma, w.beta, **tune)
+    if case == "p4_wide_budget":
+        full = net.info()
+        net.set_memory_budget(full["pinned_bytes"] + int(0.9 * full["max_cone_dynamic"]))
+        assert net.info()["n_recomputed"] > 0
+    e_p, dg_p, db_p = net.energy_grad("plain")
+    zz_p = net.edge_results()
+    net.set_tuning(grid=1)
+    runs = []
+    for _ in range(2):
+        e, dg, db = net.energy_grad("batched")
+        runs.append((e, dg, db, net.edge_results()))
+    e, dg, db, zz = runs[0]
+    assert abs(e - e_p) <= 1e-12 * abs(e_p)
+    np.testing.assert_allclose(dg, dg_p, rtol=0, atol=1e-12 * max(1, np.abs(dg_p).max()))
+    np.testing.assert_allclose(db, db_p, rtol=0, atol=1e-12 * max(1, np.abs(db_p).max()))
+    np.testing.assert_allclose(zz, zz_p, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(runs[1][3], zz, rtol=0, atol=1e-13)
+    e_f = net.energy("batched")
+    assert abs(e_f - e_p) <= 1e-12 * abs(e_p)
+
+
 @pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-10)])
 def test_wide_executor_plain_and_batched(dtype, tol):
     """Buckets wider than seq_max_bits run in the wide-op executor (its own
