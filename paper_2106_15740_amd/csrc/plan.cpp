@@ -496,7 +496,9 @@ static void buckets_one(Cone& C) {
 // a bucket (with the buckets already merged into it) joins its consumer while
 // the merged union stays within merge_bits bits and the merged step has at
 // most MAXIN inputs: for buckets this small every step costs about the same
-// fixed time, so fewer steps are faster.  A merged step is the union of its
+// fixed time, so fewer steps are faster.  At any size it joins a consumer that
+// only sums indices out of its output (no other input, no leaf of a new
+// index): the merged union is its own.  A merged step is the union of its
 // members' tensors summed over all of their eliminated indices (the same
 // contraction, Section III.B, taken several indices at a time).
 static void group_buckets(Cone& C, int merge_bits, int merge_lam_bits) {
@@ -526,7 +528,11 @@ static void group_buckets(Cone& C, int merge_bits, int merge_lam_bits) {
       const int size = gsize[t] + gelim[b];
       const int nin = gnin[t] - 1 + gnin[b];
       const int lam = glam[t] | glam[b];
-      if (size > merge_bits || nin + lam > MAXIN) continue;
+      // any size when the consumer carries no index beyond b's output and
+      // adds no input (a marginal of b's output: summing it in b's own step
+      // costs nothing and saves writing and re-reading that output)
+      const bool free_merge = size <= gsize[b] && nin + lam <= gnin[b] + glam[b];
+      if ((size > merge_bits && !free_merge) || nin + lam > MAXIN) continue;
       // the merged leaf-product table (built and differentiated per entry)
       // stays small
       std::vector<int> li;

@@ -264,13 +264,13 @@ def test_checkpointed_adjoint_under_memory_budget(mode):
     (admission in queue order) and, below one cone's own region, the adjoint
     sweep recomputes dropped bucket outputs; energy, gradient and edge terms
     must still match the state vector (p = 3 on a 12-vertex 3-regular graph,
-    min-degree order, width 17, LDS-resident programs off)."""
+    min-fill order, width 15, LDS-resident programs off)."""
     n, edges = 12, random_regular_graph(12, 3, 3)
     rng = np.random.default_rng(3)
     g, b = rng.uniform(0, np.pi, 3), rng.uniform(0, np.pi, 3)
     e_ref, dg_ref, db_ref = sv.energy_grad_adjoint(n, edges, g, b)
     zz_ref = sv.zz_expectations(n, edges, g, b)
-    net = make(n, edges, 3, "c128", "min_degree", g, b, lds_kb=0)
+    net = make(n, edges, 3, "c128", "min_fill", g, b, lds_kb=0)
     full = net.info()
     budgets = [max(int(0.5 * full["arena_keep_all"]), full["pinned_bytes"] + full["max_cone_dynamic"]),
                full["pinned_bytes"] + int(0.9 * full["max_cone_dynamic"])]
