@@ -73,7 +73,10 @@ typedef struct {
   int32_t fuse_adjoint; /* 1: the adjoint of a split bucket computes every input adjoint in one pass over its
                            union (output adjoint and inputs read once) where the loop bits can be chosen so
                            that no output needs atomics per step; 2: also the other buckets, summed tile by tile
-                           in LDS (slower on MI355X: LDS atomics); 0: one pass per input adjoint */
+                           in LDS (slower on MI355X: LDS atomics); 3: the other buckets of complex64 nets with
+                           inputs that each lack part of the union (outer products) in one pass with register
+                           slots, one output sum per loop step (slower on MI355X where many partial sums remain
+                           for atomics); 0: one pass per input adjoint */
   int32_t lds_threads;  /* workgroup size (64, 128 or 256) of the kernel that runs the light cones whose whole
                            program fits the LDS window (lds_kb), one workgroup per cone */
 } qtn_tuning;

@@ -785,7 +785,7 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->merge_bits < 0 || t->merge_bits > 16) return fail(QTN_EINVAL, "merge_bits must be in 0..16");
   if (t->merge_lam_bits < 0 || t->merge_lam_bits > 16) return fail(QTN_EINVAL, "merge_lam_bits must be in 0..16");
   if (t->lane_low != 0 && t->lane_low != 1) return fail(QTN_EINVAL, "lane_low must be 0 or 1");
-  if (t->fuse_adjoint < 0 || t->fuse_adjoint > 2) return fail(QTN_EINVAL, "fuse_adjoint must be 0, 1 or 2");
+  if (t->fuse_adjoint < 0 || t->fuse_adjoint > 3) return fail(QTN_EINVAL, "fuse_adjoint must be 0, 1, 2 or 3");
   if (t->lds_threads != 64 && t->lds_threads != 128 && t->lds_threads != 256)
     return fail(QTN_EINVAL, "lds_threads must be 64, 128 or 256");
   n->P.tune.threads = th;

@@ -920,6 +920,214 @@ __device__ __forceinline__ void exec_tile(const OpDesc& d, typename CT<R>::E* __
   }
 }
 
+// Executor of OP_ADJOINT ops flagged F_OUTER: every input adjoint of a wide
+// bucket whose inputs each lack a different part of the union (an outer
+// product of its inputs), in one pass that reads the output adjoint and each
+// input once, with every sum in registers.  Union bits: nl lanes (the lowest
+// union bits), KI slot bits (unrolled: 2^KI union elements per loop step,
+// their loads in flight together), nk loop bits walked per thread in Gray
+// order, then block bits.  Every output keeps 2^KI register slots of pairs.
+// An output holding the loop bits is flushed after every loop step; the others
+// sum over the loop and over block steps that flip only bits they lack, and
+// are flushed once.  A flush adds the slots whose bits the output lacks, then
+// combines the lanes it lacks (shuffles within the wavefront) and stores each
+// remaining value, or adds it with atomics into zeroed memory when the output
+// lacks a block bit.  Block ranges as in exec_wide.
+template <typename R, int NIN, int KI>
+__device__ __forceinline__ void exec_outer(const OpDesc& d, typename CT<R>::E* __restrict__ arena, int64_t blk_begin,
+                                           int64_t blk_end, int64_t wg_rank, int64_t wg_count) {
+  using E = typename CT<R>::E;
+  constexpr int NS = 1 << KI;
+  const int tid = threadIdx.x;
+  const int nl = d.nl, nk = d.nk;
+  const int sbits = 31 - __clz(blockDim.x >> nl);
+  const int sub = tid >> nl;
+  const int lane = tid & ((1 << nl) - 1);
+  const int zk0 = nl + KI, zb0 = nl + KI + nk;
+  uint32_t blockbits = 0;
+  for (int z = zb0; z < d.nbits - 1; ++z) blockbits |= 1u << d.zbit[z];
+  uint32_t mask[NIN], loff[NIN], lsum[NIN], slack[NIN], sst[NIN][KI > 0 ? KI : 1];
+  bool hold[NIN], atom[NIN];
+  const E* inp[NIN];
+  E* outp[NIN];
+  uint32_t aheld = 0;  // bits held by an output that sums over the loop
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    mask[i] = d.in_mask[i];
+    inp[i] = arena + d.in_off[i];
+    outp[i] = arena + (i ? d.adj_off[i] : 0);
+    hold[i] = i > 0 && nk > 0 && ((mask[i] >> d.zbit[zk0]) & 1u);
+    atom[i] = (blockbits & ~mask[i]) != 0;
+    if (i > 0 && !hold[i]) aheld |= mask[i];
+    uint32_t o = 0, ls = 0, sl = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t sh = d.lsh[i][j];
+      if (j < nl) {
+        if (sh != LSH_NONE)
+          o |= ((uint32_t)(lane >> j) & 1u) << sh;
+        else
+          ls |= 1u << j;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KI; ++j) {
+      const uint32_t u = d.zbit[nl + j];
+      const bool h = (mask[i] >> u) & 1u;
+      sst[i][j] = h ? bit_stride(mask[i], u) : 0u;
+      if (!h) sl |= 1u << j;
+    }
+    loff[i] = o;
+    lsum[i] = ls;
+    slack[i] = sl;
+  }
+  // offset of slot s of input i
+  auto soff = [&](int i, int s) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < KI; ++j)
+      if ((s >> j) & 1) o += sst[i][j];
+    return o;
+  };
+  const int nloop = 1 << nk;
+  const uint32_t base_blk = (uint32_t)blk_begin;
+  const int lg_nblk = 31 - __clz((uint32_t)(blk_end - blk_begin));
+  const int lg_st = lg_nblk - sbits;
+  const int lg_wg = 31 - __clz((uint32_t)wg_count);
+  const int lg_chunk = lg_st > lg_wg ? lg_st - lg_wg : 0;
+  const int chunk = 1 << lg_chunk;
+  const int nchunks = 1 << (lg_st - lg_chunk);
+  E acc0[NIN][NS], acc1[NIN][NS];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      acc0[i][s] = E{0, 0};
+      acc1[i][s] = E{0, 0};
+    }
+  // add the slots output i lacks, combine its lacked lanes, store or add
+  auto flush = [&](int i, uint32_t base) {
+#pragma unroll
+    for (int j = 0; j < KI; ++j)
+      if ((slack[i] >> j) & 1u) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (!((s >> j) & 1)) {
+            acc0[i][s] = cadd(acc0[i][s], acc0[i][s | (1 << j)]);
+            acc1[i][s] = cadd(acc1[i][s], acc1[i][s | (1 << j)]);
+          }
+      }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if ((uint32_t)s & slack[i]) continue;  // uniform
+      E s0 = acc0[i][s], s1 = acc1[i][s];
+      for (int j = 0; j < 6; ++j)
+        if ((lsum[i] >> j) & 1u) {
+          s0 = cadd(s0, shfl_xor_c(s0, 1 << j));
+          s1 = cadd(s1, shfl_xor_c(s1, 1 << j));
+        }
+      if ((lane & lsum[i]) == 0) {
+        E* p = outp[i] + base + soff(i, s);
+        if (atom[i]) {
+          atomic_add_c(p, s0);
+          atomic_add_c(p + 1, s1);
+        } else {
+          store_pair(p, s0, s1);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      acc0[i][s] = E{0, 0};
+      acc1[i][s] = E{0, 0};
+    }
+  };
+#pragma unroll 1
+  for (int ch = (int)wg_rank; ch < nchunks; ch += (int)wg_count) {
+    const uint32_t q0 = (uint32_t)ch << lg_chunk;
+    const uint32_t blk = base_blk + (q0 << sbits) + (uint32_t)sub;
+    uint32_t boff[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) boff[i] = loff[i];
+    for (int j = 0; j < d.nb; ++j)
+      if ((blk >> j) & 1u) {
+        const uint32_t u = d.zbit[zb0 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) boff[i] += bit_stride(mask[i], u);
+      }
+#pragma unroll 1
+    for (int c = 0; c < chunk; ++c) {
+      if (c) {
+        const int t = __ffs(c) - 1;
+        const bool up = ((c ^ (c >> 1)) >> t) & 1;
+        const uint32_t u = d.zbit[zb0 + sbits + t];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          const uint32_t st = bit_stride(mask[i], u);
+          boff[i] = up ? boff[i] + st : boff[i] - st;
+        }
+      }
+      const uint32_t nxt = c + 1 < chunk ? 1u << d.zbit[zb0 + sbits + __ffs(c + 1) - 1] : 0u;
+      uint32_t koff[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) koff[i] = boff[i];
+      uint32_t gray = 0;
+#pragma unroll 1
+      for (int it = 0; it < nloop; ++it) {
+        if (it) {
+          const int fb = __ffs(it) - 1;
+          const uint32_t u = d.zbit[zk0 + fb];
+          gray ^= 1u << fb;
+          const bool up = (gray >> fb) & 1u;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) {
+            const uint32_t st = bit_stride(mask[i], u);
+            koff[i] = up ? koff[i] + st : koff[i] - st;
+          }
+        }
+        E ob[NS], a0[NS][NIN], a1[NS][NIN];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          ob[s] = inp[0][koff[0] + soff(0, s)];
+#pragma unroll
+          for (int i = 1; i < NIN; ++i) load_pair(inp[i] + koff[i] + soff(i, s), a0[s][i], a1[s][i]);
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            // prefix products pr[i] = ob * x[1] ... x[i-1]; ex[i] = pr[i] * suffix
+            E pr[NIN];
+            pr[1] = ob[s];
+#pragma unroll
+            for (int i = 1; i + 1 < NIN; ++i) pr[i + 1] = cmul(pr[i], h ? a1[s][i] : a0[s][i]);
+            E suf = E{1, 0};
+#pragma unroll
+            for (int i = NIN - 1; i >= 1; --i) {
+              const E x = h ? a1[s][i] : a0[s][i];
+              const E e = i == NIN - 1 ? pr[i] : cmul(pr[i], suf);
+              suf = i == NIN - 1 ? x : cmul(x, suf);
+              if (h)
+                acc1[i][s] = cadd(acc1[i][s], e);
+              else
+                acc0[i][s] = cadd(acc0[i][s], e);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 1; i < NIN; ++i)
+          if (hold[i]) flush(i, koff[i]);
+      }
+      if (nxt && !(aheld & nxt)) continue;  // uniform: every summing output carries
+#pragma unroll
+      for (int i = 1; i < NIN; ++i) {
+        if (hold[i] || (nxt && !(mask[i] & nxt))) continue;
+        flush(i, boff[i]);
+      }
+    }
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void exec_adjoint_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
                                                  int64_t r, int64_t c, typename CT<R>::E* lds) {
@@ -928,6 +1136,15 @@ __device__ __forceinline__ void exec_adjoint_any(const OpDesc& d, typename CT<R>
       exec_tile<R, 3>(d, arena, b0, b1, r, c, lds);
     else if (d.n_in == 4)
       exec_tile<R, 4>(d, arena, b0, b1, r, c, lds);
+    return;
+  }
+  if (d.flags & F_OUTER) {  // planned for complex64 only
+    if constexpr (sizeof(R) == 4) {
+      if (d.n_in == 3)
+        exec_outer<R, 3, 1>(d, arena, b0, b1, r, c);
+      else if (d.n_in == 4)
+        exec_outer<R, 4, 1>(d, arena, b0, b1, r, c);
+    }
     return;
   }
   constexpr bool two = WideMaxU<R>::in_persistent > 1;

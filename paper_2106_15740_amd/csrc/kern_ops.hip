@@ -34,6 +34,15 @@ __global__ void __launch_bounds__(512) adjoint_kernel(const OpDesc* __restrict__
   exec_adjoint<R, NIN, SL>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x);
 }
 
+// One outer-product OP_ADJOINT op per launch (KI register slot bits).
+template <typename R, int NIN, int KI>
+__global__ void __launch_bounds__(512) outer_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
+  __shared__ OpDesc d;
+  stage_desc(d, ops, op);
+  const int64_t nblocks = int64_t(1) << d.nb;
+  exec_outer<R, NIN, KI>(d, reinterpret_cast<typename CT<R>::E*>(env.arena), 0, nblocks, xcd_rank(), gridDim.x);
+}
+
 // One LDS-tiled OP_ADJOINT op per launch (dynamic LDS: the tile sums).
 template <typename R, int NIN>
 __global__ void __launch_bounds__(512) tile_kernel(const OpDesc* __restrict__ ops, int op, Env env) {
@@ -80,6 +89,17 @@ hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, const Env& 
       hipLaunchKernelGGL((tile_kernel<R, 3>), g, b, lb, st, d_ops, op, env);
     else if (h.n_in == 4)
       hipLaunchKernelGGL((tile_kernel<R, 4>), g, b, lb, st, d_ops, op, env);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  if (h.kind == OP_ADJOINT && (h.flags & F_OUTER)) {  // planned for complex64 only
+    if constexpr (sizeof(R) != 4) return hipErrorInvalidValue;
+    if (h.nu != 1) return hipErrorInvalidValue;
+    if (h.n_in == 3)
+      hipLaunchKernelGGL((outer_kernel<R, 3, 1>), g, b, 0, st, d_ops, op, env);
+    else if (h.n_in == 4)
+      hipLaunchKernelGGL((outer_kernel<R, 4, 1>), g, b, 0, st, d_ops, op, env);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();

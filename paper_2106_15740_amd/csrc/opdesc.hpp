@@ -28,6 +28,8 @@ enum OpFlags : int32_t {
                  // range it is given holds at least one block per sub-block
   F_TILE = 32,   // OP_ADJOINT summed per tile in LDS: the workgroup's threads are the lanes, blocks are tiles,
                  // aux0 = LDS elements of the tile sums
+  F_OUTER = 64,  // OP_ADJOINT whose outputs sum in 2^nu register slots per thread (nu slot bits after the
+                 // lanes, then the loop bits); outputs holding the loop bits are flushed every loop step
 };
 
 // A contraction op iterates the union index u of a bucket.  Bit 0 of u is the

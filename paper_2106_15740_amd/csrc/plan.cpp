@@ -906,6 +906,119 @@ bool tile_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) 
   return true;
 }
 
+// Bit split of an OP_ADJOINT op run by the outer-product executor
+// (F_OUTER), for buckets whose inputs each lack a different part of the
+// union, so that no group of loop bits suits the fused executor.  Lanes: the
+// lowest union bits, as there.  The other bits are grouped by the set of
+// outputs holding them.  The loop takes one group and the register slots
+// one bit of another: an output lacking the loop bits sums over them in
+// its slots, one lacking the slot bits adds its slots at each flush.  Among
+// all such pairs the one whose outputs are left with the fewest partial sums
+// to add with atomics (the block bits each output lacks, weighted by its
+// size) is taken.  An output holding both loop and slot bits is flushed for
+// every element, so it must sum lane bits only.  Loop length as in the fused
+// rule.  Returns false when no pair qualifies or the block range is smaller
+// than a workgroup step.
+bool outer_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) {
+  // complex64 only: with complex128 pairs the slots would lower the occupancy
+  // of the whole persistent kernel
+  if (T.elem_bytes != 8 || d.n_in < 3 || d.n_in > 4 || (d.in_mask[0] & 1u)) return false;
+  d.adj_sel = 0;
+  for (int i = 1; i < d.n_in; ++i) {
+    if (!(d.in_mask[i] & 1u)) return false;
+    d.adj_sel |= 1u << i;
+  }
+  const int max_lanes = std::min({T.lane_cap, 6, 31 - __builtin_clz((unsigned)std::max(T.threads, 1))});
+  uint32_t lanes = 0;
+  for (int u = 1; u < nbits && __builtin_popcount(lanes) < max_lanes; ++u) lanes |= 1u << u;
+  std::map<uint32_t, uint32_t> groups;  // holders -> bits
+  for (int u = 1; u < nbits; ++u) {
+    if ((lanes >> u) & 1u) continue;
+    uint32_t h = 0;
+    for (int i = 1; i < d.n_in; ++i) h |= ((d.in_mask[i] >> u) & 1u) << i;
+    groups[h] |= 1u << u;
+  }
+  const uint32_t outs = d.adj_sel;
+  const int nl = __builtin_popcount(lanes);
+  // the lowest bits of a group first (neighbouring elements)
+  auto take = [](uint32_t bits, int n) {
+    uint32_t r = 0;
+    for (int u = 0; u < 32 && n > 0; ++u)
+      if ((bits >> u) & 1u) {
+        r |= 1u << u;
+        --n;
+      }
+    return r;
+  };
+  double best = -1;
+  uint32_t best_slot = 0, best_loop = 0;
+  for (const auto& g2 : groups) {
+    if (g2.first == outs) continue;  // every output holds it: nothing sums over it
+    for (const auto& g1 : groups) {
+      if (g1.first == g2.first || g1.first == outs) continue;
+      bool ok = true;
+      for (int i = 1; i < d.n_in; ++i)
+        if (((g1.first & g2.first) >> i) & 1u)
+          ok &= !(all & ~d.in_mask[i] & ~lanes & ~1u);
+      if (!ok) continue;
+      const int ki = 1;  // register budget of the persistent kernel
+      const uint32_t slot = take(g1.second, ki);
+      const int rest = nbits - 1 - nl - ki;  // loop and block bits
+      const int loopable = __builtin_popcount(g2.second);
+      int nk = std::max(0, std::min(loopable, rest - T.par_bits + nl));
+      nk = std::min(nk, T.loop_cap);
+      nk = std::max(nk, std::min(loopable, 3));
+      if (nk < 1) continue;
+      const uint32_t loop = take(g2.second, nk);
+      const uint32_t blocks = all & ~1u & ~lanes & ~slot & ~loop;
+      const int nb = __builtin_popcount(blocks);
+      const int64_t nsub = std::max(1, T.threads >> nl);
+      if (std::min<int64_t>(std::max(1, T.tile_blocks), int64_t(1) << nb) < nsub) continue;
+      double cost = 0;  // partial sums written per output element, weighted by size
+      for (int i = 1; i < d.n_in; ++i)
+        cost += std::ldexp(1.0, __builtin_popcount(d.in_mask[i]) + __builtin_popcount(blocks & ~d.in_mask[i]));
+      if (best < 0 || cost < best) {
+        best = cost;
+        best_slot = slot;
+        best_loop = loop;
+      }
+    }
+  }
+  if (best < 0) return false;
+  const int ki = __builtin_popcount(best_slot), nk = __builtin_popcount(best_loop);
+  d.nl = nl;
+  d.nu = ki;
+  d.nk = nk;
+  d.nb = nbits - 1 - nl - ki - nk;
+  int z = 0;
+  for (int u = 1; u < nbits; ++u)
+    if ((lanes >> u) & 1u) d.zbit[z++] = (uint8_t)u;
+  for (int u = 1; u < nbits; ++u)
+    if ((best_slot >> u) & 1u) d.zbit[z++] = (uint8_t)u;
+  for (int u = 1; u < nbits; ++u)
+    if ((best_loop >> u) & 1u) d.zbit[z++] = (uint8_t)u;
+  uint32_t blockbits = 0;
+  for (int u = 1; u < nbits; ++u)
+    if (!(((lanes | best_slot | best_loop) >> u) & 1u)) {
+      d.zbit[z++] = (uint8_t)u;
+      blockbits |= 1u << u;
+    }
+  for (; z < 32; ++z) d.zbit[z] = 0;
+  bool atomic = false;
+  for (int i = 1; i < d.n_in; ++i) atomic |= (blockbits & ~d.in_mask[i]) != 0;
+  d.lane_sum = 0;
+  d.out_mask = 0;
+  d.out_off = 0;
+  d.flags = F_WIDE | F_OUTER | (atomic ? F_ATOMIC : 0);
+  for (int i = 0; i <= MAXIN; ++i)
+    for (int j = 0; j < MAXLANE; ++j) {
+      const uint32_t m = i < d.n_in ? d.in_mask[i] : 0u;
+      const uint32_t u = d.zbit[j];
+      d.lsh[i][j] = (j < d.nl && ((m >> u) & 1u)) ? (uint8_t)__builtin_popcount(m & ((1u << u) - 1u)) : LSH_NONE;
+    }
+  return true;
+}
+
 OpDesc blank(int kind, int cone) {
   OpDesc d;
   std::memset(&d, 0, sizeof(d));
@@ -1154,13 +1267,14 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       OpDesc d = blank(OP_ADJOINT, (int)c);
       d.nbits = nbits;
       add_common(d, -1, true);
-      if (fused_adjoint_bits(d, nbits, all, T) || (T.fuse_adjoint >= 2 && tile_adjoint_bits(d, nbits, all, T))) {
+      if (fused_adjoint_bits(d, nbits, all, T) || (T.fuse_adjoint == 3 && outer_adjoint_bits(d, nbits, all, T)) ||
+          (T.fuse_adjoint == 2 && tile_adjoint_bits(d, nbits, all, T))) {
         int i = 1;
         if (Bk.lam_mask) d.adj_off[i++] = buf_code(BK_LAMADJ, (int)bb);
         for (int t = 0; t < nin; ++t) d.adj_off[i++] = buf_code(BK_ADJ, Bk.in_bkt[t]);
         // outputs summed with atomics (those that sum a block bit) start from zero
         uint32_t blockbits = 0;
-        for (int q = d.nl + d.nk; q < nbits - 1; ++q) blockbits |= 1u << d.zbit[q];
+        for (int q = d.nl + d.nu + d.nk; q < nbits - 1; ++q) blockbits |= 1u << d.zbit[q];
         for (int k = 1; k < d.n_in; ++k)
           if (blockbits & ~d.in_mask[k]) {
             OpDesc z = blank(OP_ZERO, (int)c);
@@ -1685,18 +1799,23 @@ static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
   if (d.nbits <= P.tune.seq_max_bits || !(d.flags & F_WIDE)) return "adjoint op not wide";
   if (d.n_in < 3 || d.n_in > 4) return "adjoint op with a bad input count";
   const bool tiled = d.flags & F_TILE;
-  if (d.nu != 0 || d.nl < 1 || d.nl + d.nk + d.nb != d.nbits - 1) return "adjoint op bit partition";
+  const bool outer = d.flags & F_OUTER;
+  if (tiled && outer) return "adjoint op both tiled and outer";
+  if ((outer ? d.nu != 1 : d.nu != 0) || d.nl < 1 ||
+      d.nl + d.nu + d.nk + d.nb != d.nbits - 1)
+    return "adjoint op bit partition";
+  if (outer && (d.nk < 1 || P.tune.elem_bytes != 8)) return "outer adjoint op without loop bits or not complex64";
   if (tiled ? (1 << d.nl) != P.tune.threads : d.nl > 6) return "adjoint op lane count";
   if (d.adj_sel != (((1u << d.n_in) - 1u) & ~1u)) return "adjoint op output selection";
   if ((d.in_mask[0] & 1u) || (d.in_mask[0] & ~all)) return "adjoint op output adjoint mask";
   for (int i = 1; i < d.n_in; ++i)
     if (!(d.in_mask[i] & 1u) || (d.in_mask[i] & ~all)) return "adjoint op input mask";
-  uint32_t seen = 0, lanes = 0, loop = 0, blocks = 0;
+  uint32_t seen = 0, lanes = 0, slots = 0, loop = 0, blocks = 0;
   for (int z = 0; z < d.nbits - 1; ++z) {
     const uint32_t u = d.zbit[z];
     if (u < 1 || (int)u >= d.nbits || (seen >> u) & 1) return "adjoint op bad zbit";
     seen |= 1u << u;
-    (z < d.nl ? lanes : (z < d.nl + d.nk ? loop : blocks)) |= 1u << u;
+    (z < d.nl ? lanes : z < d.nl + d.nu ? slots : z < d.nl + d.nu + d.nk ? loop : blocks) |= 1u << u;
   }
   bool atomic = false;
   int64_t tile_elems = 0;
@@ -1705,6 +1824,10 @@ static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
     if (tiled) {
       if (d.in_mask[i] == all) return "LDS-tiled adjoint with an output holding the whole union";
       tile_elems += int64_t(2) << __builtin_popcount(d.in_mask[i] & (lanes | loop));
+    } else if (outer) {
+      if (held != 0 && held != loop) return "adjoint op output holds part of the loop bits";
+      if (held && (d.in_mask[i] & slots) && (all & ~d.in_mask[i] & ~lanes & ~1u))
+        return "outer adjoint op output flushed per element sums a non-lane bit";
     } else {
       if (held != 0 && held != loop) return "adjoint op output holds part of the loop bits";
       if (held && (all & ~d.in_mask[i] & ~lanes & ~1u)) return "adjoint op loop holder sums a non-lane bit";

@@ -327,8 +327,9 @@ def test_wide_executor_plain_and_batched(dtype, tol):
     launches in the plain loop; tiles inside the persistent sweep, with fewer
     outputs per thread).  A low seq_max_bits sends most buckets of p = 4 light
     cones there, with reductions over lanes, loops and blocks; the gradient
-    with one adjoint pass per input matches the fused adjoint's and the
-    LDS-tiled adjoint's (fuse_adjoint = 2)."""
+    with one adjoint pass per input matches the fused adjoint's, the
+    LDS-tiled adjoint's (fuse_adjoint = 2) and the outer-product adjoint's
+    (fuse_adjoint = 3)."""
     w = workload("p4_n100")
     net = make(w.n, w.edges, w.p, dtype, "min_fill", w.gamma, w.beta, seq_max_bits=9, lane_cap=6, tile_blocks=64)
     net_sep = make(w.n, w.edges, w.p, dtype, "min_fill", w.gamma, w.beta, seq_max_bits=9, lane_cap=6, tile_blocks=64,
@@ -340,6 +341,11 @@ def test_wide_executor_plain_and_batched(dtype, tol):
     _, dg_t, db_t = net_tile.energy_grad("batched")
     _, dg_tp, db_tp = net_tile.energy_grad("plain")
     del net_tile
+    net_outer = make(w.n, w.edges, w.p, dtype, "min_fill", w.gamma, w.beta, seq_max_bits=9, lane_cap=6,
+                     tile_blocks=64, fuse_adjoint=3)
+    _, dg_o, db_o = net_outer.energy_grad("batched")
+    _, dg_op, db_op = net_outer.energy_grad("plain")
+    del net_outer
     ref = np.array([tn.zz_edge(w.n, w.edges, w.gamma, w.beta, j, k) for j, k in w.edges[:3]])
     e_p, dg_p, db_p = net.energy_grad("plain")
     zz_p = net.edge_results()
@@ -354,7 +360,7 @@ def test_wide_executor_plain_and_batched(dtype, tol):
     np.testing.assert_allclose(db_b, db_p, atol=gt * max(1, np.abs(db_p).max()))
     np.testing.assert_allclose(dg_b, dg_s, atol=gt * max(1, np.abs(dg_s).max()))
     np.testing.assert_allclose(db_b, db_s, atol=gt * max(1, np.abs(db_s).max()))
-    for dg_x, db_x in ((dg_t, db_t), (dg_tp, db_tp)):
+    for dg_x, db_x in ((dg_t, db_t), (dg_tp, db_tp), (dg_o, db_o), (dg_op, db_op)):
         np.testing.assert_allclose(dg_x, dg_s, atol=gt * max(1, np.abs(dg_s).max()))
         np.testing.assert_allclose(db_x, db_s, atol=gt * max(1, np.abs(db_s).max()))
 
@@ -363,15 +369,16 @@ def test_wide_executor_plain_and_batched(dtype, tol):
 @pytest.mark.parametrize("lane_low", [0, 1])
 def test_fused_adjoint_gradient_vs_statevector(dtype, tol, lane_low):
     """Buckets wider than seq_max_bits compute all input adjoints in one pass
-    (fuse_adjoint = 1; 2 also sums the other buckets tile by tile in LDS) or
-    one pass per input (0).  All, with either lane policy, plain and batched,
-    give the state-vector adjoint gradient of the p = 4, N = 16 BFS subgraph;
-    each fused plan has fewer ops."""
+    (fuse_adjoint = 1; 2 also sums the other buckets tile by tile in LDS; 3
+    sums outer-product buckets in register slots, complex64 only) or one pass
+    per input (0).  All, with either lane policy, plain and batched, give the
+    state-vector adjoint gradient of the p = 4, N = 16 BFS subgraph; each
+    fused plan has fewer ops."""
     w = workload("p4_n100")
     n, edges = bfs_subgraph(w.n, w.edges, 16)
     e_ref, dg_ref, db_ref = sv.energy_grad_adjoint(n, edges, w.gamma, w.beta)
     n_ops = {}
-    for fuse in (0, 1, 2):
+    for fuse in (0, 1, 2, 3):
         net = make(n, edges, w.p, dtype, "min_fill", w.gamma, w.beta, seq_max_bits=7, merge_bits=0, threads=64,
                    lane_cap=6, tile_blocks=64, lane_low=lane_low, fuse_adjoint=fuse)
         n_ops[fuse] = net.info()["n_ops_grad"]
@@ -381,6 +388,8 @@ def test_fused_adjoint_gradient_vs_statevector(dtype, tol, lane_low):
             np.testing.assert_allclose(dg, dg_ref, atol=tol * max(1, np.abs(dg_ref).max()))
             np.testing.assert_allclose(db, db_ref, atol=tol * max(1, np.abs(db_ref).max()))
     assert n_ops[2] < n_ops[1] < n_ops[0]
+    if dtype == "c64":
+        assert n_ops[3] < n_ops[1]
 
 
 def test_optimisation_driver_reaches_the_p1_optimum():

@@ -99,7 +99,7 @@ def test_tuning_roundtrip_and_validation():
     assert ei.value.status == L.QTN_EINVAL
 
 
-@pytest.mark.parametrize("fuse,lane_low", [(0, 0), (0, 1), (1, 1), (2, 1)])
+@pytest.mark.parametrize("fuse,lane_low", [(0, 0), (0, 1), (1, 1), (2, 1), (3, 1)])
 @pytest.mark.parametrize("seq_max_bits,threads", [(7, 64), (9, 256), (12, 512)])
 def test_wide_plans_fused_and_separate_adjoints(fuse, lane_low, seq_max_bits, threads):
     """Wide buckets (p = 4, N = 100) planned with one adjoint pass per input or
@@ -121,7 +121,7 @@ def test_wide_plans_fused_and_separate_adjoints(fuse, lane_low, seq_max_bits, th
     with pytest.raises(ValueError):
         net.set_tuning(no_such_field=1)
     with pytest.raises(QtnError):
-        net.set_tuning(fuse_adjoint=3)
+        net.set_tuning(fuse_adjoint=4)
 
 
 @pytest.mark.parametrize("edges,n,p", [([(0, 0)], 2, 1), ([(0, 1), (1, 0)], 2, 1), ([(0, 5)], 3, 1),
