@@ -319,6 +319,17 @@ qtn_status qtn_cost_model(int32_t n_vertices, int32_t n_edges, const int32_t* ed
                           qtn_net_variant variant, qtn_order_kind kind, int32_t n_repeats, double temperature,
                           uint64_t seed, qtn_cost* out);
 
+/* qtn_cost_model that also writes the elimination order it evaluated into
+ * order_out[0 .. out->n_indices) (host, caller-owned, order_cap entries).
+ * Index ids follow the construction order: the initial index of every qubit
+ * (qubit q gets id q), then each gate's new indices as the circuit creates
+ * them (a two-qubit gate numbers its first qubit's new index first: the CNOT
+ * control, the ZZ gate's first vertex of the edge as listed).  QTN_EINVAL as
+ * qtn_cost_model, and when order_cap < n_indices (out is still filled). */
+qtn_status qtn_cost_model_order(int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                                qtn_net_variant variant, qtn_order_kind kind, int32_t n_repeats, double temperature,
+                                uint64_t seed, qtn_cost* out, int32_t* order_out, int32_t order_cap);
+
 /* Achievable-bandwidth reference: the library's plain copy kernel copies the
  * first half of the caller's device buffer `buf` (`bytes` long, 16-byte
  * aligned) onto its second half, `reps` times on `stream` after one warm-up,

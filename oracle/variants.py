@@ -114,6 +114,30 @@ def amplitude(n: int, edges: Sequence[Edge], gamma, beta, variant: str) -> compl
     return tn.contract(ts, order)
 
 
+def elimination_cost(n: int, edges: Sequence[Edge], p: int, variant: str, order: Sequence[int]) -> Tuple[int, float]:
+    """(width, sum over eliminated indices of 2^|union|) of eliminating the
+    variant's network in `order` (Section III.B, symbolically): eliminating v
+    replaces every tensor that carries v by one tensor on the union of their
+    indices without v; the width is the largest such result, and the work of
+    the step is 2^|union| (one product term per assignment of the union).
+    Index ids as network() numbers them."""
+    ts, nidx = network(n, edges, [0.1] * p, [0.2] * p, variant)
+    if sorted(order) != list(range(nidx)):
+        raise ValueError("order is not a permutation of the network's indices")
+    live = [set(ix) for _, ix in ts]
+    width, ops = 0, 0.0
+    for v in order:
+        touching = [t for t in live if v in t]
+        live = [t for t in live if v not in t]
+        union = set().union(*touching)
+        ops += 2.0 ** len(union)
+        rest = union - {v}
+        width = max(width, len(rest))
+        if rest:
+            live.append(rest)
+    return width, ops
+
+
 def counts(n: int, edges: Sequence[Edge], p: int, variant: str) -> Tuple[int, int]:
     """(indices, tensors) of the variant's network."""
     ts, nidx = network(n, edges, [0.1] * p, [0.2] * p, variant)

@@ -23,7 +23,7 @@ EXPORTS = [
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
-    "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model", "qtn_energy_grad_noalloc",
+    "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model", "qtn_cost_model_order", "qtn_energy_grad_noalloc",
     "qtn_time_wide_sweep",
     "qtn_net_free",
 ]
@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
         "qtn_build_amplitude": (I32, [P, I32, I32, P, I32, I32, C.POINTER(P)]),
         "qtn_amplitude": (I32, [P, I32, P, SZ, P, P, P]),
         "qtn_cost_model": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost)]),
+        "qtn_cost_model_order": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost), P, I32]),
         "qtn_energy_grad_noalloc": (I32, [P, I32, P, P, P, P, P]),
         "qtn_time_wide_sweep": (I32, [P, I32, I32, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D),
                                       C.POINTER(I64), C.POINTER(I64)]),

@@ -16,8 +16,10 @@ from . import _lib as L
 VARIANTS = ("default", "diagonal", "zz", "diagonal_zz")
 _ORDERS = {"min_degree": L.QTN_ORDER_MIN_DEGREE, "min_fill": L.QTN_ORDER_MIN_FILL}
 
-# memory of the paper's two machines and the bytes of one complex128 element
-LAPTOP_BYTES = 4e9
+# memory of the paper's two machines and the bytes of one complex128 element;
+# the laptop's 4 GB is read as 4 GiB (2^32 bytes: a width-28 complex128
+# tensor), the aggregate 800 TB as 800e12 bytes (largest width 45 either way)
+LAPTOP_BYTES = 4.0 * 2 ** 30
 SUPERCOMPUTER_BYTES = 800e12
 ELEM_BYTES = 16
 
@@ -31,6 +33,20 @@ def cost(n: int, edges: Sequence[Tuple[int, int]], p: int, variant: str, order: 
     L.check(L.lib().qtn_cost_model(int(n), len(e), e.ctypes.data_as(C.c_void_p), int(p), VARIANTS.index(variant),
                                    _ORDERS[order], int(repeats), float(temperature), int(seed), C.byref(out)))
     return out.as_dict()
+
+
+def cost_and_order(n: int, edges: Sequence[Tuple[int, int]], p: int, variant: str, order: str = "min_fill",
+                   repeats: int = 10, temperature: float = 0.02, seed: int = 0) -> Tuple[Dict[str, float], List[int]]:
+    """cost() and the elimination order it evaluated (index ids in the order
+    the construction creates them; see qtn_cost_model_order)."""
+    e = np.ascontiguousarray(np.array(edges, dtype=np.int32).reshape(-1, 2))
+    first = cost(n, edges, p, variant, order, repeats=0)
+    buf = np.zeros(max(1, int(first["n_indices"])), dtype=np.int32)
+    out = L.Cost()
+    L.check(L.lib().qtn_cost_model_order(int(n), len(e), e.ctypes.data_as(C.c_void_p), int(p), VARIANTS.index(variant),
+                                         _ORDERS[order], int(repeats), float(temperature), int(seed), C.byref(out),
+                                         buf.ctypes.data_as(C.c_void_p), len(buf)))
+    return out.as_dict(), [int(x) for x in buf[: out.n_indices]]
 
 
 def _graphs(n: int, seeds: Iterable[int]):

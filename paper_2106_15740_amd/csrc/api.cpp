@@ -1078,7 +1078,15 @@ qtn_status qtn_time_persistent(qtn_net* n, int32_t with_grad, void* ws, size_t w
 qtn_status qtn_cost_model(int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
                           qtn_net_variant variant, qtn_order_kind kind, int32_t n_repeats, double temperature,
                           uint64_t seed, qtn_cost* out) {
+  return qtn_cost_model_order(n_vertices, n_edges, edges, p, variant, kind, n_repeats, temperature, seed, out,
+                              nullptr, 0);
+}
+
+qtn_status qtn_cost_model_order(int32_t n_vertices, int32_t n_edges, const int32_t* edges, int32_t p,
+                                qtn_net_variant variant, qtn_order_kind kind, int32_t n_repeats, double temperature,
+                                uint64_t seed, qtn_cost* out, int32_t* order_out, int32_t order_cap) {
   if (!out) return fail(QTN_EINVAL, "out is NULL");
+  if (order_out && order_cap < 0) return fail(QTN_EINVAL, "order_cap must be >= 0");
   if (variant < QTN_NET_DEFAULT || variant > QTN_NET_DIAGONAL_ZZ) return fail(QTN_EINVAL, "unknown network variant");
   if (kind != QTN_ORDER_MIN_DEGREE && kind != QTN_ORDER_MIN_FILL) return fail(QTN_EINVAL, "unknown order kind");
   if (n_repeats < 0 || !(temperature >= 0.0) || !std::isfinite(temperature))
@@ -1094,12 +1102,19 @@ qtn_status qtn_cost_model(int32_t n_vertices, int32_t n_edges, const int32_t* ed
     O.temperature = temperature;
     O.seed = seed;
     const auto t0 = std::chrono::steady_clock::now();
-    const CostEstimate c = cost_model(n_vertices, E, p, (int)variant, O);
+    std::vector<int> order;
+    const CostEstimate c = cost_model(n_vertices, E, p, (int)variant, O, order_out ? &order : nullptr);
     out->order_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     out->n_indices = c.n_indices;
     out->n_tensors = c.n_tensors;
     out->width = c.width;
     out->log2_ops = c.log2_ops;
+    if (order_out) {
+      if (order_cap < c.n_indices)
+        return fail(QTN_EINVAL, "order_out holds " + std::to_string(order_cap) + " entries, the network has " +
+                                    std::to_string(c.n_indices) + " indices");
+      std::copy(order.begin(), order.end(), order_out);
+    }
     return QTN_OK;
   } catch (const std::bad_alloc&) {
     return fail(QTN_ENOMEM, "host allocation failed");

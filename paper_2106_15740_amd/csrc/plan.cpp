@@ -318,7 +318,9 @@ void order_one(Cone& C, const OrderOptions& O, uint64_t cone_seed) {
 // 2-index tensor per one-qubit gate, 4 indices per two-qubit gate); with it,
 // a gate keeps the index of every qubit it acts on diagonally (Z rotations and
 // ZZ on both of their qubits, CNOT on its control), so the ZZ phase becomes a
-// rank-2 tensor on the two current indices.
+// rank-2 tensor on the two current indices.  Indices are numbered in the order
+// the construction creates them (a two-qubit gate numbers its first qubit's
+// new index first), the numbering of the exported elimination order.
 struct IndexNet {
   int n_idx = 0;
   std::vector<std::vector<int>> tensors;
@@ -361,16 +363,18 @@ IndexNet variant_network(int n, const std::vector<std::pair<int32_t, int32_t>>& 
             one_qubit(w, diag);  // Z rotation on the target
             continue;
           }
-          // CNOT(u -> w): the control keeps its index under the diagonal simplification
-          const int nw = T.n_idx++;
+          // CNOT(u -> w): the control keeps its index under the diagonal
+          // simplification; otherwise the control's new index is numbered first
           if (diag) {
+            const int nw = T.n_idx++;
             T.tensors.push_back({cur[u], cur[w], nw});
+            cur[w] = nw;
           } else {
-            const int nu = T.n_idx++;
+            const int nu = T.n_idx++, nw = T.n_idx++;
             T.tensors.push_back({cur[u], cur[w], nu, nw});
             cur[u] = nu;
+            cur[w] = nw;
           }
-          cur[w] = nw;
         }
       }
     }
@@ -391,7 +395,7 @@ IndexNet variant_network(int n, const std::vector<std::pair<int32_t, int32_t>>& 
 }  // namespace
 
 CostEstimate cost_model(int n, const std::vector<std::pair<int32_t, int32_t>>& edges, int p, int variant,
-                        const OrderOptions& O) {
+                        const OrderOptions& O, std::vector<int>* order_out) {
   const IndexNet T = variant_network(n, edges, p, variant);
   // the orderer works on the interaction graph: a tensor links every pair of
   // its indices
@@ -430,6 +434,7 @@ CostEstimate cost_model(int n, const std::vector<std::pair<int32_t, int32_t>>& e
     if (!out.empty()) place(out);
   }
   R.log2_ops = ops > 0 ? std::log2(ops) : 0.0;
+  if (order_out) *order_out = C.order;
   return R;
 }
 

@@ -163,14 +163,15 @@ void order_cones(Plan& P, const OrderOptions& O, int n_threads);
 
 // Contraction cost of the single-amplitude network under one of the paper's
 // four constructions (0 default, 1 diagonal, 2 ZZ gates, 3 diagonal + ZZ),
-// ordered by the same greedy / randomized greedy orderer.
+// ordered by the same greedy / randomized greedy orderer.  order_out
+// (nullable) receives the elimination order (index ids in construction order).
 struct CostEstimate {
   int n_indices = 0, n_tensors = 0;
   int width = 0;          // largest intermediate rank
   double log2_ops = 0;    // log2 of sum over buckets of 2^|union|
 };
 CostEstimate cost_model(int n, const std::vector<std::pair<int32_t, int32_t>>& edges, int p, int variant,
-                        const OrderOptions& O);
+                        const OrderOptions& O, std::vector<int>* order_out = nullptr);
 // Builds every cone's forward and adjoint programs, places the buffers by
 // lifetime (recomputing bucket outputs in the adjoint sweep where the memory
 // budget requires it) and resolves all operand offsets.

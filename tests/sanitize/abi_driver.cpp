@@ -143,6 +143,21 @@ static void cost_models(int n, const std::vector<int32_t>& edges, int p) {
     }
   qtn_cost c;
   EXPECT(qtn_cost_model(n, m, edges.data(), p, (qtn_net_variant)9, QTN_ORDER_MIN_FILL, 0, 0.5, 7, &c), QTN_EINVAL);
+  // the exported order is a permutation of the indices; a short buffer is refused
+  EXPECT(qtn_cost_model(n, m, edges.data(), p, QTN_NET_DIAGONAL_ZZ, QTN_ORDER_MIN_FILL, 2, 0.5, 7, &c), QTN_OK);
+  std::vector<int32_t> order(c.n_indices, -1), seen(c.n_indices, 0);
+  EXPECT(qtn_cost_model_order(n, m, edges.data(), p, QTN_NET_DIAGONAL_ZZ, QTN_ORDER_MIN_FILL, 2, 0.5, 7, &c,
+                              order.data(), (int32_t)order.size()),
+         QTN_OK);
+  for (int32_t v : order)
+    if (v < 0 || v >= c.n_indices || seen[v]++) {
+      std::fprintf(stderr, "exported order is not a permutation\n");
+      ++g_fail;
+      break;
+    }
+  EXPECT(qtn_cost_model_order(n, m, edges.data(), p, QTN_NET_DIAGONAL_ZZ, QTN_ORDER_MIN_FILL, 2, 0.5, 7, &c,
+                              order.data(), (int32_t)order.size() - 1),
+         QTN_EINVAL);
 }
 
 int main(int argc, char** argv) {
