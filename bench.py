@@ -35,6 +35,11 @@ P5_TIMED_MAX_WIDTH = 23  # widest oracle contraction timed in the p = 5 CPU extr
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_persistent_kernel_p3_n244.json")
 
 
+def log(msg: str) -> None:
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_15740_amd", "csrc")
@@ -250,7 +255,7 @@ WIDE_TUNING = dict(seq_max_bits=16, tile_blocks=128, par_bits=21)
 WIDE_TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_wide_sweep_p5_n1000.json")
 
 
-def wide_leg(repeats: int, steps: int, copy_gbps):
+def wide_leg(repeats: int, steps: int, copy_gbps, retune: bool = False):
     """p = 5, N = 1000 (1500 edges), c64, min-degree randomized greedy order
     (widths up to 26, 0.5 GB tensors): the HBM-bound workload.  Reports the
     whole sweep, the in-sweep rate of its buckets of width >= 20 (their ops as
@@ -258,15 +263,21 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     width band, and the other greedy order."""
     import torch
 
-    from paper_2106_15740_amd import QaoaNet
+    from paper_2106_15740_amd import QaoaNet, tunecache
     from workloads import workload
 
     w = workload("p5_n1000")
     t0 = time.perf_counter()
     net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_degree", device=0, repeats=repeats)
     plan_s = time.perf_counter() - t0
-    net.set_tuning(**WIDE_TUNING)
     net.set_params(w.gamma, w.beta)
+    # tiles: the tuning cache's entry for this plan, else the global and
+    # per-band autotuners started from WIDE_TUNING (and stored)
+    net.set_tuning(**WIDE_TUNING)
+    t1 = time.perf_counter()
+    entry = tunecache.tuned(net, with_grad=True, retune=retune)
+    tune_s = time.perf_counter() - t1
+    log(f"p5_n1000: tiles from {entry['source']} in {tune_s:.1f} s")
     info = net.info()
     dt, e, k_ms, _ = time_sweeps(net, steps, 1)
     pk_ms = net.time_persistent(with_grad=True, reps=2)
@@ -286,11 +297,13 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
         bands.append({"widths": f"{lo}-{hi - 1}" if hi else f">={lo}", "ops": k, "alg_bytes": b, "ms": ms,
                       "achieved_GBps": b / (ms * 1e-3) / 1e9 if ms > 0 else None})
     tuning = net.tuning()
+    bands = net.band_tuning()
     # the same sweep under workspace budgets: a quarter of the keep-everything
     # arena (cones admitted into a shared area as regions free up), and just
     # below the largest cone's own working set (that cone drops outputs after
     # its forward sweep and recomputes them in its adjoint sweep)
     budgets = []
+    log("p5_n1000: memory budgets")
     for label, nbytes in (("quarter_of_keep_all", int(0.25 * info["arena_keep_all"])),
                           ("below_largest_cone", info["pinned_bytes"] + int(0.95 * info["max_cone_dynamic"]))):
         net.set_memory_budget(nbytes)
@@ -305,9 +318,11 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
     net.set_memory_budget(0)
     del net
     torch.cuda.empty_cache()
+    log("p5_n1000: other order")
     # the other greedy order (min-fill: narrower, widths up to 25 on this graph)
     net_mf = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=0, repeats=repeats)
-    net_mf.set_tuning(**WIDE_TUNING)
+    net_mf.set_tuning(**tuning)
+    net_mf.set_band_tuning(bands)
     net_mf.set_params(w.gamma, w.beta)
     info_mf = net_mf.info()
     dt_mf, e_mf, k_ms_mf, _ = time_sweeps(net_mf, steps, 1)
@@ -339,6 +354,8 @@ def wide_leg(repeats: int, steps: int, copy_gbps):
         "energy": e,
         "plan_s": plan_s,
         "tuning": tuning,
+        "band_tuning": bands,
+        "tuning_source": {"source": entry["source"], "key": entry["key"], "seconds": tune_s},
         "other_order": other,
     }
     roof20 = {"bound": "hbm", "achieved": ws20["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -393,19 +410,22 @@ def profile_leg(which: str, repeats: int):
     """One p = 5 measurement alone, for profiler runs: `p5_sweep` times the
     persistent kernel of the whole sweep, `p5_wide20` the width >= 20 ops as a
     launch of their own (both after one warm sweep)."""
-    from paper_2106_15740_amd import QaoaNet
+    from paper_2106_15740_amd import QaoaNet, tunecache
     from workloads import workload
 
     w = workload("p5_n1000")
     net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_degree", device=0, repeats=repeats)
     net.set_tuning(**WIDE_TUNING)
+    entry = tunecache.tuned(net, with_grad=True, search=False)  # the cached tiles, if any
     net.set_params(w.gamma, w.beta)
     net.energy_grad("batched")
     info = net.info()
-    out = {"profile": which, "tuning": net.tuning()}
+    out = {"profile": which, "tuning": net.tuning(), "band_tuning": net.band_tuning(),
+           "tuning_source": None if entry is None else entry["source"]}
     if which == "p5_sweep":
         out["persistent_kernel_ms"] = net.time_persistent(with_grad=True, reps=3)
-        out["alg_bytes_per_launch"] = info["fwd_bytes_bucket"] + info["bwd_bytes_bucket"]
+        out["alg_bytes_per_launch"] = info["fwd_bytes"] + info["bwd_bytes"]
+        out["alg_bytes_per_launch_index_buckets"] = info["fwd_bytes_bucket"] + info["bwd_bytes_bucket"]
     else:
         out.update(net.time_wide_sweep(min_width=20, with_grad=True, reps=3))
     print(json.dumps(out))
@@ -422,6 +442,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuners even when the tuning cache has an entry for the plan (and store it)")
     ap.add_argument("--tuning", default="",
                     help="fixed tile shapes instead of the autotuner, e.g. threads=128,lane_cap=7,seq_max_bits=14")
     ap.add_argument("--no-wide", action="store_true", help="skip the p=5 N=1000 leg")
@@ -455,26 +477,32 @@ def main():
     if not args.no_cpu:
         import subprocess
 
+        log("CPU oracle baseline")
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only", "--workload", args.workload],
                            capture_output=True, text=True, check=True)
         cpu = json.loads(r.stdout.strip().splitlines()[-1])
+        log(f"CPU oracle baseline done: {cpu['value']:.1f} {cpu['unit']}")
 
     import torch
 
-    from paper_2106_15740_amd import QaoaNet, copy_bandwidth
+    from paper_2106_15740_amd import QaoaNet, copy_bandwidth, tunecache
 
     t0 = time.perf_counter()
     net = QaoaNet(w.n, w.edges, w.p, dtype=w.dtype, order=w.order, device=0, repeats=args.repeats)
     plan_s = time.perf_counter() - t0
     net.set_params(w.gamma, w.beta)
+    log(f"{args.workload}: plan built in {plan_s:.1f} s; tuning")
+    tune_entry = None
     if args.tuning:
         net.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
-        tuned = net.tuning()
-    else:
-        tuned = net.tuning() if args.no_autotune else net.autotune(with_grad=True)
+    elif not args.no_autotune:
+        tune_entry = tunecache.tuned(net, with_grad=True, retune=args.retune)
+    tuned = net.tuning()
     info = net.info()
 
+    log(f"{args.workload}: timing {args.steps} steps")
     dt, e, k_avg_ms, k_cnt = time_sweeps(net, args.steps, args.warmup)
+    log(f"{args.workload}: {1e3 * dt / args.steps:.3f} ms per step")
     ms_step = 1e3 * dt / args.steps
     cones_per_s = len(w.edges) * args.steps / dt
     # the dominant kernel alone: HIP events around the persistent kernel on
@@ -550,12 +578,16 @@ def main():
         "energy": e,
         "plan_s": plan_s,
         "tuning": tuned,
+        "tuning_source": None if tune_entry is None else {"source": tune_entry["source"], "key": tune_entry["key"]},
     }
     if not args.no_wide:
         del net
         torch.cuda.empty_cache()
-        out["wide"], out["roofline_width_ge_20"] = wide_leg(args.repeats, steps=3, copy_gbps=copy_gbps)
+        log("p5_n1000 leg")
+        out["wide"], out["roofline_width_ge_20"] = wide_leg(args.repeats, steps=3, copy_gbps=copy_gbps,
+                                                            retune=args.retune)
     if not args.no_amplitude:
+        log("amplitude leg")
         out["amplitude"] = amplitude_leg()
     if cpu is not None:
         cpu["gpu_speedup"] = cones_per_s / cpu["value"]

@@ -228,8 +228,9 @@ qtn_status qtn_set_tuning(qtn_net* net, const qtn_tuning* t);
  * `stream` by coordinate descent over four groups (workgroup size and lane
  * cap; split thresholds seq_max_bits and tile_blocks; merge_bits and
  * merge_lam_bits; lds_threads and lds_kb), keeps the fastest setting and
- * returns it in *best
- * (nullable).  Needs qtn_set_params first and a workspace as for the sweep;
+ * returns it in *best (nullable).  Each candidate: one warm sweep, one timed
+ * sweep, then the average of max(reps, about 25 ms worth, at most 200)
+ * replays.  Needs qtn_set_params first and a workspace as for the sweep;
  * settings whose workspace would not fit in ws_bytes are skipped. */
 qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
                         int32_t reps, qtn_tuning* best);
@@ -239,6 +240,35 @@ qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t
  * host outputs since the last reset, from HIP events recorded on the launch
  * stream around the replay; and the number of such sweeps. */
 qtn_status qtn_kernel_time(qtn_net* net, double* ms_sum, int64_t* count, int32_t reset);
+
+/* Tile parameters of wide buckets by bucket signature band: band 0 = buckets
+ * of more than seq_max_bits and at most 20 union bits, band 1 = 21..24, band 2
+ * = 25 or more (Section III.B: the union of a bucket, its width + 1).  A field
+ * of 0 keeps the global value, the qtn_tuning field of the same name; else
+ * par_bits in 8..24, tile_blocks a power of two, loop_cap in 1..31.
+ * Sequential programs (seq_max_bits or fewer union bits) are not affected. */
+#define QTN_BANDS 3
+typedef struct {
+  int32_t par_bits, tile_blocks, loop_cap;
+} qtn_band_tuning;
+/* out[QTN_BANDS] (host). */
+qtn_status qtn_get_band_tuning(const qtn_net* net, qtn_band_tuning* out);
+/* in[QTN_BANDS] (host); rebuilds the device plan like qtn_set_tuning.
+ * QTN_EINVAL for values out of range; a band setting that leaves some wide
+ * bucket without a valid tiling is refused (QTN_EUNSUPPORTED) and the
+ * previous bands are kept. */
+qtn_status qtn_set_band_tuning(qtn_net* net, const qtn_band_tuning* in);
+/* Per-band autotuner: for each band that holds a wide bucket, times the
+ * band's ops as a sub-sweep of their own (as qtn_time_wide_sweep, all kinds,
+ * `reps` replays) for par_bits in {19, 21, 23} x tile_blocks in {64, 128,
+ * 256} with the bands already tuned in place, and keeps the fastest.  Leaves
+ * the chosen bands set, writes them to best_out[QTN_BANDS] (nullable) and
+ * the whole persistent sweep's time (as qtn_time_persistent) to ms_out
+ * (nullable).  Workspace and errors as qtn_autotune; candidates whose plan
+ * needs a larger workspace are skipped.  Host work: one plan rebuild per
+ * candidate. */
+qtn_status qtn_autotune_bands(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
+                              int32_t reps, qtn_band_tuning* best_out, double* ms_out);
 
 /* Times the contraction ops of buckets whose output rank is >= min_width
  * (forward and, with with_grad, adjoint ops) one launch at a time on

@@ -24,7 +24,7 @@ EXPORTS = [
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
     "qtn_kernel_time", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
     "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model", "qtn_cost_model_order", "qtn_energy_grad_noalloc",
-    "qtn_time_wide_sweep",
+    "qtn_time_wide_sweep", "qtn_get_band_tuning", "qtn_set_band_tuning", "qtn_autotune_bands",
     "qtn_net_free",
 ]
 
@@ -41,6 +41,16 @@ class Tuning(C.Structure):
                 ("lds_kb", C.c_int32), ("par_bits", C.c_int32), ("merge_bits", C.c_int32),
                 ("merge_lam_bits", C.c_int32), ("lane_low", C.c_int32),
                 ("fuse_adjoint", C.c_int32), ("lds_threads", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+QTN_BANDS = 3
+
+
+class BandTuning(C.Structure):
+    _fields_ = [("par_bits", C.c_int32), ("tile_blocks", C.c_int32), ("loop_cap", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -111,6 +121,9 @@ def lib() -> C.CDLL:
         "qtn_energy_grad_noalloc": (I32, [P, I32, P, P, P, P, P]),
         "qtn_time_wide_sweep": (I32, [P, I32, I32, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D),
                                       C.POINTER(I64), C.POINTER(I64)]),
+        "qtn_get_band_tuning": (I32, [P, P]),
+        "qtn_set_band_tuning": (I32, [P, P]),
+        "qtn_autotune_bands": (I32, [P, I32, P, SZ, P, I32, P, C.POINTER(D)]),
         "qtn_net_free": (None, [P]),
     }
     for name, (res, args) in sig.items():

@@ -826,14 +826,21 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
     }
     if ((r = check_ready(n, ws, ws_bytes, with_grad != 0)) != QTN_OK) return r;
     if ((r = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, true)) != QTN_OK) return r;
-    HIPCHECK(hipEventRecord(e0, st));
-    for (int k = 0; k < reps; ++k)
-      if ((r = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, false)) != QTN_OK) return r;
-    HIPCHECK(hipEventRecord(e1, st));
-    HIPCHECK(hipEventSynchronize(e1));
-    if (sweep_flag(n)) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
+    // one timed sweep sizes the replay count: about 25 ms of sweeps per
+    // candidate (short sweeps are noisy), at least `reps`, at most 200
     float ms = 0;
-    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    int k_reps = 1;
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHECK(hipEventRecord(e0, st));
+      for (int k = 0; k < k_reps; ++k)
+        if ((r = run_sweep(n, QTN_BATCHED, with_grad != 0, ws, ws_bytes, st, nullptr, false)) != QTN_OK) return r;
+      HIPCHECK(hipEventRecord(e1, st));
+      HIPCHECK(hipEventSynchronize(e1));
+      if (sweep_flag(n)) return fail(QTN_EDEVICE, "persistent sweep gave up waiting on a dependency");
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)k_reps;
+      if (pass == 0) k_reps = std::max(reps, std::min(200, (int)std::ceil(25.0 / std::max(ms, 1e-3f))));
+    }
     *ms_out = ms;
     return QTN_OK;
   };
@@ -1155,6 +1162,89 @@ qtn_status qtn_copy_bandwidth(qtn_ctx* ctx, void* buf, size_t bytes, void* strea
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(QTN_EDEVICE, std::string("copy kernel: ") + hipGetErrorString(e));
   if (gbps_out) *gbps_out = best;
+  return QTN_OK;
+}
+
+qtn_status qtn_get_band_tuning(const qtn_net* n, qtn_band_tuning* out) {
+  if (!n || !out) return fail(QTN_EINVAL, "net or out is NULL");
+  for (int b = 0; b < QTN_BANDS; ++b) {
+    out[b].par_bits = n->P.tune.band[b].par_bits;
+    out[b].tile_blocks = n->P.tune.band[b].tile_blocks;
+    out[b].loop_cap = n->P.tune.band[b].loop_cap;
+  }
+  return QTN_OK;
+}
+
+qtn_status qtn_set_band_tuning(qtn_net* n, const qtn_band_tuning* in) {
+  if (!n || !in) return fail(QTN_EINVAL, "net or in is NULL");
+  for (int b = 0; b < QTN_BANDS; ++b) {
+    const qtn_band_tuning& t = in[b];
+    if (t.par_bits != 0 && (t.par_bits < 8 || t.par_bits > 24)) return fail(QTN_EINVAL, "band par_bits must be 0 or 8..24");
+    if (t.tile_blocks < 0 || (t.tile_blocks & (t.tile_blocks - 1)))
+      return fail(QTN_EINVAL, "band tile_blocks must be 0 or a power of two");
+    if (t.loop_cap < 0 || t.loop_cap > 31) return fail(QTN_EINVAL, "band loop_cap must be in 0..31");
+  }
+  TuneParams::Band old[TuneParams::kBands];
+  for (int b = 0; b < QTN_BANDS; ++b) {
+    old[b] = n->P.tune.band[b];
+    n->P.tune.band[b].par_bits = in[b].par_bits;
+    n->P.tune.band[b].tile_blocks = in[b].tile_blocks;
+    n->P.tune.band[b].loop_cap = in[b].loop_cap;
+  }
+  if (!n->P.ordered) return QTN_OK;
+  qtn_status s = rebuild_programs(n);
+  if (s != QTN_OK) {
+    const std::string msg = qtn_last_error();
+    for (int b = 0; b < QTN_BANDS; ++b) n->P.tune.band[b] = old[b];
+    (void)rebuild_programs(n);
+    return fail(s, msg);
+  }
+  return QTN_OK;
+}
+
+qtn_status qtn_autotune_bands(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes, void* stream, int32_t reps,
+                              qtn_band_tuning* best_out, double* ms_out) {
+  qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
+  if (s != QTN_OK) return s;
+  if (reps < 1) reps = 2;
+  // widths (output ranks) of each band's buckets: union bits - 1
+  const int lo_w[QTN_BANDS] = {n->P.tune.seq_max_bits, 20, 24};
+  const int hi_w[QTN_BANDS] = {19, 23, MAXBITS};
+  qtn_band_tuning cur[QTN_BANDS];
+  qtn_get_band_tuning(n, cur);
+  for (int b = 0; b < QTN_BANDS && s == QTN_OK; ++b) {
+    if (lo_w[b] > hi_w[b]) continue;
+    bool any = false;
+    for (const OpDesc& d : n->P.ops)
+      any |= (d.kind == OP_CONTRACT || d.kind == OP_ADJOINT) && d.nbits - 1 >= lo_w[b] && d.nbits - 1 <= hi_w[b];
+    if (!any) continue;
+    double best = 1e300;
+    qtn_band_tuning keep = cur[b];
+    for (int pb : {19, 21, 23})
+      for (int tb : {64, 128, 256}) {
+        cur[b].par_bits = pb;
+        cur[b].tile_blocks = tb;
+        cur[b].loop_cap = 0;
+        if (qtn_set_band_tuning(n, cur) != QTN_OK) continue;  // no valid plan with these tiles
+        if (ws_layout(n, with_grad != 0).total > ws_bytes) continue;
+        if ((s = check_ready(n, ws, ws_bytes, with_grad != 0)) != QTN_OK) break;
+        double bytes = 0, ms = 0;
+        s = qtn_time_wide_sweep(n, with_grad, lo_w[b], hi_w[b], 7, ws, ws_bytes, stream, reps, &bytes, &ms, nullptr,
+                                nullptr);
+        if (s != QTN_OK) break;
+        if (ms < best) {
+          best = ms;
+          keep = cur[b];
+        }
+      }
+    cur[b] = keep;
+  }
+  if (s == QTN_OK) s = qtn_set_band_tuning(n, cur);
+  if (s != QTN_OK) return s;
+  n->kernel_ms_sum = 0;
+  n->kernel_count = 0;
+  if (best_out) qtn_get_band_tuning(n, best_out);
+  if (ms_out) return qtn_time_persistent(n, with_grad, ws, ws_bytes, stream, reps, ms_out);
   return QTN_OK;
 }
 

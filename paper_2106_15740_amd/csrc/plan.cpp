@@ -638,7 +638,8 @@ void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool w
 // most 4 inputs, all but input 0 holding the eliminated index, go to the wide
 // executor when every block range they are given (a tile of tile_blocks
 // blocks, or all blocks) holds at least one block per sub-block.
-void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T) {
+void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T0) {
+  const TuneParams T = T0.for_bits(nbits);
   bool wide = !seq && d.n_in <= 4;
   for (int i = 1; i < d.n_in; ++i) wide = wide && (d.in_mask[i] & 1u) != 0;
   if (wide) {
@@ -776,7 +777,8 @@ void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool w
 // adjoint) for a single input (its adjoint does not read it, so it need not
 // be kept), more than 3 inputs, an input without the eliminated index, no
 // group of at least 2 bits, or too few blocks per tile.
-bool fused_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) {
+bool fused_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T0) {
+  const TuneParams T = T0.for_bits(nbits);
   if (d.n_in < 3 || d.n_in > 4 || (d.in_mask[0] & 1u)) return false;
   d.adj_sel = 0;
   for (int i = 1; i < d.n_in; ++i) {
@@ -924,7 +926,8 @@ bool tile_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) 
 // every element, so it must sum lane bits only.  Loop length as in the fused
 // rule.  Returns false when no pair qualifies or the block range is smaller
 // than a workgroup step.
-bool outer_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T) {
+bool outer_adjoint_bits(OpDesc& d, int nbits, uint32_t all, const TuneParams& T0) {
+  const TuneParams T = T0.for_bits(nbits);
   // complex64 only: with complex128 pairs the slots would lower the occupancy
   // of the whole persistent kernel
   if (T.elem_bytes != 8 || d.n_in < 3 || d.n_in > 4 || (d.in_mask[0] & 1u)) return false;
@@ -1842,7 +1845,7 @@ static std::string validate_adjoint_op(const Plan& P, const OpDesc& d) {
   if (tiled && (tile_elems != d.aux0 || d.aux0 > P.lds_elems)) return "LDS-tiled adjoint tile size";
   if (atomic != bool(d.flags & F_ATOMIC)) return "adjoint op atomic flag mismatch";
   const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
-  if (std::min<int64_t>(std::max(1, P.tune.tile_blocks), int64_t(1) << d.nb) < nsub)
+  if (std::min<int64_t>(std::max(1, P.tune.for_bits(d.nbits).tile_blocks), int64_t(1) << d.nb) < nsub)
     return "adjoint op block range smaller than a workgroup step";
   for (int i = 0; i < d.n_in; ++i) {
     const int64_t sz = int64_t(1) << __builtin_popcount(d.in_mask[i]);
@@ -2074,7 +2077,7 @@ std::string validate_plan(const Plan& P) {
       for (int i = 1; i < d.n_in; ++i)
         if (!(d.in_mask[i] & 1u)) return "op " + S(o) + "wide op input without the eliminated index";
       const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
-      if (std::min<int64_t>(std::max(1, P.tune.tile_blocks), int64_t(1) << d.nb) < nsub)
+      if (std::min<int64_t>(std::max(1, P.tune.for_bits(d.nbits).tile_blocks), int64_t(1) << d.nb) < nsub)
         return "op " + S(o) + "wide op block range smaller than a workgroup step";
       if (d.nbits <= P.tune.seq_max_bits) return "op " + S(o) + "wide op inside a sequential program";
     } else if (d.nu > ((P.tune.elem_bytes == 8 && d.n_in <= 2) ? 1 : 0)) {
@@ -2246,9 +2249,10 @@ static void cone_chains(const Plan& P, bool grad, const std::function<bool(int32
           close();
           open_here = false;
           // tiles of an LDS-tiled adjoint: about 2^16 union elements per item
-          const int64_t per = (d.flags & F_TILE) ? std::min<int64_t>(std::max(1, T.tile_blocks),
+          const int tb = T.for_bits(d.nbits).tile_blocks;
+          const int64_t per = (d.flags & F_TILE) ? std::min<int64_t>(std::max(1, tb),
                                                                        int64_t(1) << std::max(0, 16 - d.nl - d.nk))
-                                                 : std::max(1, T.tile_blocks);
+                                                 : std::max(1, tb);
           segs[c].push_back(Seg{{o, o + 1, -1, -1}, true, int64_t(1) << d.nb, per});
         } else {
           if (!open_here) {

@@ -111,6 +111,24 @@ struct TuneParams {
   int fuse_adjoint = 1;     // wide buckets: every input adjoint in one pass where a loop-bit group fits (1), also
                             // LDS tiles for the others (2), or one op per input (0)
   int lds_threads = 256;    // workgroup size of the kernel that runs the LDS-resident cones
+  // Tile parameters of wide ops by union size (bucket signature bands: <= 20,
+  // 21..24, >= 25 union bits); 0 keeps the value above.
+  struct Band {
+    int par_bits = 0, tile_blocks = 0, loop_cap = 0;
+  };
+  static constexpr int kBands = 3;
+  Band band[kBands];
+  static int band_of(int nbits) { return nbits <= 20 ? 0 : (nbits <= 24 ? 1 : 2); }
+  // the parameters an op with nbits union bits is planned with
+  TuneParams for_bits(int nbits) const {
+    TuneParams t = *this;
+    if (nbits <= seq_max_bits) return t;  // sequential programs keep the global values
+    const Band& b = band[band_of(nbits)];
+    if (b.par_bits) t.par_bits = b.par_bits;
+    if (b.tile_blocks) t.tile_blocks = b.tile_blocks;
+    if (b.loop_cap) t.loop_cap = b.loop_cap;
+    return t;
+  }
 };
 
 struct Plan {

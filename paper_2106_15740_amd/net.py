@@ -142,6 +142,28 @@ class QaoaNet:
         L.check(self._lib.qtn_set_tuning(self.handle, C.byref(t)))
         self._ws = {k: v for k, v in self._ws.items() if k == "buf"}
 
+    def band_tuning(self) -> list:
+        """Tile parameters of wide buckets per union-size band (0: the global
+        value): [{'par_bits', 'tile_blocks', 'loop_cap'}] * QTN_BANDS."""
+        arr = (L.BandTuning * L.QTN_BANDS)()
+        L.check(self._lib.qtn_get_band_tuning(self.handle, arr))
+        return [b.as_dict() for b in arr]
+
+    def set_band_tuning(self, bands) -> None:
+        arr = (L.BandTuning * L.QTN_BANDS)()
+        for i, b in enumerate(bands):
+            for k, v in b.items():
+                setattr(arr[i], k, int(v))
+        L.check(self._lib.qtn_set_band_tuning(self.handle, arr))
+        self._ws = {k: v for k, v in self._ws.items() if k == "buf"}
+
+    def signature(self) -> str:
+        """The plan's shape before tiling (cones, depth, dtype, contraction width,
+        buckets and their algorithmic bytes): the key of tuning caches."""
+        i = self.info()
+        return (f"n{i['n_cones']}-p{i['p']}-{self.dtype}-w{i['max_width']}-b{i['n_buckets']}-"
+                f"B{int(i['fwd_bytes_bucket'])}")
+
     # ------------------------------------------------------------------ device work
     def _workspace(self, with_grad: bool):
         import torch
@@ -233,6 +255,17 @@ class QaoaNet:
                                        self._stream(), int(reps), C.byref(t)))
         self._ws = {k: v for k, v in self._ws.items() if k == "buf"}
         return t.as_dict()
+
+    def autotune_bands(self, with_grad: bool = True, reps: int = 2) -> Tuple[list, float]:
+        """Per-band tile search (qtn_autotune_bands): the chosen bands and the
+        whole persistent sweep's device ms with them."""
+        ws = self._workspace(with_grad)
+        arr = (L.BandTuning * L.QTN_BANDS)()
+        ms = C.c_double()
+        L.check(self._lib.qtn_autotune_bands(self.handle, int(bool(with_grad)), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                             self._stream(), int(reps), arr, C.byref(ms)))
+        self._ws = {k: v for k, v in self._ws.items() if k == "buf"}
+        return [b.as_dict() for b in arr], ms.value
 
     def time_wide_ops(self, min_width: int = 20, with_grad: bool = True, reps: int = 2) -> Tuple[float, float, int]:
         """(algorithmic bytes, device ms, op count) of the contraction ops whose

@@ -70,6 +70,16 @@ static void tunings(qtn_net* net, int m, bool per_edge) {
   t.lds_kb = 1000;
   EXPECT(qtn_set_tuning(net, &t), QTN_EINVAL);
   EXPECT(qtn_set_tuning(net, &t0), QTN_OK);
+  // tiles per bucket-signature band
+  qtn_band_tuning b[QTN_BANDS] = {{19, 64, 8}, {23, 256, 0}, {0, 0, 0}}, got[QTN_BANDS];
+  EXPECT(qtn_set_band_tuning(net, b), QTN_OK);
+  check_plan(net, m, per_edge);
+  EXPECT(qtn_get_band_tuning(net, got), QTN_OK);
+  if (got[0].par_bits != 19 || got[1].tile_blocks != 256) ++g_fail;
+  qtn_band_tuning bad[QTN_BANDS] = {{40, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  EXPECT(qtn_set_band_tuning(net, bad), QTN_EINVAL);
+  const qtn_band_tuning zero[QTN_BANDS] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  EXPECT(qtn_set_band_tuning(net, zero), QTN_OK);
 }
 
 static void budgets(qtn_net* net, int m) {

@@ -120,6 +120,26 @@ def test_p3_n244_autotuned_plan_vs_oracle():
     check_against_golden("p3_n244", net, "plain")
 
 
+def test_p4_n100_band_autotuned_and_cached_plan_vs_oracle(tmp_path):
+    """The global and per-band autotuners (tunecache.tuned) pick the tiles of
+    the p = 4 workload and store them under (architecture, dtype, plan
+    signature); a second net of the same plan takes them from the cache.  Both
+    plans pass the full comparison with the oracle."""
+    from paper_2106_15740_amd import tunecache
+
+    path = str(tmp_path / "tune.json")
+    _, net = net_for("p4_n100", "min_fill")
+    e = tunecache.tuned(net, with_grad=True, path=path)
+    print(f"[tuned] {e}", flush=True)
+    assert e["source"] == "search" and e["stored"]
+    check_against_golden("p4_n100", net, "batched")
+    _, net2 = net_for("p4_n100", "min_fill")
+    e2 = tunecache.tuned(net2, with_grad=True, path=path, search=False)
+    assert e2["source"] == "cache" and e2["key"] == e["key"]
+    assert net2.tuning() == net.tuning() and net2.band_tuning() == net.band_tuning()
+    check_against_golden("p4_n100", net2, "batched")
+
+
 def test_p4_n100_every_edge_vs_oracle():
     """p = 4, N = 100 (150 edges, widths up to 22): every edge term and, for
     one edge per oracle width, its derivatives."""

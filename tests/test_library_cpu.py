@@ -124,6 +124,37 @@ def test_wide_plans_fused_and_separate_adjoints(fuse, lane_low, seq_max_bits, th
         net.set_tuning(fuse_adjoint=4)
 
 
+def test_band_tuning_plans():
+    """Tile parameters per bucket-signature band (union bits <= 20, 21..24,
+    >= 25) re-plan only the wide buckets of their band: the plan stays valid,
+    the queue changes, sequential programs and algorithmic bytes do not; bad
+    values are refused and keep the previous bands; zeros restore the global
+    values.  The plan signature (the tuning cache's key) ignores tiling."""
+    w = workload("p4_n100")
+    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=None)
+    net.set_tuning(seq_max_bits=12)
+    sig = net.signature()
+    base = net.info()
+    assert net.band_tuning() == [dict(par_bits=0, tile_blocks=0, loop_cap=0)] * 3
+    bands = [dict(par_bits=19, tile_blocks=64, loop_cap=8), dict(par_bits=23, tile_blocks=256, loop_cap=0), {}]
+    net.set_band_tuning(bands)
+    net.validate()
+    got = net.info()
+    assert got["n_items_grad"] != base["n_items_grad"]
+    assert got["fwd_bytes"] == base["fwd_bytes"] and got["bwd_bytes"] == base["bwd_bytes"]
+    assert got["n_lds_cones"] == base["n_lds_cones"]
+    assert net.signature() == sig
+    before = net.band_tuning()
+    for bad in ([dict(par_bits=30), {}, {}], [dict(tile_blocks=3), {}, {}], [dict(loop_cap=40), {}, {}]):
+        with pytest.raises(QtnError) as ei:
+            net.set_band_tuning(bad)
+        assert ei.value.status == L.QTN_EINVAL
+        assert net.band_tuning() == before
+    net.set_band_tuning([{}, {}, {}])
+    assert net.info()["n_items_grad"] == base["n_items_grad"]
+    net.validate()
+
+
 @pytest.mark.parametrize("edges,n,p", [([(0, 0)], 2, 1), ([(0, 1), (1, 0)], 2, 1), ([(0, 5)], 3, 1),
                                        ([(0, 1)], 2, 0), ([(-1, 1)], 2, 1)])
 def test_invalid_graphs_rejected(edges, n, p):
