@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 P5_TIMED_MAX_WIDTH = 23  # widest oracle contraction timed in the p = 5 CPU extrapolation
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_persistent_kernel_p3_n244.json")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_small_kernel_p3_n244.json")
+P5_TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_persistent_kernel_p5_n1000.json")
 
 
 def log(msg: str) -> None:
@@ -51,7 +52,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=TRAFFIC_JSON, tuning=None):
+def measured_traffic(path=TRAFFIC_JSON, tuning=None, bands=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     runs, only while the kernel sources (and the tile shapes) are the ones
     they were taken with."""
@@ -63,6 +64,8 @@ def measured_traffic(path=TRAFFIC_JSON, tuning=None):
     if t.get("source_hash") != kernel_source_hash():
         return None
     if tuning is not None and t.get("tuning") not in (None, tuning):
+        return None
+    if bands is not None and t.get("band_tuning") not in (None, bands):
         return None
     return t.get("bytes_per_launch")
 
@@ -346,6 +349,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps, retune: bool = False):
         "persistent_kernel_ms": pk_ms,
         "achieved_GBps": achieved_b,
         "frac_of_peak": achieved_b / HBM_PEAK_GBS,
+        "traffic_bytes_per_launch": measured_traffic(P5_TRAFFIC_JSON, tuning, bands),
         "frac_of_copy": achieved_b / copy_gbps if copy_gbps else None,
         "workspace_GB": info["ws_grad"] / 1e9,
         "keep_all_GB": info["arena_keep_all"] / 1e9,
@@ -360,9 +364,10 @@ def wide_leg(repeats: int, steps: int, copy_gbps, retune: bool = False):
     }
     roof20 = {"bound": "hbm", "achieved": ws20["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": ws20["achieved_GBps"] / HBM_PEAK_GBS if ws20["achieved_GBps"] else None,
-              "traffic": measured_traffic(WIDE_TRAFFIC_JSON, tuning),
+              "traffic": measured_traffic(WIDE_TRAFFIC_JSON, tuning, bands),
               "kernel": "persistent_kernel (queue of the width >= 20 ops only)",
-              "kernel_ms": ws20["ms"], "alg_bytes_per_launch": ws20["alg_bytes"], "ops": ws20["ops"],
+              "kernel_ms": ws20["ms"], "alg_bytes_per_launch": ws20["alg_bytes"],
+              "op_bytes_per_launch": ws20["op_bytes"], "ops": ws20["ops"],
               "items": ws20["items"], "copy_kernel_GBps": copy_gbps,
               "frac_of_copy": ws20["achieved_GBps"] / copy_gbps if (copy_gbps and ws20["achieved_GBps"]) else None,
               "workload": "p=5 N=1000 min-degree randomized greedy: every forward and adjoint op of a bucket with "
@@ -562,7 +567,11 @@ def main():
         "roofline": {"bound": "latency", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(TRAFFIC_JSON, tuned),
-                     "kernel": "persistent_kernel", "kernel_ms": pk_ms, "sweep_ms": k_avg_ms,
+                     "kernel": ("small_kernel (every light cone LDS-resident, one workgroup each)"
+                                if info["n_lds_cones"] == len(w.edges) else
+                                "persistent_kernel" if info["n_lds_cones"] == 0 else
+                                "small_kernel (LDS-resident cones) + persistent_kernel (queued cones)"),
+                     "kernel_ms": pk_ms, "sweep_ms": k_avg_ms,
                      "alg_bytes_per_launch": alg_merged,
                      "alg_bytes_per_launch_index_buckets": alg_bytes,
                      "copy_kernel_GBps": copy_gbps,

@@ -289,18 +289,24 @@ qtn_status qtn_time_wide_ops(qtn_net* net, int32_t with_grad, int32_t min_width,
  * launch of the persistent kernel, `reps` times (after one warm-up) between
  * HIP events on `stream`.  Reads the tensors left in `workspace` by the last
  * sweep of the same kind (outputs are overwritten or accumulated, so run a
- * sweep again before reading results).  Returns the ops' algorithmic bytes
- * (each input read once, output written once), the average device time, and
- * the op and queue-item counts.  Allocates (and frees) the sub-queue's device
- * copy.  QTN_EDEVICE if a dependency wait gave up. */
+ * sweep again before reading results).  Returns (each output nullable) the
+ * algorithmic bytes of the selected contraction steps as qtn_info's fwd_bytes
+ * and bwd_bytes count them (forward, if kinds has bit 0: every input read and
+ * the output written; adjoint, if kinds has bit 1 or 2: the output adjoint
+ * and every stored input read and every input adjoint written), the ops' own
+ * operand bytes (each op's inputs read and output written once: one-input
+ * adjoint passes read the output adjoint again), the average device time,
+ * and the op and queue-item counts.  Allocates (and frees) the sub-queue's
+ * device copy.  QTN_EDEVICE if a dependency wait gave up. */
 qtn_status qtn_time_wide_sweep(qtn_net* net, int32_t with_grad, int32_t min_width, int32_t max_width, int32_t kinds,
                                void* workspace, size_t ws_bytes, void* stream, int32_t reps, double* bytes_out,
-                               double* ms_out, int64_t* n_ops_out, int64_t* n_items_out);
+                               double* op_bytes_out, double* ms_out, int64_t* n_ops_out, int64_t* n_items_out);
 
-/* Device time of the persistent kernel alone: `reps` batched sweeps (after
- * one warm-up) are enqueued on `stream` without graph capture, each with HIP
- * events right before and after the persistent kernel; *ms_out is their
- * average.  Needs qtn_set_params and a workspace as for the sweep.  QTN_EDEVICE
+/* Device time of the sweep's contraction kernels alone (the kernel of the
+ * LDS-resident light cones, when there are any, then the persistent kernel
+ * of the queued ones, when there are any): `reps` batched sweeps (after one
+ * warm-up) are enqueued on `stream` without graph capture, each with HIP
+ * events right before and after those kernels; *ms_out is their average.  Needs qtn_set_params and a workspace as for the sweep.  QTN_EDEVICE
  * if a sweep's dependency wait gave up. */
 qtn_status qtn_time_persistent(qtn_net* net, int32_t with_grad, void* workspace, size_t ws_bytes, void* stream,
                                int32_t reps, double* ms_out);

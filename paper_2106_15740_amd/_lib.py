@@ -119,7 +119,7 @@ def lib() -> C.CDLL:
         "qtn_cost_model": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost)]),
         "qtn_cost_model_order": (I32, [I32, I32, P, I32, I32, I32, I32, D, C.c_uint64, C.POINTER(Cost), P, I32]),
         "qtn_energy_grad_noalloc": (I32, [P, I32, P, P, P, P, P]),
-        "qtn_time_wide_sweep": (I32, [P, I32, I32, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D),
+        "qtn_time_wide_sweep": (I32, [P, I32, I32, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(D),
                                       C.POINTER(I64), C.POINTER(I64)]),
         "qtn_get_band_tuning": (I32, [P, P]),
         "qtn_set_band_tuning": (I32, [P, P]),

@@ -953,8 +953,8 @@ qtn_status qtn_time_wide_ops(qtn_net* n, int32_t with_grad, int32_t min_width, v
 }
 
 qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width, int32_t max_width, int32_t kinds,
-                               void* ws, size_t ws_bytes, void* stream, int32_t reps, double* bytes_out, double* ms_out,
-                               int64_t* n_ops_out, int64_t* n_items_out) {
+                               void* ws, size_t ws_bytes, void* stream, int32_t reps, double* bytes_out,
+                               double* op_bytes_out, double* ms_out, int64_t* n_ops_out, int64_t* n_items_out) {
   qtn_status s = check_ready(n, ws, ws_bytes, with_grad != 0);
   if (s != QTN_OK) return s;
   if (reps < 1) return fail(QTN_EINVAL, "reps must be >= 1");
@@ -989,13 +989,33 @@ qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width,
     bytes += b * n->elem;
     ++cnt;
   }
+  // algorithmic bytes of the selected contraction steps, as the sweep's
+  // totals count them: forward, every input read and the output written;
+  // adjoint, the output adjoint and every stored input read and every input
+  // adjoint written (queued cones only: LDS-resident ones are not in a
+  // sub-sweep)
+  double alg = 0;
+  for (size_t c = 0; c < n->P.cones.size(); ++c) {
+    if (!n->P.cone_lds.empty() && n->P.cone_lds[c]) continue;
+    for (const Bucket& B : n->P.cones[c].buckets) {
+      const int w = B.nbits() - 1;
+      if (w < min_width || w > max_width) continue;
+      double in = 0;
+      for (uint32_t m : B.in_mask) in += std::ldexp(1.0, __builtin_popcount(m));
+      const double out = std::ldexp(1.0, B.out_rank());
+      if (kinds & 1) alg += in + out;
+      if (grad && (kinds & 6)) alg += out + 2 * in;
+    }
+  }
+  alg *= n->elem;
   Queue q;
   try {
     build_queue(n->P, grad, keep, q);
   } catch (const std::bad_alloc&) {
     return fail(QTN_ENOMEM, "host allocation failed");
   }
-  if (bytes_out) *bytes_out = bytes;
+  if (bytes_out) *bytes_out = alg;
+  if (op_bytes_out) *op_bytes_out = bytes;
   if (n_ops_out) *n_ops_out = cnt;
   if (n_items_out) *n_items_out = (int64_t)q.items.size();
   if (ms_out) *ms_out = 0;
@@ -1229,8 +1249,8 @@ qtn_status qtn_autotune_bands(qtn_net* n, int32_t with_grad, void* ws, size_t ws
         if (ws_layout(n, with_grad != 0).total > ws_bytes) continue;
         if ((s = check_ready(n, ws, ws_bytes, with_grad != 0)) != QTN_OK) break;
         double bytes = 0, ms = 0;
-        s = qtn_time_wide_sweep(n, with_grad, lo_w[b], hi_w[b], 7, ws, ws_bytes, stream, reps, &bytes, &ms, nullptr,
-                                nullptr);
+        s = qtn_time_wide_sweep(n, with_grad, lo_w[b], hi_w[b], 7, ws, ws_bytes, stream, reps, &bytes, nullptr, &ms,
+                                nullptr, nullptr);
         if (s != QTN_OK) break;
         if (ms < best) {
           best = ms;

@@ -282,18 +282,21 @@ class QaoaNet:
         """In-sweep rate of the buckets of output rank in [min_width,
         max_width] (0: unbounded): their ops (kinds: bit 0 forward, bit 1
         single-input adjoints, bit 2 fused adjoints; 0 all) as one persistent
-        launch of their own (after a sweep)."""
+        launch of their own (after a sweep).  alg_bytes: the steps'
+        algorithmic bytes (as the sweep totals); op_bytes: the ops' operand
+        bytes (re-reads of separate adjoint passes included)."""
         ws = self._workspace(with_grad)
-        b, ms, n, it = C.c_double(), C.c_double(), C.c_int64(), C.c_int64()
+        b, ob, ms, n, it = C.c_double(), C.c_double(), C.c_double(), C.c_int64(), C.c_int64()
         L.check(self._lib.qtn_time_wide_sweep(self.handle, int(bool(with_grad)), int(min_width), int(max_width),
                                               int(kinds),
                                               C.c_void_p(ws.data_ptr()), ws.numel(), self._stream(), int(reps),
-                                              C.byref(b), C.byref(ms), C.byref(n), C.byref(it)))
-        return {"alg_bytes": b.value, "ms": ms.value, "ops": n.value, "items": it.value}
+                                              C.byref(b), C.byref(ob), C.byref(ms), C.byref(n), C.byref(it)))
+        return {"alg_bytes": b.value, "op_bytes": ob.value, "ms": ms.value, "ops": n.value, "items": it.value}
 
     def time_persistent(self, with_grad: bool = True, reps: int = 10) -> float:
-        """Average device ms of the persistent kernel alone (sweeps enqueued
-        without graph capture, HIP events around that kernel)."""
+        """Average device ms of the sweep's contraction kernels alone (the
+        LDS-resident cones' kernel and the persistent kernel; sweeps enqueued
+        without graph capture, HIP events around those kernels)."""
         ws = self._workspace(with_grad)
         ms = C.c_double()
         L.check(self._lib.qtn_time_persistent(self.handle, int(bool(with_grad)), C.c_void_p(ws.data_ptr()), ws.numel(),
