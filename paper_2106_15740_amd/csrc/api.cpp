@@ -961,11 +961,11 @@ qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width,
   const bool grad = with_grad != 0;
   // the ops of buckets with output rank >= min_width, in each cone's program
   // order, as a queue of their own
-  std::vector<char> in_prog(n->P.ops.size(), 0);
+  std::vector<char> in_prog(n->P.ops.size(), 0);  // 1: forward op, 2: adjoint-sweep op
   for (size_t c = 0; c < n->P.cones.size(); ++c) {
     for (int32_t o = n->P.cone_fwd_lo[c]; o < n->P.cone_fwd_hi[c]; ++o) in_prog[o] = 1;
     if (grad)
-      for (int32_t o = n->P.cone_adj_lo[c]; o < n->P.cone_adj_hi[c]; ++o) in_prog[o] = 1;
+      for (int32_t o = n->P.cone_adj_lo[c]; o < n->P.cone_adj_hi[c]; ++o) in_prog[o] = 2;
   }
   double bytes = 0;
   int64_t cnt = 0;
@@ -975,9 +975,9 @@ qtn_status qtn_time_wide_sweep(qtn_net* n, int32_t with_grad, int32_t min_width,
     const OpDesc& d = n->P.ops[o];
     if (!in_prog[o] || (d.kind != OP_CONTRACT && d.kind != OP_ADJOINT)) return false;
     if (d.nbits - 1 < min_width || d.nbits - 1 > max_width) return false;
-    // forward op: input 0 holds the eliminated index; adjoint op: input 0 is
-    // the output adjoint, which lacks it
-    const int kind = d.kind == OP_ADJOINT ? 4 : ((d.in_mask[0] & 1u) ? 1 : 2);
+    // forward contraction, one-input adjoint pass (or a recomputation in the
+    // adjoint sweep), fused adjoint
+    const int kind = d.kind == OP_ADJOINT ? 4 : (in_prog[o] == 1 ? 1 : 2);
     return (kinds & kind) != 0;
   };
   for (size_t o = 0; o < n->P.ops.size(); ++o) {

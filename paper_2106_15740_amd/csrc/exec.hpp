@@ -311,9 +311,11 @@ __device__ __forceinline__ void exec_contract(const OpDesc& d, typename CT<R>::E
 // ------------------------------------------------------------------ wide ops
 // Executor of the ops flagged F_WIDE (buckets too wide for one workgroup).
 // Everything that decides the instruction stream is a template parameter, so
-// the step body has no branches between its loads: NIN inputs, S0 = 1 when
-// input 0 lacks the eliminated index (the output adjoint of an adjoint op;
-// every other input holds it and is loaded as a 16-byte pair), UU = 2^nu
+// the step body has no branches between its loads: NIN inputs, of which the
+// first S0 (0, 1 or 2) lack the eliminated index and are loaded as single
+// elements (the output adjoint of an adjoint op; an input of a merged step
+// that a later bucket brought in), every other input holds it and is loaded
+// as a 16-byte pair, UU = 2^nu
 // outputs per thread.  All loads of a step are issued before the first use.
 // When the op has more per-thread output bits than UU covers (nu > log2 UU,
 // at most one more), the step repeats for the extra bit.  KS: the UU slots
@@ -458,7 +460,7 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
 #pragma unroll
           for (int i = 0; i < NIN; ++i) {
             const uint32_t o = koff[i] + us[i][k];
-            if (i == 0 && S0 == 1)
+            if (i < S0)
               a0[k][i] = inp[i][o];
             else
               load_pair(inp[i] + o, a0[k][i], a1[k][i]);
@@ -466,11 +468,11 @@ __device__ __forceinline__ void exec_wide(const OpDesc& d, typename CT<R>::E* __
 #pragma unroll
         for (int k = 0; k < UU; ++k) {
           E p0 = a0[k][0];
-          E p1 = S0 == 1 ? a0[k][0] : a1[k][0];
+          E p1 = S0 >= 1 ? a0[k][0] : a1[k][0];
 #pragma unroll
           for (int i = 1; i < NIN; ++i) {
             p0 = cmul(p0, a0[k][i]);
-            p1 = cmul(p1, a1[k][i]);
+            p1 = cmul(p1, i < S0 ? a0[k][i] : a1[k][i]);
           }
           acc0[k] = cadd(acc0[k], p0);
           acc1[k] = cadd(acc1[k], p1);
@@ -560,16 +562,21 @@ __device__ __forceinline__ void exec_wide_u(const OpDesc& d, typename CT<R>::E* 
 template <typename R>
 __device__ __forceinline__ void exec_wide_any(const OpDesc& d, typename CT<R>::E* arena, int64_t b0, int64_t b1,
                                               int64_t r, int64_t c, RedBuf<typename CT<R>::E>* red) {
-  const bool s0 = !(d.in_mask[0] & 1u);
-  switch (d.n_in * 2 + (s0 ? 1 : 0)) {
-    case 2: exec_wide_u<R, 1, 0>(d, arena, b0, b1, r, c, red); break;
-    case 3: exec_wide_u<R, 1, 1>(d, arena, b0, b1, r, c, red); break;
-    case 4: exec_wide_u<R, 2, 0>(d, arena, b0, b1, r, c, red); break;
-    case 5: exec_wide_u<R, 2, 1>(d, arena, b0, b1, r, c, red); break;
-    case 6: exec_wide_u<R, 3, 0>(d, arena, b0, b1, r, c, red); break;
-    case 7: exec_wide_u<R, 3, 1>(d, arena, b0, b1, r, c, red); break;
-    case 8: exec_wide_u<R, 4, 0>(d, arena, b0, b1, r, c, red); break;
-    default: exec_wide_u<R, 4, 1>(d, arena, b0, b1, r, c, red); break;
+  // leading inputs without the eliminated index (the planner puts them first)
+  const int ns = !(d.in_mask[0] & 1u) ? (d.n_in > 1 && !(d.in_mask[1] & 1u) ? 2 : 1) : 0;
+  switch (d.n_in * 3 + ns) {
+    case 3: exec_wide_u<R, 1, 0>(d, arena, b0, b1, r, c, red); break;
+    case 4: exec_wide_u<R, 1, 1>(d, arena, b0, b1, r, c, red); break;
+    case 6: exec_wide_u<R, 2, 0>(d, arena, b0, b1, r, c, red); break;
+    case 7: exec_wide_u<R, 2, 1>(d, arena, b0, b1, r, c, red); break;
+    case 8: exec_wide_u<R, 2, 2>(d, arena, b0, b1, r, c, red); break;
+    case 9: exec_wide_u<R, 3, 0>(d, arena, b0, b1, r, c, red); break;
+    case 10: exec_wide_u<R, 3, 1>(d, arena, b0, b1, r, c, red); break;
+    case 11: exec_wide_u<R, 3, 2>(d, arena, b0, b1, r, c, red); break;
+    case 12: exec_wide_u<R, 4, 0>(d, arena, b0, b1, r, c, red); break;
+    case 13: exec_wide_u<R, 4, 1>(d, arena, b0, b1, r, c, red); break;
+    case 14: exec_wide_u<R, 4, 2>(d, arena, b0, b1, r, c, red); break;
+    default: break;
   }
 }
 

@@ -120,7 +120,7 @@ hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, const Env& 
     return hipGetLastError();
   }
   if (h.flags & F_WIDE) {
-    const bool s0 = !(h.in_mask[0] & 1u);
+    const int ns = !(h.in_mask[0] & 1u) ? (h.n_in > 1 && !(h.in_mask[1] & 1u) ? 2 : 1) : 0;
     const int uu = 1 << h.nu;
     // no output bits per thread: the slots take the first loop bits (one or two)
     const int ks = h.nu == 0 ? std::min(h.nk, WideMaxU<R>::value == 4 ? 2 : 1) : 0;
@@ -138,15 +138,18 @@ hipError_t launch_op_t(const OpDesc* d_ops, const OpDesc& h, int op, const Env& 
     else                                              \
       QTN_WIDE(N, S, WideMaxU<R>::value, false);      \
   } while (0)
-    switch (h.n_in * 2 + (s0 ? 1 : 0)) {
-      case 2: QTN_WIDE_U(1, 0); break;
-      case 3: QTN_WIDE_U(1, 1); break;
-      case 4: QTN_WIDE_U(2, 0); break;
-      case 5: QTN_WIDE_U(2, 1); break;
-      case 6: QTN_WIDE_U(3, 0); break;
-      case 7: QTN_WIDE_U(3, 1); break;
-      case 8: QTN_WIDE_U(4, 0); break;
-      case 9: QTN_WIDE_U(4, 1); break;
+    switch (h.n_in * 3 + ns) {
+      case 3: QTN_WIDE_U(1, 0); break;
+      case 4: QTN_WIDE_U(1, 1); break;
+      case 6: QTN_WIDE_U(2, 0); break;
+      case 7: QTN_WIDE_U(2, 1); break;
+      case 8: QTN_WIDE_U(2, 2); break;
+      case 9: QTN_WIDE_U(3, 0); break;
+      case 10: QTN_WIDE_U(3, 1); break;
+      case 11: QTN_WIDE_U(3, 2); break;
+      case 12: QTN_WIDE_U(4, 0); break;
+      case 13: QTN_WIDE_U(4, 1); break;
+      case 14: QTN_WIDE_U(4, 2); break;
       default: return hipErrorInvalidValue;
     }
 #undef QTN_WIDE_U

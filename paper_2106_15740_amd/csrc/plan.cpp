@@ -502,8 +502,9 @@ static void buckets_one(Cone& C) {
 // the merged union stays within merge_bits bits and the merged step has at
 // most MAXIN inputs: for buckets this small every step costs about the same
 // fixed time, so fewer steps are faster.  At any size it joins a consumer that
-// only sums indices out of its output (no other input, no leaf of a new
-// index): the merged union is its own.  A merged step is the union of its
+// adds no index to its union (its output is then never written): a marginal
+// of its output always, one that adds inputs when the merged step suits the
+// wide executor.  A merged step is the union of its
 // members' tensors summed over all of their eliminated indices (the same
 // contraction, Section III.B, taken several indices at a time).
 static void group_buckets(Cone& C, int merge_bits, int merge_lam_bits) {
@@ -511,13 +512,16 @@ static void group_buckets(Cone& C, int merge_bits, int merge_lam_bits) {
   const int n = (int)Pl.size();
   std::vector<int> pos(C.n_idx);
   for (int s = 0; s < n; ++s) pos[C.order[s]] = s;
-  std::vector<int> root(n), gsize(n), gelim(n, 1), gnin(n), glam(n);
+  std::vector<int> root(n), gsize(n), gelim(n, 1), gnin(n), glam(n), gfirst(n);
   std::vector<std::vector<int>> gleafidx(n);  // indices carried by the group's leaves
+  std::vector<std::vector<int>> ginputs(n);   // producer groups (their roots) feeding the group
   for (int b = 0; b < n; ++b) {
     root[b] = b;
     gsize[b] = Pl[b].nbits();
     gnin[b] = (int)Pl[b].in_bkt.size();
     glam[b] = Pl[b].lam_mask ? 1 : 0;
+    gfirst[b] = Pl[b].v;
+    ginputs[b] = Pl[b].in_bkt;
     for (int li : Pl[b].leaves) {
       gleafidx[b].push_back(C.leaves[li].a);
       if (C.leaves[li].b >= 0) gleafidx[b].push_back(C.leaves[li].b);
@@ -533,23 +537,50 @@ static void group_buckets(Cone& C, int merge_bits, int merge_lam_bits) {
       const int size = gsize[t] + gelim[b];
       const int nin = gnin[t] - 1 + gnin[b];
       const int lam = glam[t] | glam[b];
-      // any size when the consumer carries no index beyond b's output and
-      // adds no input (a marginal of b's output: summing it in b's own step
-      // costs nothing and saves writing and re-reading that output)
-      const bool free_merge = size <= gsize[b] && nin + lam <= gnin[b] + glam[b];
-      if ((size > merge_bits && !free_merge) || nin + lam > MAXIN) continue;
+      if (nin + lam > MAXIN) continue;
       // the merged leaf-product table (built and differentiated per entry)
       // stays small
       std::vector<int> li;
       std::set_union(gleafidx[t].begin(), gleafidx[t].end(), gleafidx[b].begin(), gleafidx[b].end(),
                      std::back_inserter(li));
       if ((int)li.size() > merge_lam_bits) continue;
+      // At any size, when the consumer carries no index beyond b's output
+      // (the merged union is b's own), the merge saves writing b's output
+      // and reading it back (forward and adjoint):
+      //  * a marginal of b's output (no input added): always;
+      //  * with the consumer's other inputs (or leaf table) added: when the
+      //    merged step still suits the wide executor -- at most 4 inputs,
+      //    at most one of them without the step's first eliminated index
+      //    (its adjoint passes then have at most two such inputs, the output
+      //    adjoint being the other).
+      bool wide_ok = false;
+      if (size <= gsize[b]) {
+        if (nin + lam <= gnin[b] + glam[b]) {
+          wide_ok = true;
+        } else if (nin + lam <= 4) {
+          const int first = pos[gfirst[t]] < pos[gfirst[b]] ? gfirst[t] : gfirst[b];
+          auto holds = [&](const std::vector<int>& ix) { return std::find(ix.begin(), ix.end(), first) != ix.end(); };
+          int singles = 0;
+          for (int g : {b, t})
+            for (int x : ginputs[g])
+              if (x != b && !holds(std::vector<int>(Pl[x].uni.begin() + 1, Pl[x].uni.end()))) ++singles;
+          if (lam && !holds(li)) ++singles;
+          wide_ok = singles <= 1;
+        }
+      }
+      if (size > merge_bits && !wide_ok) continue;
       gleafidx[t] = li;
       root[b] = t;
       gsize[t] = size;
       gelim[t] += gelim[b];
       gnin[t] = nin;
       glam[t] = lam;
+      if (pos[gfirst[b]] < pos[gfirst[t]]) gfirst[t] = gfirst[b];
+      std::vector<int> ins;
+      for (int x : ginputs[t])
+        if (x != b) ins.push_back(x);
+      ins.insert(ins.end(), ginputs[b].begin(), ginputs[b].end());
+      ginputs[t] = ins;
     }
   std::vector<int> idx(n, -1);
   int ng = 0;
@@ -633,15 +664,25 @@ struct Ctx {
 // bit may become a block bit (no atomics).
 void partition_bits_as(OpDesc& d, int nbits, uint32_t out_mask, bool seq, bool wide, const TuneParams& T);
 
+// Inputs of a contraction op without the eliminated index (bit 0), if they
+// are its first 0, 1 or 2 inputs (the wide executor loads them as single
+// elements, the others as pairs); -1 otherwise.
+int wide_singles(const OpDesc& d) {
+  int k = 0;
+  while (k < d.n_in && !(d.in_mask[k] & 1u)) ++k;
+  for (int i = k; i < d.n_in; ++i)
+    if (!(d.in_mask[i] & 1u)) return -1;
+  return k <= 2 ? k : -1;
+}
+
 // Splits the union bits of a contraction op into lanes, per-thread outputs,
 // the summation loop and blocks.  Ops outside sequential programs with at
-// most 4 inputs, all but input 0 holding the eliminated index, go to the wide
-// executor when every block range they are given (a tile of tile_blocks
-// blocks, or all blocks) holds at least one block per sub-block.
+// most 4 inputs, of which at most the first two lack the eliminated index, go
+// to the wide executor when every block range they are given (a tile of
+// tile_blocks blocks, or all blocks) holds at least one block per sub-block.
 void partition_bits(OpDesc& d, int nbits, uint32_t out_mask, bool seq, const TuneParams& T0) {
   const TuneParams T = T0.for_bits(nbits);
-  bool wide = !seq && d.n_in <= 4;
-  for (int i = 1; i < d.n_in; ++i) wide = wide && (d.in_mask[i] & 1u) != 0;
+  bool wide = !seq && d.n_in <= 4 && wide_singles(d) >= 0;
   if (wide) {
     partition_bits_as(d, nbits, out_mask, seq, true, T);
     const int64_t nsub = std::max(1, T.threads >> d.nl);
@@ -1162,6 +1203,24 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
     ref_n[b] = d.aux1;
     G.leaf.push_back(d);
   }
+  // inputs [from, n_in) without the eliminated index (bit 0) first, the
+  // order the wide executor takes them in (single elements, then pairs)
+  auto singles_first = [](OpDesc& d, int from) {
+    int64_t off[MAXIN];
+    uint32_t msk[MAXIN];
+    int k = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = from; i < d.n_in; ++i)
+        if (bool(d.in_mask[i] & 1u) == bool(pass)) {
+          off[k] = d.in_off[i];
+          msk[k] = d.in_mask[i];
+          ++k;
+        }
+    for (int i = from; i < d.n_in; ++i) {
+      d.in_off[i] = off[i - from];
+      d.in_mask[i] = msk[i - from];
+    }
+  };
   // forward contraction of bucket b, writing `out` (its output or a
   // recomputation, which reads the recomputed values of inputs that were
   // dropped too)
@@ -1186,6 +1245,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       ++ni;
     }
     d.n_in = ni;
+    singles_first(d, 0);
     d.out_mask = ((nbits >= 32 ? 0u : (1u << nbits)) - 1u) & ~Bk.elim_mask();
     d.out_off = out;
     partition_bits(d, nbits, d.out_mask, nbits <= T.seq_max_bits, T);
@@ -1301,6 +1361,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       d.nbits = nbits;
       add_common(d, t, true);
       if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
+      singles_first(d, 1);
       d.out_mask = Bk.in_mask[t];
       d.out_off = buf_code(BK_ADJ, Bk.in_bkt[t]);
       partition_bits(d, nbits, d.out_mask, seq, T);
@@ -1312,6 +1373,7 @@ std::string emit_cone(Plan& P, size_t c, ConeProg& G) {
       d.nbits = nbits;
       add_common(d, -1, false);
       if (d.n_in > MAXIN) return "adjoint op with more than 8 inputs";
+      singles_first(d, 1);
       d.out_mask = Bk.lam_mask;
       d.out_off = buf_code(BK_LAMADJ, (int)bb);
       partition_bits(d, nbits, d.out_mask, seq, T);
@@ -2074,8 +2136,7 @@ std::string validate_plan(const Plan& P) {
     if (d.flags & F_WIDE) {
       if (d.nu > (P.tune.elem_bytes == 8 ? 2 : 1)) return "op " + S(o) + "too many unroll bits";
       if (d.n_in > 4) return "op " + S(o) + "wide op with more than 4 inputs";
-      for (int i = 1; i < d.n_in; ++i)
-        if (!(d.in_mask[i] & 1u)) return "op " + S(o) + "wide op input without the eliminated index";
+      if (wide_singles(d) < 0) return "op " + S(o) + "wide op with inputs without the eliminated index after a pair";
       const int64_t nsub = std::max(1, P.tune.threads >> d.nl);
       if (std::min<int64_t>(std::max(1, P.tune.for_bits(d.nbits).tile_blocks), int64_t(1) << d.nb) < nsub)
         return "op " + S(o) + "wide op block range smaller than a workgroup step";

@@ -29,8 +29,13 @@ def arch(device: int) -> str:
     return name.split(":")[0]
 
 
+# the planner's step structure (merging rules); entries of another version
+# were tuned for different programs
+PLAN_VERSION = 2
+
+
 def key(net) -> str:
-    return f"{arch(net.device)}|{net.dtype}|{net.signature()}"
+    return f"{arch(net.device)}|{net.dtype}|{net.signature()}|plan{PLAN_VERSION}"
 
 
 def load(path: Optional[str] = None) -> dict:
