@@ -235,12 +235,17 @@ def _oracle_edge_grad(n, edges, gamma, beta, edge, h, dtype="c128"):
     return z
 
 
-def time_sweeps(net, steps: int, warmup: int, mode: str = "batched"):
+def time_sweeps(net, steps: int, warmup: int, mode: str = "batched", settle_s: float = 0.0):
     """Wall time of `steps` energy + gradient sweeps bracketed by device
     synchronisation, the last energy, and the average device time of the graph
-    replay (HIP events on the launch stream)."""
+    replay (HIP events on the launch stream).  Before the `warmup` sweeps,
+    sweeps run for settle_s seconds: a GPU that was idle runs short kernels
+    about 1.5x slower for the first few hundred milliseconds of work."""
     import torch
 
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < settle_s:
+        net.energy_grad(mode)
     for _ in range(warmup):
         net.energy_grad(mode)
     net.kernel_time(reset=True)
@@ -450,8 +455,10 @@ def profile_leg(which: str, repeats: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--settle", type=float, default=1.0,
+                    help="seconds of untimed sweeps before the warm-up steps (the GPU's clocks ramp up)")
     ap.add_argument("--workload", default="p3_n244")
     ap.add_argument("--repeats", type=int, default=10,
                     help="randomized greedy order: runs per cone on top of the deterministic one (0: deterministic)")
@@ -517,7 +524,7 @@ def main():
     info = net.info()
 
     log(f"{args.workload}: timing {args.steps} steps")
-    dt, e, k_avg_ms, k_cnt = time_sweeps(net, args.steps, args.warmup)
+    dt, e, k_avg_ms, k_cnt = time_sweeps(net, args.steps, args.warmup, settle_s=args.settle)
     log(f"{args.workload}: {1e3 * dt / args.steps:.3f} ms per step")
     ms_step = 1e3 * dt / args.steps
     cones_per_s = len(w.edges) * args.steps / dt
@@ -533,7 +540,7 @@ def main():
         net2.set_params(w.gamma, w.beta)
         net2.set_tuning(**{k: v for k, v in tuned.items()})
         i2 = net2.info()
-        dt2, _, k2, _ = time_sweeps(net2, args.steps, args.warmup)
+        dt2, _, k2, _ = time_sweeps(net2, args.steps, args.warmup, settle_s=min(args.settle, 0.3))
         other = {"order": o2, "max_width": i2["max_width"], "edge_light_cones_per_s": len(w.edges) * args.steps / dt2,
                  "ms_per_step": 1e3 * dt2 / args.steps,
                  "alg_GBps": (i2["fwd_bytes"] + i2["bwd_bytes"]) / (k2 * 1e-3) / 1e9}
