@@ -1362,13 +1362,15 @@ __device__ __forceinline__ uint32_t nib(uint64_t v, int j) { return (uint32_t)(v
 // ls dimensions (the output element and, when the output has fewer than 64
 // elements, the lowest summed dimensions, which are then reduced across the
 // wavefront); lane bits are the first min(nv, 6) dimensions, the rest of v is
-// a per-lane loop.  Each lane walks the summed dimensions nv.. in Gray-code
-// order, two at a time (both values of the first), so its loads are
-// independent.  Offsets move by XOR: every dimension an input holds is one
-// bit of its element index.
+// a per-lane loop (in Gray-code order).  Each lane walks the summed dimensions
+// nv.. in Gray-code order, two at a time (both values of the first), so its
+// loads are independent.  Offsets move by XOR: every dimension an input holds
+// is one bit of its element index.  An op shared by nparts wavefronts: this
+// one takes part `part` of the outer loop (contiguous chunks).
 template <typename R, int NIN>
 __device__ __forceinline__ void small_contract(const SmallOp& d, typename CT<R>::E* __restrict__ lds,
-                                               typename CT<R>::E* __restrict__ arena, int lane) {
+                                               typename CT<R>::E* __restrict__ arena, int lane, int part = 0,
+                                               int nparts = 1) {
   using E = typename CT<R>::E;
   const int nb = d.nbits, no = d.n_out, ns = nb - no;
   const int ls = min(ns, max(0, 6 - no));
@@ -1391,9 +1393,19 @@ __device__ __forceinline__ void small_contract(const SmallOp& d, typename CT<R>:
   }
   const bool active = lane < (1 << nl);
   const int nouter = 1 << (nv - nl);
-  uint32_t g = 0;  // Gray code of the outer loop (dimensions 6 .. nv - 1)
-  for (int h = 0; h < nouter; ++h) {
-    if (h) {
+  const int chunk = (nouter + nparts - 1) / nparts;
+  const int h0 = min(nouter, part * chunk), h1 = min(nouter, h0 + chunk);
+  uint32_t g = (uint32_t)(h0 ^ (h0 >> 1));  // Gray code of the outer loop (dimensions 6 .. nv - 1)
+  for (int t = 0; t < nv - nl; ++t)
+    if ((g >> t) & 1u) {
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) {
+        const uint32_t s = nib(d.shift[i], 6 + t);
+        off[i] ^= s == 0xfu ? 0u : (1u << s);
+      }
+    }
+  for (int h = h0; h < h1; ++h) {
+    if (h > h0) {
       const int t = __ffs(h) - 1;
       g ^= 1u << t;
 #pragma unroll
@@ -1458,16 +1470,16 @@ __device__ __forceinline__ void small_contract(const SmallOp& d, typename CT<R>:
 
 template <typename R>
 __device__ __forceinline__ void small_contract_any(const SmallOp& d, typename CT<R>::E* lds,
-                                                   typename CT<R>::E* arena, int lane) {
+                                                   typename CT<R>::E* arena, int lane, int part, int nparts) {
   switch (d.n_in) {
-    case 1: small_contract<R, 1>(d, lds, arena, lane); break;
-    case 2: small_contract<R, 2>(d, lds, arena, lane); break;
-    case 3: small_contract<R, 3>(d, lds, arena, lane); break;
-    case 4: small_contract<R, 4>(d, lds, arena, lane); break;
-    case 5: small_contract<R, 5>(d, lds, arena, lane); break;
-    case 6: small_contract<R, 6>(d, lds, arena, lane); break;
-    case 7: small_contract<R, 7>(d, lds, arena, lane); break;
-    default: small_contract<R, 8>(d, lds, arena, lane); break;
+    case 1: small_contract<R, 1>(d, lds, arena, lane, part, nparts); break;
+    case 2: small_contract<R, 2>(d, lds, arena, lane, part, nparts); break;
+    case 3: small_contract<R, 3>(d, lds, arena, lane, part, nparts); break;
+    case 4: small_contract<R, 4>(d, lds, arena, lane, part, nparts); break;
+    case 5: small_contract<R, 5>(d, lds, arena, lane, part, nparts); break;
+    case 6: small_contract<R, 6>(d, lds, arena, lane, part, nparts); break;
+    case 7: small_contract<R, 7>(d, lds, arena, lane, part, nparts); break;
+    default: small_contract<R, 8>(d, lds, arena, lane, part, nparts); break;
   }
 }
 
@@ -1690,7 +1702,8 @@ __device__ __forceinline__ void run_small(const SmallOp* small, int lo, int hi, 
       const uint32_t w0 = __builtin_amdgcn_readfirstlane(src[0]), w1 = __builtin_amdgcn_readfirstlane(src[1]);
       const uint32_t kind = w0 & 0xffu, flags = w1 & 0xffu, owner = (w1 >> 8) & 0xffu;
       if (j > 0 && (flags & SF_SYNC)) __syncthreads();
-      if (kind != S_COPYIN && (int)(owner % nw) != wave) continue;
+      const bool split = flags & SF_SPLIT;
+      if (kind != S_COPYIN && !split && (int)(owner % nw) != wave) continue;
       // every field into a scalar register: uniform control flow, no private copy
       SmallOp d;
       {
@@ -1704,7 +1717,7 @@ __device__ __forceinline__ void run_small(const SmallOp* small, int lo, int hi, 
         continue;
       }
       if (d.kind == S_CONTRACT)
-        small_contract_any<R>(d, lds, reinterpret_cast<E*>(env.arena), lane);
+        small_contract_any<R>(d, lds, reinterpret_cast<E*>(env.arena), lane, split ? wave : 0, split ? nw : 1);
       else if (d.kind == S_RESULT)
         small_result<R>(d, lds, env, lane);
     }

@@ -90,6 +90,7 @@ enum SmallKind : uint8_t {
 };
 enum SmallFlags : uint8_t {
   SF_SYNC = 1,  // barrier before the op (it reads or overwrites data of an op since the last barrier)
+  SF_SPLIT = 8,  // S_CONTRACT shared by every wavefront of the workgroup (each takes a chunk of its outputs)
   SF_GOUT = 2,  // the output goes to global memory at element offset gout (not LDS)
   SF_GRAD = 4,  // S_RESULT also writes the adjoint seeds and zeroes the gradient accumulators
 };

@@ -1670,7 +1670,28 @@ static void small_programs(Plan& P, const std::vector<ConeProg>& progs) {
           return o.kind == S_CONTRACT ? std::ldexp(1.0, o.nbits) * o.n_in + 256.0 : 64.0;
         };
         std::stable_sort(by_size.begin(), by_size.end(), [&](size_t a, size_t b) { return cost(a) > cost(b); });
-        for (size_t k : by_size) {
+        // the stage's largest op is shared by every wavefront when it costs
+        // more than the others together and its outer output walk has at
+        // least two steps (more than 64 output elements)
+        size_t first = 0;
+        if (nwaves > 1 && !by_size.empty()) {
+          SmallOp& o = P.small[by_size[0]];
+          double rest = 0;
+          for (size_t i = 1; i < by_size.size(); ++i) rest += cost(by_size[i]);
+          if (o.kind == S_CONTRACT && o.n_out >= 7 && cost(by_size[0]) > rest) {
+            o.flags |= SF_SPLIT;
+            o.wave = 0;
+            // the executor's split: contiguous chunks of the 2^(n_out-6) outer steps
+            const int nouter = 1 << (o.n_out - 6), chunk = (nouter + nwaves - 1) / nwaves;
+            for (int w = 0; w < nwaves; ++w) {
+              const int h0 = std::min(nouter, w * chunk), h1 = std::min(nouter, h0 + chunk);
+              load[w] += cost(by_size[0]) * (h1 - h0) / nouter;
+            }
+            first = 1;
+          }
+        }
+        for (size_t i = first; i < by_size.size(); ++i) {
+          const size_t k = by_size[i];
           const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
           P.small[k].wave = (uint8_t)w;
           load[w] += cost(k);
@@ -2186,6 +2207,7 @@ std::string validate_plan(const Plan& P) {
         const SmallOp& d = P.small[k];
         auto in_window = [&](int64_t off, int64_t n) { return off >= 0 && off + n <= P.lds_elems; };
         if (d.cone != (int32_t)c) return "LDS op " + S(k) + "of another cone";
+        if ((d.flags & SF_SPLIT) && (d.kind != S_CONTRACT || d.n_out < 7)) return "LDS op " + S(k) + "split op shape";
         if (d.kind == S_CONTRACT) {
           if (d.nbits > 15 || d.n_out > d.nbits || d.n_in < 1 || d.n_in > 8) return "LDS op " + S(k) + "shape";
           if (d.flags & SF_GOUT) {
