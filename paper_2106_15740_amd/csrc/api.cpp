@@ -234,7 +234,7 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
   HIPCHECK(launch_small_copy(n->dh_leafvals, n->d_leafvals, n->leaf_bytes, st,
                              batched && !leaf_launch ? ctl : nullptr, pg.init, pg.n_nodes));
   if (leaf_launch)
-    HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.leaf_lo, leaf_hi, env, st, batched ? ctl : nullptr, pg.init,
+    HIPCHECK(launch_batch(n->c128, false, 64, n->d_ops, n->P.leaf_lo, leaf_hi, env, st, batched ? ctl : nullptr, pg.init,
                           pg.n_nodes));
   if (mode == QTN_PLAIN) {
     for (size_t c = 0; c < n->P.cones.size(); ++c) {
@@ -265,8 +265,10 @@ qtn_status enqueue_sweep(qtn_net* n, int mode, bool grad, void* ws, hipStream_t 
                                  T.threads, grid, lds_bytes, kSpinLimit, st));
     if (pk1) HIPCHECK(hipEventRecord(pk1, st));
   }
-  if (grad && lgrad_hi > n->P.lgrad_lo)
-    HIPCHECK(launch_batch(n->c128, n->d_ops, n->P.lgrad_lo, lgrad_hi, env, st));
+  if (grad && n->P.lgrad_mid > n->P.lgrad_lo)
+    HIPCHECK(launch_batch(n->c128, true, 8, n->d_ops, n->P.lgrad_lo, n->P.lgrad_mid, env, st));
+  if (grad && lgrad_hi > n->P.lgrad_mid)
+    HIPCHECK(launch_batch(n->c128, true, 64, n->d_ops, n->P.lgrad_mid, lgrad_hi, env, st));
   // E, dE/dtheta straight into the mapped host buffer, followed (at the
   // workspace's ctl offset) by the queue head and the persistent kernel's
   // error flag

@@ -1483,6 +1483,22 @@ __device__ __forceinline__ void small_contract_any(const SmallOp& d, typename CT
   }
 }
 
+// A table's leaf references (L <= LM <= 64) into uniform registers: lane q
+// loads reference q (one load for all of them), readlane hands each to the
+// wavefront; references beyond L read as zero.
+template <int LM>
+__device__ __forceinline__ void load_refs(const LeafRef* refs, int L, int lane, LeafRef (&lr)[LM]) {
+  const uint32_t mine = lane < L ? reinterpret_cast<const uint32_t*>(refs)[lane] : 0u;
+#pragma unroll
+  for (int q = 0; q < LM; ++q) {
+    const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)mine, q);
+    lr[q].kind = (int16_t)(r & 0xffffu);
+    lr[q].pa = (int8_t)((r >> 16) & 0xffu);
+    lr[q].pb = (int8_t)(r >> 24);
+  }
+}
+static_assert(sizeof(LeafRef) == 4, "a leaf reference is one 32-bit word");
+
 // Leaf-product table on one wavefront (lane 0..63): entry e of out = product
 // over the table's L leaves of leaf[e restricted to the leaf's two indices].
 // LM >= L: the body is branch-free (missing leaves multiply by one), so every
@@ -1492,8 +1508,7 @@ __device__ __forceinline__ void leaf_table_wave_m(typename CT<R>::E* out, int n,
                                                   const typename CT<R>::E* vals, int lane) {
   using E = typename CT<R>::E;
   LeafRef lr[LM];
-#pragma unroll
-  for (int q = 0; q < LM; ++q) lr[q] = q < L ? refs[q] : LeafRef{0, 0, 0};
+  load_refs<LM>(refs, L, lane, lr);
   for (int e = lane; e < n; e += 64) {
     E v[LM];
 #pragma unroll
@@ -1545,12 +1560,10 @@ __device__ __forceinline__ void leafgrad_wave_m(const typename CT<R>::E* lbar, i
                                                 double* res, int p, int lane) {
   using E = typename CT<R>::E;
   LeafRef lr[LM];
+  load_refs<LM>(refs, L, lane, lr);
   int slot[LM];
 #pragma unroll
-  for (int q = 0; q < LM; ++q) {
-    lr[q] = q < L ? refs[q] : LeafRef{0, 0, 0};
-    slot[q] = q < L ? theta_slot(lr[q].kind, p) : -1;
-  }
+  for (int q = 0; q < LM; ++q) slot[q] = q < L ? theta_slot(lr[q].kind, p) : -1;
   double sxd[LM], syd[LM];
 #pragma unroll
   for (int q = 0; q < LM; ++q) sxd[q] = syd[q] = 0.0;
@@ -1599,14 +1612,16 @@ __device__ __forceinline__ void leafgrad_wave_m(const typename CT<R>::E* lbar, i
   }
 }
 
-template <typename R>
+// (LMAX: the caller's bound on L; a smaller bound leaves the larger variants
+// out of the kernel, and with them their register footprint)
+template <typename R, int LMAX = 64>
 __device__ __forceinline__ void leafgrad_wave(const typename CT<R>::E* lbar, int n, const LeafRef* refs, int L,
                                               const typename CT<R>::E* vals, const typename CT<R>::E* dvals,
                                               double* res, int p, int lane) {
   using E = typename CT<R>::E;
   if (L <= 4) {
     leafgrad_wave_m<R, 4>(lbar, n, refs, L, vals, dvals, res, p, lane);
-  } else if (L <= 8) {
+  } else if (LMAX <= 8 || L <= 8) {
     leafgrad_wave_m<R, 8>(lbar, n, refs, L, vals, dvals, res, p, lane);
   } else if (L <= 16) {
     leafgrad_wave_m<R, 16>(lbar, n, refs, L, vals, dvals, res, p, lane);

@@ -14,10 +14,13 @@
 
 namespace qtn {
 
-// Leaf-product tables (OP_LEAF) and leaf gradients (OP_LEAFGRAD) of every
-// cone, one wavefront per op: the tables have a few to a few hundred entries,
-// so a whole workgroup per op would idle.
-template <typename R>
+// Leaf-product tables (OP_LEAF, GRAD false) or leaf gradients (OP_LEAFGRAD,
+// GRAD true, tables of at most LMAX leaves) of every cone, one wavefront per
+// op: the tables have a few to a few hundred entries, so a whole workgroup per
+// op would idle.  Separate kernels, so the tables and the gradients of tables
+// with few leaves keep the small register footprint (and the occupancy) of
+// their simpler bodies.
+template <typename R, bool GRAD, int LMAX>
 __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restrict__ ops, int lo, int hi, Env env,
                                                          int32_t* ctl, const int32_t* __restrict__ ctl_init,
                                                          int n_nodes) {
@@ -33,24 +36,22 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
   // the leaf values and their derivatives (4 entries per kind, 3 + 4p kinds,
   // p <= 16) are looked up once per leaf and table entry: keep them in LDS
   constexpr int NV = 4 * (3 + 4 * 16);
-  __shared__ E s_vals[NV], s_dvals[NV];
+  __shared__ E s_vals[NV], s_dvals[GRAD ? NV : 1];
   const int nv = 4 * (3 + 4 * env.p);
   for (int i = threadIdx.x; i < nv && i < NV; i += blockDim.x) {
     s_vals[i] = reinterpret_cast<const E*>(env.leafvals)[i];
-    s_dvals[i] = reinterpret_cast<const E*>(env.dleafvals)[i];
+    if (GRAD) s_dvals[i] = reinterpret_cast<const E*>(env.dleafvals)[i];
   }
   __syncthreads();
-  const E* vals = s_vals;
-  const E* dvals = s_dvals;
   E* arena = reinterpret_cast<E*>(env.arena);
   for (int op = lo + wave; op < hi; op += nwaves) {
     const OpDesc& d = ops[op];
     const int64_t n = int64_t(1) << d.nbits;
     const LeafRef* refs = env.leafrefs + d.aux0;
-    if (d.kind == OP_LEAF)
-      leaf_table_wave<R>(arena + d.out_off, (int)n, refs, d.aux1, vals, lane);
-    else if (d.kind == OP_LEAFGRAD)
-      leafgrad_wave<R>(arena + d.in_off[0], (int)n, refs, d.aux1, vals, dvals,
+    if (!GRAD)
+      leaf_table_wave<R>(arena + d.out_off, (int)n, refs, d.aux1, s_vals, lane);
+    else
+      leafgrad_wave<R, LMAX>(arena + d.in_off[0], (int)n, refs, d.aux1, s_vals, s_dvals,
                        env.res + (int64_t)d.cone * env.res_stride, env.p, lane);
   }
 }
@@ -176,17 +177,30 @@ hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, co
               : launch_op_t<float>(d_ops, h, op, env, threads, max_grid, st);
 }
 
-hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, hipStream_t st, int32_t* ctl,
-                        const int32_t* ctl_init, int n_nodes) {
+hipError_t launch_batch(bool c128, bool grad, int lmax, const OpDesc* d_ops, int lo, int hi, const Env& env,
+                        hipStream_t st, int32_t* ctl, const int32_t* ctl_init, int n_nodes) {
   if (hi <= lo && !ctl) return hipSuccess;
   // 4 wavefronts per workgroup, one op each
   const int grid = std::max(1, std::min(std::max(hi - lo, 0) / 4 + 1, 4096));
-  if (c128)
-    hipLaunchKernelGGL(leaf_batch_kernel<double>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env, ctl, ctl_init,
-                       n_nodes);
-  else
-    hipLaunchKernelGGL(leaf_batch_kernel<float>, dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env, ctl, ctl_init,
-                       n_nodes);
+#define QTN_LEAF(R, G, LM) \
+  hipLaunchKernelGGL((leaf_batch_kernel<R, G, LM>), dim3(grid), dim3(256), 0, st, d_ops, lo, hi, env, ctl, ctl_init, \
+                     n_nodes)
+  if (c128) {
+    if (!grad)
+      QTN_LEAF(double, false, 64);
+    else if (lmax <= 8)
+      QTN_LEAF(double, true, 8);
+    else
+      QTN_LEAF(double, true, 64);
+  } else {
+    if (!grad)
+      QTN_LEAF(float, false, 64);
+    else if (lmax <= 8)
+      QTN_LEAF(float, true, 8);
+    else
+      QTN_LEAF(float, true, 64);
+  }
+#undef QTN_LEAF
   return hipGetLastError();
 }
 

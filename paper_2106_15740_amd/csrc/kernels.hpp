@@ -20,11 +20,12 @@ struct Env {
 
 hipError_t launch_op(bool c128, const OpDesc* d_ops, const OpDesc& h, int op, const Env& env, int threads,
                      int max_grid, hipStream_t st);
-// ops [lo, hi) (OP_LEAF or OP_LEAFGRAD), one wavefront each; with ctl, the
-// same launch resets the persistent sweep's queue head, error flag and node
-// counters (n_nodes of them, from ctl_init)
-hipError_t launch_batch(bool c128, const OpDesc* d_ops, int lo, int hi, const Env& env, hipStream_t st,
-                        int32_t* ctl = nullptr, const int32_t* ctl_init = nullptr, int n_nodes = 0);
+// ops [lo, hi) (all OP_LEAF, or with grad all OP_LEAFGRAD of tables with at
+// most lmax leaves), one wavefront each; with ctl, the same launch resets the
+// persistent sweep's queue head, error flag and node counters (n_nodes of
+// them, from ctl_init)
+hipError_t launch_batch(bool c128, bool grad, int lmax, const OpDesc* d_ops, int lo, int hi, const Env& env,
+                        hipStream_t st, int32_t* ctl = nullptr, const int32_t* ctl_init = nullptr, int n_nodes = 0);
 // bytes (a multiple of 4, <= 1 MiB) from src to dst with one workgroup;
 // either side may be mapped pinned host memory.  With ctl, the same launch
 // resets the persistent sweep's queue head, error flag and node counters.

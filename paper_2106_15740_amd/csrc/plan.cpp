@@ -1817,8 +1817,14 @@ std::string build_programs(Plan& P, int elem_bytes) {
   P.ops.insert(P.ops.end(), leaf_ops.begin(), leaf_ops.end());
   P.leaf_hi = (int32_t)P.ops.size();
   P.lgrad_lo = P.leaf_hi;
+  // leaf gradients of tables with at most 8 leaves first: they run in a
+  // kernel of their own whose smaller register footprint fits more
+  // wavefronts per SIMD
+  std::stable_partition(lgrad_ops.begin(), lgrad_ops.end(), [](const OpDesc& d) { return d.aux1 <= 8; });
   P.ops.insert(P.ops.end(), lgrad_ops.begin(), lgrad_ops.end());
   P.lgrad_hi = (int32_t)P.ops.size();
+  P.lgrad_mid = P.lgrad_lo;
+  while (P.lgrad_mid < P.lgrad_hi && P.ops[P.lgrad_mid].aux1 <= 8) ++P.lgrad_mid;
   // pinned parts side by side, then the dynamic area
   int64_t off = 0;
   for (size_t c = 0; c < nc; ++c) {

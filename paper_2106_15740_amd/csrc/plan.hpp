@@ -144,6 +144,7 @@ struct Plan {
   std::vector<LeafRef> leafrefs;
   int32_t leaf_lo = 0, leaf_hi = 0;    // all OP_LEAF ops (run before the sweep)
   int32_t lgrad_lo = 0, lgrad_hi = 0;  // all OP_LEAFGRAD ops (run after the adjoint sweep)
+  int32_t lgrad_mid = 0;               // [lgrad_lo, lgrad_mid): tables of at most 8 leaves, then the others
   std::vector<char> cone_lds;          // cone runs LDS-resident in the persistent sweep (as a SmallOp program)
   std::vector<SmallOp> small;          // LDS-resident programs of those cones
   std::vector<int32_t> small_fwd_lo, small_fwd_hi;    // per cone: forward-only program in `small`

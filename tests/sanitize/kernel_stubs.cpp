@@ -9,7 +9,7 @@ namespace qtn {
 hipError_t launch_op(bool, const OpDesc*, const OpDesc&, int, const Env&, int, int, hipStream_t) {
   return hipErrorNotSupported;
 }
-hipError_t launch_batch(bool, const OpDesc*, int, int, const Env&, hipStream_t, int32_t*, const int32_t*, int) {
+hipError_t launch_batch(bool, bool, int, const OpDesc*, int, int, const Env&, hipStream_t, int32_t*, const int32_t*, int) {
   return hipErrorNotSupported;
 }
 hipError_t launch_small_copy(const void*, void*, size_t, hipStream_t, int32_t*, const int32_t*, int) {
