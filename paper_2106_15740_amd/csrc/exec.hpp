@@ -1689,53 +1689,66 @@ __device__ __forceinline__ void small_result(const SmallOp& d, typename CT<R>::E
   }
 }
 
-// One cone's LDS-resident program small[lo, hi) on the whole workgroup.  The
-// ops come through `sprog` in chunks of SMALL_CHUNK (one bulk load per
-// chunk, every thread a 16-byte word, instead of a dependent load per op) and
-// are read from there into scalar registers.  The leaf-block copy runs on all
+// One cone's LDS-resident program small[lo, hi) on the whole workgroup.  Each
+// wavefront reads the ops itself, one op (32 words) per load, lane q holding
+// word q: the next op's load is issued before the current op runs, so it
+// arrives during it, and no wavefront waits for another to fetch the
+// program.  Fields go to scalar registers by readlane, only those the op's
+// kind needs (a contraction: the header, its inputs' dimension maps, the
+// global output offset when it has one).  The leaf-block copy runs on all
 // threads; every other op on its wavefront (ops between two barriers are
-// independent, so the wavefronts run them side by side).
-constexpr int SMALL_CHUNK = 16;
-
+// independent, so the wavefronts run them side by side).  The workgroup has a
+// power-of-two number of wavefronts (1, 2 or 4).
 template <typename R>
-__device__ __forceinline__ void run_small(const SmallOp* small, int lo, int hi, typename CT<R>::E* lds, SmallOp* sprog,
+__device__ __forceinline__ void run_small(const SmallOp* small, int lo, int hi, typename CT<R>::E* lds,
                                           const Env& env) {
   using E = typename CT<R>::E;
+  constexpr int NW = (int)(sizeof(SmallOp) / 4);  // 32 words per op
+  static_assert(NW == 32, "an op is read by half a wavefront");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
-  for (int k0 = lo; k0 < hi; k0 += SMALL_CHUNK) {
-    const int nk = min(SMALL_CHUNK, hi - k0);
-    constexpr int W = sizeof(SmallOp) / sizeof(uint4);
-    __syncthreads();  // the previous chunk's ops are done with sprog
-    for (int t = threadIdx.x; t < nk * W; t += blockDim.x)
-      reinterpret_cast<uint4*>(sprog)[t] = reinterpret_cast<const uint4*>(small + k0)[t];
-    __syncthreads();
-    for (int j = 0; j < nk; ++j) {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(sprog + j);
-      // kind, flags and wavefront first: the other wavefronts skip the op here
-      const uint32_t w0 = __builtin_amdgcn_readfirstlane(src[0]), w1 = __builtin_amdgcn_readfirstlane(src[1]);
-      const uint32_t kind = w0 & 0xffu, flags = w1 & 0xffu, owner = (w1 >> 8) & 0xffu;
-      if (j > 0 && (flags & SF_SYNC)) __syncthreads();
-      const bool split = flags & SF_SPLIT;
-      if (kind != S_COPYIN && !split && (int)(owner % nw) != wave) continue;
-      // every field into a scalar register: uniform control flow, no private copy
-      SmallOp d;
-      {
-        uint32_t* dw = reinterpret_cast<uint32_t*>(&d);
+  const uint32_t* words = reinterpret_cast<const uint32_t*>(small);
+  uint32_t cur = words[(size_t)lo * NW + (lane & (NW - 1))];
+  for (int k = lo; k < hi; ++k) {
+    const uint32_t nxt = k + 1 < hi ? words[(size_t)(k + 1) * NW + (lane & (NW - 1))] : 0u;
+    auto W = [&](int q) { return (uint32_t)__builtin_amdgcn_readlane((int)cur, q); };
+    // kind, flags and wavefront first: the other wavefronts skip the op here
+    const uint32_t w0 = W(0), w1 = W(1);
+    const uint32_t kind = w0 & 0xffu, flags = w1 & 0xffu, owner = (w1 >> 8) & 0xffu;
+    if (k > lo && (flags & SF_SYNC)) __syncthreads();
+    const bool split = flags & SF_SPLIT;
+    if (kind != S_COPYIN && !split && (int)(owner & (uint32_t)(nw - 1)) != wave) {
+      cur = nxt;
+      continue;
+    }
+    SmallOp d;
+    uint32_t* dw = reinterpret_cast<uint32_t*>(&d);
+    dw[0] = w0;
+    dw[1] = w1;
 #pragma unroll
-        for (int q = 0; q < (int)(sizeof(SmallOp) / 4); ++q) dw[q] = __builtin_amdgcn_readfirstlane(src[q]);
+    for (int q = 2; q < 8; ++q) dw[q] = W(q);
+    if (kind == S_CONTRACT) {
+      const int nin = (int)((w0 >> 8) & 0xffu);
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q < 2 * nin) dw[8 + q] = W(8 + q);
+      if (flags & SF_GOUT) {
+        dw[24] = W(24);
+        dw[25] = W(25);
       }
-      if (d.kind == S_COPYIN) {
+      small_contract_any<R>(d, lds, reinterpret_cast<E*>(env.arena), lane, split ? wave : 0, split ? nw : 1);
+    } else {
+#pragma unroll
+      for (int q = 8; q < NW; ++q) dw[q] = W(q);
+      if (kind == S_COPYIN) {
         const E* src = reinterpret_cast<const E*>(env.arena) + d.gout;
         for (int t = threadIdx.x; t < d.aux1; t += blockDim.x) lds[t] = src[t];
-        continue;
-      }
-      if (d.kind == S_CONTRACT)
-        small_contract_any<R>(d, lds, reinterpret_cast<E*>(env.arena), lane, split ? wave : 0, split ? nw : 1);
-      else if (d.kind == S_RESULT)
+      } else if (kind == S_RESULT) {
         small_result<R>(d, lds, env, lane);
+      }
     }
+    cur = nxt;
   }
 }
 

@@ -64,9 +64,8 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallOp* __restrict__ 
                                                     Env env) {
   using E = typename CT<R>::E;
   extern __shared__ __align__(16) char dyn_lds[];
-  __shared__ SmallOp sprog[SMALL_CHUNK];
   const int2 r = load_const(reinterpret_cast<const int2*>(items) + blockIdx.x);
-  run_small<R>(small, r.x, r.y, reinterpret_cast<E*>(dyn_lds), sprog, env);
+  run_small<R>(small, r.x, r.y, reinterpret_cast<E*>(dyn_lds), env);
 }
 
 // Copy of a few hundred bytes between device memory and mapped pinned host
