@@ -70,6 +70,34 @@ __device__ __forceinline__ double2 shfl_xor_c(double2 v, int m) {
   return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
 }
 
+// v of lane + 2^J (lanes whose bit J is 0 only: those read inside their row of
+// 16, where J < 4 is a row shift of the VALU's data-parallel lane moves, no
+// LDS round trip; the others read an unspecified value)
+template <int J>
+__device__ __forceinline__ float lane_down(float v) {
+  if constexpr (J < 4)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 | (1 << J), 0xf, 0xf, true));
+  else
+    return __shfl_xor(v, 1 << J);
+}
+template <int J>
+__device__ __forceinline__ double lane_down(double v) {
+  if constexpr (J < 4) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x100 | (1 << J), 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x100 | (1 << J), 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __shfl_xor(v, 1 << J);
+  }
+}
+template <int J, typename C>
+__device__ __forceinline__ C lane_down_c(C v) {
+  C r;
+  r.x = lane_down<J>(v.x);
+  r.y = lane_down<J>(v.y);
+  return r;
+}
+
 // Parameter slot of a leaf kind inside a cone's result record: gamma_l at
 // 2 + 2l, beta_l at 2 + 2p + 2l (real, imaginary); -1 for |+>, Z and <0|.
 __device__ __forceinline__ int theta_slot(int kind, int p) {
@@ -1453,10 +1481,15 @@ __device__ __forceinline__ void small_contract(const SmallOp& d, typename CT<R>:
       }
     }
     acc0 = cadd(acc0, acc1);
-    // summed lane dimensions no .. nv - 1 (then nv <= 6)
-#pragma unroll
-    for (int j = 0; j < 6; ++j)
-      if (j >= no && j < nv) acc0 = cadd(acc0, shfl_xor_c(acc0, 1 << j));
+    // summed lane dimensions no .. nv - 1 (then nv <= 6), lowest first: each
+    // step adds the value of lane + 2^j, so the lanes with all of these bits
+    // zero (the ones that store) end with the whole sum
+    if (no <= 0 && nv > 0) acc0 = cadd(acc0, lane_down_c<0>(acc0));
+    if (no <= 1 && nv > 1) acc0 = cadd(acc0, lane_down_c<1>(acc0));
+    if (no <= 2 && nv > 2) acc0 = cadd(acc0, lane_down_c<2>(acc0));
+    if (no <= 3 && nv > 3) acc0 = cadd(acc0, lane_down_c<3>(acc0));
+    if (no <= 4 && nv > 4) acc0 = cadd(acc0, lane_down_c<4>(acc0));
+    if (no <= 5 && nv > 5) acc0 = cadd(acc0, lane_down_c<5>(acc0));
     const uint32_t v = (uint32_t)lane | (g << 6);
     if (active && ((v >> no) & ((1u << ls) - 1u)) == 0) {
       const uint32_t o = v & ((1u << no) - 1u);

@@ -111,26 +111,41 @@ __global__ void final_kernel(const double* __restrict__ res, int res_stride, int
                              typename CT<R>::E* zz_out, double* fin, double* host_fin, const int32_t* ctl,
                              int32_t* host_ctl) {
   using E = typename CT<R>::E;
+  // all 1 + 2p sums in one pass over the cones (p <= 16), then one
+  // wavefront reduction each and a sum over the wavefronts
+  constexpr int MAXV = 1 + 2 * 16;
+  constexpr int MAXW = 1024 / 64;
+  __shared__ double part[MAXV][MAXW];
   const int nv = 1 + (with_grad ? 2 * p : 0);
-  for (int c = threadIdx.x; c < n_cones; c += blockDim.x)
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  for (int c = threadIdx.x; c < n_cones; c += blockDim.x) {
+    const double* r = res + (int64_t)c * res_stride;
     if (zz_out) {
       E z;
-      z.x = (R)res[(int64_t)c * res_stride];
-      z.y = (R)res[(int64_t)c * res_stride + 1];
+      z.x = (R)r[0];
+      z.y = (R)r[1];
       zz_out[c] = z;
     }
-  for (int v = 0; v < nv; ++v) {
-    double acc = 0;
-    for (int c = threadIdx.x; c < n_cones; c += blockDim.x) {
-      const double* r = res + (int64_t)c * res_stride;
-      acc += v == 0 ? 0.5 * (1.0 - r[0]) : -0.5 * r[2 + 2 * (v - 1)];
+    acc[0] += 0.5 * (1.0 - r[0]);
+#pragma unroll
+    for (int v = 1; v < MAXV; ++v)
+      if (v < nv) acc[v] -= 0.5 * r[2 + 2 * (v - 1)];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v)
+    if (v < nv) {
+      const double t = wave_sum(acc[v]);
+      if (lane == 0) part[v][wave] = t;
     }
-    const double2 s = block_sum<R>(make_double2(acc, 0));
-    if (threadIdx.x == 0) {
-      fin[v] = s.x;
-      if (host_fin) host_fin[v] = s.x;
-    }
-    __syncthreads();
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double t = 0;
+    for (int w = 0; w < nw; ++w) t += part[threadIdx.x][w];
+    fin[threadIdx.x] = t;
+    if (host_fin) host_fin[threadIdx.x] = t;
   }
   // the queue head and the persistent kernel's error flag, next to the results
   if (host_ctl && threadIdx.x < 2) host_ctl[threadIdx.x] = ctl ? ctl[threadIdx.x] : 0;
