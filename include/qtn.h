@@ -77,7 +77,7 @@ typedef struct {
                            inputs that each lack part of the union (outer products) in one pass with register
                            slots, one output sum per loop step (slower on MI355X where many partial sums remain
                            for atomics); 0: one pass per input adjoint */
-  int32_t lds_threads;  /* workgroup size (64, 128 or 256) of the kernel that runs the light cones whose whole
+  int32_t lds_threads;  /* workgroup size (64, 128, 256 or 512) of the kernel that runs the light cones whose whole
                            program fits the LDS window (lds_kb), one workgroup per cone */
 } qtn_tuning;
 

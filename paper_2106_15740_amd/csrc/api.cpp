@@ -788,8 +788,8 @@ qtn_status qtn_set_tuning(qtn_net* n, const qtn_tuning* t) {
   if (t->merge_lam_bits < 0 || t->merge_lam_bits > 16) return fail(QTN_EINVAL, "merge_lam_bits must be in 0..16");
   if (t->lane_low != 0 && t->lane_low != 1) return fail(QTN_EINVAL, "lane_low must be 0 or 1");
   if (t->fuse_adjoint < 0 || t->fuse_adjoint > 3) return fail(QTN_EINVAL, "fuse_adjoint must be 0, 1, 2 or 3");
-  if (t->lds_threads != 64 && t->lds_threads != 128 && t->lds_threads != 256)
-    return fail(QTN_EINVAL, "lds_threads must be 64, 128 or 256");
+  if (t->lds_threads != 64 && t->lds_threads != 128 && t->lds_threads != 256 && t->lds_threads != 512)
+    return fail(QTN_EINVAL, "lds_threads must be 64, 128, 256 or 512");
   n->P.tune.threads = th;
   n->P.tune.lane_low = t->lane_low;
   n->P.tune.fuse_adjoint = t->fuse_adjoint;
@@ -874,7 +874,7 @@ qtn_status qtn_autotune(qtn_net* n, int32_t with_grad, void* ws, size_t ws_bytes
         }
     } else if (stage == 3) {
       // LDS-resident cones: workgroup size and LDS window cap
-      for (int lt : {128, 256})
+      for (int lt : {128, 256, 512})
         for (int kb : {64, 96}) {
           qtn_tuning t = b0;
           t.lds_threads = lt;

@@ -1731,7 +1731,7 @@ __device__ __forceinline__ void small_result(const SmallOp& d, typename CT<R>::E
 // global output offset when it has one).  The leaf-block copy runs on all
 // threads; every other op on its wavefront (ops between two barriers are
 // independent, so the wavefronts run them side by side).  The workgroup has a
-// power-of-two number of wavefronts (1, 2 or 4).
+// power-of-two number of wavefronts (1, 2, 4 or 8).
 template <typename R>
 __device__ __forceinline__ void run_small(const SmallOp* small, int lo, int hi, typename CT<R>::E* lds,
                                           const Env& env) {

@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) leaf_batch_kernel(const OpDesc* __restric
 // small[items[2k], items[2k + 1]) of one cone with every tensor in its LDS
 // window (items are ordered longest first).
 template <typename R>
-__global__ void __launch_bounds__(256) small_kernel(const SmallOp* __restrict__ small, const int32_t* __restrict__ items,
+__global__ void __launch_bounds__(512) small_kernel(const SmallOp* __restrict__ small, const int32_t* __restrict__ items,
                                                     Env env) {
   using E = typename CT<R>::E;
   extern __shared__ __align__(16) char dyn_lds[];

@@ -259,14 +259,15 @@ def test_forced_split_buckets_and_atomics():
         np.testing.assert_allclose(db, dbp, atol=1e-10)
 
 
-@pytest.mark.parametrize("lds_kb", [0, 16, 64])
-def test_lds_resident_and_global_sweeps_agree(lds_kb):
+@pytest.mark.parametrize("lds_kb,lds_threads", [(0, 256), (16, 256), (64, 256), (64, 64), (64, 512)])
+def test_lds_resident_and_global_sweeps_agree(lds_kb, lds_threads):
     """The batched sweep keeps a cone in an LDS window when its program fits
-    (lds_kb); every window size must give the oracle's values."""
+    (lds_kb), run by 1 to 8 wavefronts; every window size and workgroup must
+    give the oracle's values."""
     w = workload("p3_n244")
     edges = w.edges[:60]
     ref = np.array([tn.zz_edge(w.n, edges, w.gamma, w.beta, j, k) for j, k in edges])
-    net = make(w.n, edges, w.p, "c128", "min_fill", w.gamma, w.beta, lds_kb=lds_kb)
+    net = make(w.n, edges, w.p, "c128", "min_fill", w.gamma, w.beta, lds_kb=lds_kb, lds_threads=lds_threads)
     e, dg, db = net.energy_grad("batched")
     np.testing.assert_allclose(net.edge_results(), ref, atol=1e-10)
     e2, dg2, db2 = net.energy_grad("plain")
