@@ -2202,6 +2202,14 @@ std::string validate_plan(const Plan& P) {
       }
     }
   }
+  // leaf gradients: tables of at most 8 leaves first (their kernel only has
+  // the variants up to 8 leaves), then the others
+  if (P.lgrad_mid < P.lgrad_lo || P.lgrad_mid > P.lgrad_hi) return "leaf-gradient split outside its range";
+  for (int32_t o = P.lgrad_lo; o < P.lgrad_hi; ++o) {
+    const OpDesc& d = P.ops[o];
+    if (d.kind != OP_LEAFGRAD) return "op " + S(o) + "not a leaf gradient";
+    if ((o < P.lgrad_mid) != (d.aux1 <= 8)) return "op " + S(o) + "leaf gradient in the wrong launch";
+  }
   // LDS-resident programs: every operand inside the window; each input's
   // dimensions map one to one onto its element bits
   for (size_t c = 0; c < P.cones.size(); ++c) {
