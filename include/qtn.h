@@ -237,9 +237,17 @@ qtn_status qtn_autotune(qtn_net* net, int32_t with_grad, void* workspace, size_t
 
 /* Device time of the batched sweep's graph replay (leaf upload, queue reset,
  * persistent kernel, final reduction), summed over batched sweeps that wrote
- * host outputs since the last reset, from HIP events recorded on the launch
- * stream around the replay; and the number of such sweeps. */
+ * host outputs since the last reset while sweep timing was on, from HIP events
+ * recorded on the launch stream around the replay; and the number of such
+ * sweeps. */
 qtn_status qtn_kernel_time(qtn_net* net, double* ms_sum, int64_t* count, int32_t reset);
+
+/* Sweep timing for qtn_kernel_time: with on != 0 every batched sweep records
+ * a HIP event on its stream before and after the graph replay.  Off by
+ * default: each event record adds several microseconds to a sweep of a few
+ * hundred, and a synchronous caller waits for them.  Errors: QTN_EINVAL for a
+ * NULL net. */
+qtn_status qtn_set_sweep_timing(qtn_net* net, int32_t on);
 
 /* Tile parameters of wide buckets by bucket signature band: band 0 = buckets
  * of more than seq_max_bits and at most 20 union bits, band 1 = 21..24, band 2

@@ -89,6 +89,7 @@ struct qtn_net {
   GraphCache graph[2];
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
   bool ev_pending = false;
+  bool sweep_timing = false;  // HIP events around each batched graph replay (qtn_set_sweep_timing)
   double kernel_ms_sum = 0;
   int64_t kernel_count = 0;
   std::vector<double> gamma, beta;
@@ -345,10 +346,14 @@ qtn_status run_sweep(qtn_net* n, int mode, bool grad, void* ws, size_t ws_bytes,
     n->last_mode = mode;
     n->last_grad = grad;
     n->last_ws = ws;
-    HIPCHECK(hipEventRecord(n->ev_k0, st));
-    HIPCHECK(hipGraphLaunch(g.exec, st));
-    HIPCHECK(hipEventRecord(n->ev_k1, st));
-    n->ev_pending = true;
+    if (n->sweep_timing) {
+      HIPCHECK(hipEventRecord(n->ev_k0, st));
+      HIPCHECK(hipGraphLaunch(g.exec, st));
+      HIPCHECK(hipEventRecord(n->ev_k1, st));
+      n->ev_pending = true;
+    } else {
+      HIPCHECK(hipGraphLaunch(g.exec, st));
+    }
   } else {
     qtn_status s = enqueue_sweep(n, mode, grad, ws, st, zz_out);
     if (s != QTN_OK) return s;
@@ -1267,6 +1272,12 @@ qtn_status qtn_autotune_bands(qtn_net* n, int32_t with_grad, void* ws, size_t ws
   n->kernel_count = 0;
   if (best_out) qtn_get_band_tuning(n, best_out);
   if (ms_out) return qtn_time_persistent(n, with_grad, ws, ws_bytes, stream, reps, ms_out);
+  return QTN_OK;
+}
+
+qtn_status qtn_set_sweep_timing(qtn_net* n, int32_t on) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  n->sweep_timing = on != 0;
   return QTN_OK;
 }
 

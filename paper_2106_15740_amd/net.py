@@ -303,7 +303,14 @@ class QaoaNet:
                                               self._stream(), int(reps), C.byref(ms)))
         return ms.value
 
+    def set_sweep_timing(self, on: bool) -> None:
+        """Record HIP events around every batched sweep for kernel_time (off
+        by default: each event adds microseconds to a sweep)."""
+        L.check(self._lib.qtn_set_sweep_timing(self.handle, int(bool(on))))
+
     def kernel_time(self, reset: bool = False) -> Tuple[float, int]:
+        """(device ms summed, sweeps) of the batched sweeps timed since the
+        last reset (those run with set_sweep_timing(True))."""
         ms = C.c_double()
         cnt = C.c_int64()
         L.check(self._lib.qtn_kernel_time(self.handle, C.byref(ms), C.byref(cnt), int(bool(reset))))

@@ -459,3 +459,26 @@ def test_single_amplitude_vs_statevector(mode, dtype):
                 arr[l] += h
                 fd = (up - dn) / (2 * h)
                 assert abs(d[l] - fd) <= (1e-8 if dtype == "c128" else 1e-5), (l, d[l], fd)
+
+
+def test_sweep_timing_is_opt_in():
+    """Batched sweeps record their timing events only while sweep timing is
+    on; the results do not depend on it."""
+    w = workload("p3_n244")
+    edges = w.edges[:24]
+    net = make(w.n, edges, w.p, "c64", "min_fill", w.gamma, w.beta)
+    e0, dg0, db0 = net.energy_grad("batched")
+    net.kernel_time(reset=True)
+    for _ in range(3):
+        net.energy_grad("batched")
+    assert net.kernel_time(reset=True) == (0.0, 0)
+    net.set_sweep_timing(True)
+    for _ in range(3):
+        e1, dg1, db1 = net.energy_grad("batched")
+    ms, cnt = net.kernel_time(reset=True)
+    net.set_sweep_timing(False)
+    assert cnt == 3 and ms > 0
+    assert e1 == e0
+    # (leaf gradients meet in atomics, so their order of addition may differ)
+    np.testing.assert_allclose(dg1, dg0, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(db1, db0, rtol=1e-12, atol=1e-12)
