@@ -209,15 +209,19 @@ class QaoaNet:
         return e.value
 
     def energy_grad(self, mode: str = "batched", zz_out=None) -> Tuple[float, np.ndarray, np.ndarray]:
+        import torch
+
+        # (the per-step path of an optimizer loop: plain integers for the
+        # pointer arguments, one output array for both gradients)
         ws = self._workspace(True)
         e = C.c_double()
-        dg = np.zeros(self.p)
-        db = np.zeros(self.p)
-        L.check(self._lib.qtn_energy_grad(self.handle, _MODES[mode], C.c_void_p(ws.data_ptr()), ws.numel(),
-                                          self._stream(),
-                                          C.c_void_p(zz_out.data_ptr() if zz_out is not None else 0), C.byref(e),
-                                          dg.ctypes.data_as(C.c_void_p), db.ctypes.data_as(C.c_void_p)))
-        return e.value, dg, db
+        g = np.zeros(2 * self.p)
+        at = g.ctypes.data
+        L.check(self._lib.qtn_energy_grad(self.handle, _MODES[mode], ws.data_ptr(), ws.numel(),
+                                          torch.cuda.current_stream(self.device).cuda_stream,
+                                          zz_out.data_ptr() if zz_out is not None else None, C.byref(e),
+                                          at, at + 8 * self.p))
+        return e.value, g[:self.p], g[self.p:]
 
     def energy_grad_noalloc(self, mode: str = "batched", zz_out=None) -> Tuple[float, np.ndarray, np.ndarray]:
         """energy_grad through the allocation-free entry point: the workspace is
