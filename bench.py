@@ -603,8 +603,10 @@ def main():
                      "frac_of_copy": (achieved / copy_gbps) if achieved else None,
                      "note": "p=3 sweeps are chains of small dependent steps whose tensors live in LDS and cache: "
                              "bound by dependency latency, not HBM; achieved = algorithmic bytes of the plan's "
-                             "contraction steps (each input read once, each output written once) over the persistent "
-                             "kernel's time; the count with one bucket per index beside it"},
+                             "contraction steps (each input read once, each output written once) over the "
+                             "contraction kernel's time (HIP events around it: kernel_ms); the count with one bucket "
+                             "per index beside it; sweep_ms: the whole graph replay (leaf kernels and final "
+                             "reduction included)"},
         "plain_loop": None if plain_ms is None else {
             "ms_per_step": plain_ms, "edge_light_cones_per_s": len(w.edges) / (plain_ms * 1e-3),
             "speedup_batched_vs_plain": plain_ms / ms_step},
