@@ -194,6 +194,18 @@ qtn_status qtn_energy_grad_noalloc(qtn_net* net, qtn_mode mode, void* stream, vo
 qtn_status qtn_edge_results(qtn_net* net, const void* workspace, void* stream, double* zz, double* dzz);
 
 qtn_status qtn_get_info(const qtn_net* net, qtn_info* out);
+
+/* Census of the ordered plan's contraction steps (Section III.B: a step
+ * multiplies the tensors holding its eliminated indices and sums those
+ * indices) that contain a dense matrix product: two inputs A and B sharing at
+ * least min_bits summed indices (the inner dimension K), each with at least
+ * min_bits kept indices the other lacks (M and N); their shared kept indices
+ * are batch dimensions.  n_steps: all steps; n_gemm: steps with such a pair;
+ * gemm_flops / total_flops: real flops of those steps / of all steps (a step
+ * of k inputs over union U: 6 (k - 1) 2^|U| for the products, plus the sums).
+ * Host only; QTN_ESTATE before ordering. */
+qtn_status qtn_gemm_census(const qtn_net* net, int32_t min_bits, int64_t* n_steps, int64_t* n_gemm,
+                           double* gemm_flops, double* total_flops);
 /* Per-cone statistics (host arrays of n_edges, each nullable): contraction
  * width, qubits in the light cone, tensor indices, leaf tensors, buckets,
  * algorithmic forward / adjoint bytes. */

@@ -22,7 +22,7 @@ EXPORTS = [
     "qtn_workspace_size",
     "qtn_set_params", "qtn_contract", "qtn_energy_grad", "qtn_edge_results", "qtn_get_info",
     "qtn_cone_stats", "qtn_validate_plan", "qtn_get_tuning", "qtn_set_tuning", "qtn_autotune",
-    "qtn_kernel_time", "qtn_set_sweep_timing", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
+    "qtn_kernel_time", "qtn_set_sweep_timing", "qtn_gemm_census", "qtn_time_wide_ops", "qtn_set_memory_budget", "qtn_copy_bandwidth", "qtn_time_persistent",
     "qtn_build_amplitude", "qtn_amplitude", "qtn_cost_model", "qtn_cost_model_order", "qtn_energy_grad_noalloc",
     "qtn_time_wide_sweep", "qtn_get_band_tuning", "qtn_set_band_tuning", "qtn_autotune_bands",
     "qtn_net_free",
@@ -111,6 +111,7 @@ def lib() -> C.CDLL:
         "qtn_autotune": (I32, [P, I32, P, SZ, P, I32, C.POINTER(Tuning)]),
         "qtn_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64), I32]),
         "qtn_set_sweep_timing": (I32, [P, I32]),
+        "qtn_gemm_census": (I32, [P, I32, C.POINTER(I64), C.POINTER(I64), C.POINTER(D), C.POINTER(D)]),
         "qtn_set_memory_budget": (I32, [P, SZ]),
         "qtn_time_wide_ops": (I32, [P, I32, I32, P, SZ, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)]),
         "qtn_copy_bandwidth": (I32, [P, P, SZ, P, I32, C.POINTER(D)]),

@@ -702,6 +702,42 @@ qtn_status qtn_edge_results(qtn_net* n, const void* ws, void* stream, double* zz
   return QTN_OK;
 }
 
+qtn_status qtn_gemm_census(const qtn_net* n, int32_t min_bits, int64_t* n_steps, int64_t* n_gemm, double* gemm_flops,
+                           double* total_flops) {
+  if (!n) return fail(QTN_EINVAL, "net is NULL");
+  if (!n->P.ordered) return fail(QTN_ESTATE, "qtn_order has not been called");
+  if (min_bits < 1) return fail(QTN_EINVAL, "min_bits must be >= 1");
+  int64_t steps = 0, gemm = 0;
+  double fg = 0, ft = 0;
+  for (const Cone& C : n->P.cones)
+    for (const Bucket& B : C.buckets) {
+      std::vector<uint32_t> in(B.in_mask.begin(), B.in_mask.end());
+      if (B.lam_mask) in.push_back(B.lam_mask);
+      const uint32_t summed = B.elim_mask();
+      const double f = 6.0 * std::max<int>((int)in.size() - 1, 0) * std::ldexp(1.0, B.nbits()) +
+                       2.0 * std::ldexp(1.0, B.nbits());
+      bool dense = false;
+      for (size_t a = 0; a < in.size() && !dense; ++a)
+        for (size_t b = a + 1; b < in.size() && !dense; ++b) {
+          const int k = __builtin_popcount(in[a] & in[b] & summed);
+          const int m = __builtin_popcount(in[a] & ~in[b] & ~summed);
+          const int nn = __builtin_popcount(in[b] & ~in[a] & ~summed);
+          dense = k >= min_bits && m >= min_bits && nn >= min_bits;
+        }
+      ++steps;
+      ft += f;
+      if (dense) {
+        ++gemm;
+        fg += f;
+      }
+    }
+  if (n_steps) *n_steps = steps;
+  if (n_gemm) *n_gemm = gemm;
+  if (gemm_flops) *gemm_flops = fg;
+  if (total_flops) *total_flops = ft;
+  return QTN_OK;
+}
+
 qtn_status qtn_get_info(const qtn_net* n, qtn_info* out) {
   if (!n || !out) return fail(QTN_EINVAL, "net or out is NULL");
   std::memset(out, 0, sizeof(*out));

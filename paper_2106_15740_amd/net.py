@@ -307,6 +307,16 @@ class QaoaNet:
                                               self._stream(), int(reps), C.byref(ms)))
         return ms.value
 
+    def gemm_census(self, min_bits: int = 4) -> dict:
+        """Contraction steps that contain a dense matrix product (two inputs
+        sharing >= min_bits summed indices, each with >= min_bits kept indices
+        the other lacks) and their share of the plan's flops."""
+        ns, ng = C.c_int64(), C.c_int64()
+        fg, ft = C.c_double(), C.c_double()
+        L.check(self._lib.qtn_gemm_census(self.handle, int(min_bits), C.byref(ns), C.byref(ng), C.byref(fg),
+                                          C.byref(ft)))
+        return {"steps": ns.value, "gemm_steps": ng.value, "gemm_flops": fg.value, "total_flops": ft.value}
+
     def set_sweep_timing(self, on: bool) -> None:
         """Record HIP events around every batched sweep for kernel_time (off
         by default: each event adds microseconds to a sweep)."""

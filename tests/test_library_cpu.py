@@ -250,6 +250,33 @@ def test_merged_steps_cover_every_bucket(merge_bits):
     assert info["max_width"] == base["max_width"]
 
 
+def test_gemm_census_counts_steps_and_flops():
+    """The dense-product census walks every contraction step once: its step
+    count is the plan's, stricter thresholds find fewer such steps, their
+    flops are a part of the total, and the total does not depend on the
+    threshold."""
+    from paper_2106_15740_amd import _lib as L
+
+    w = workload("p3_n244")
+    net = QaoaNet(w.n, w.edges, w.p, dtype="c64", order="min_fill", device=None)
+    info = net.info()
+    c = [net.gemm_census(b) for b in (1, 2, 3, 4, 30)]
+    assert all(x["steps"] == info["n_steps"] for x in c)
+    assert [x["gemm_steps"] for x in c] == sorted((x["gemm_steps"] for x in c), reverse=True)
+    assert c[-1]["gemm_steps"] == 0 and c[-1]["gemm_flops"] == 0
+    assert c[0]["gemm_steps"] > 0
+    for x in c:
+        assert 0 <= x["gemm_flops"] <= x["total_flops"] == c[0]["total_flops"]
+    with pytest.raises(L.QtnError):
+        net.gemm_census(0)
+    # without merging every step is one bucket, and each costs at least
+    # 2 2^|U| >= 4 flops
+    net.set_tuning(merge_bits=0)
+    c1, i1 = net.gemm_census(1), net.info()
+    assert c1["steps"] == i1["n_buckets"] == i1["n_steps"]
+    assert c1["total_flops"] >= 4 * c1["steps"]
+
+
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_amplitude_network_plan(p):
     """The single-amplitude network has p+1 indices per qubit (one bucket
