@@ -294,6 +294,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps, retune: bool = False):
     tune_s = time.perf_counter() - t1
     log(f"p5_n1000: tiles from {entry['source']} in {tune_s:.1f} s")
     info = net.info()
+    census = net.gemm_census(4)  # steps holding a dense product with K, M, N >= 16
     dt, e, k_ms, _ = time_sweeps(net, steps, 1)
     pk_ms = net.time_persistent(with_grad=True, reps=2)
     alg = info["fwd_bytes"] + info["bwd_bytes"]
@@ -377,6 +378,7 @@ def wide_leg(repeats: int, steps: int, copy_gbps, retune: bool = False):
         "workspace_GB": info["ws_grad"] / 1e9,
         "keep_all_GB": info["arena_keep_all"] / 1e9,
         "memory_budgets": budgets,
+        "gemm_census_k16": census,
         "width_ge_20_standalone_bands": bands,
         "energy": e,
         "plan_s": plan_s,
